@@ -1,0 +1,458 @@
+/*
+ * Oracle for the block-step Barnes-Hut tree gravity of Miki & Umemura,
+ * "GOTHIC: Gravitational oct-tree code accelerated by hierarchical time step
+ * controlling" (arXiv:1610.07279).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, float64 CPU
+ * implementation used by the tests, the smoke check and the CPU baseline of
+ * the benchmark to check the HIP library.  The product path never calls it,
+ * and it shares no code, header or table with the HIP sources.
+ *
+ * Every function restates one step of the paper in the paper's order:
+ *   keys            Section 2.1 + Appendix A (Morton: the 63-bit interleave;
+ *                   Peano-Hilbert: the level-by-level rotation/inversion)
+ *   sort            Section 2.1 (stable radix sort of (key, index) pairs)
+ *   tree            Section 2.1 (breadth-first octree from the sorted keys)
+ *   moments         Section 2.1 (pseudo j-particles: mass, centre of mass,
+ *                   enclosing radius) + a quadrupole extension (second moments)
+ *   groups          Section 2.3 (pseudo i-particles, geometric-centre ball of
+ *                   Appendix B)
+ *   walk            Sections 2.2-2.3 (opening-angle MAC, Eq. of Barnes & Hut,
+ *                   with the lambda-distance of the pseudo i-particle)
+ *   direct          Section 1, the softened direct sum
+ *   time levels and RK2 / leap-frog integration, Section 2.7
+ * Readings where the paper is silent are stated at each function.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (see build.py).
+ * FP contraction stays off so every double operation is one IEEE rounding.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NLEV 21 /* bits per axis; 3*21 = 63-bit keys (Appendix A) */
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ---------------------------------------------------------------------- */
+/* Direct sum (Section 1): a_i = sum_{j != i} m_j (r_j - r_i)/(|r_j-r_i|^2+eps^2)^{3/2}
+ * and phi_i = -sum_{j != i} m_j / (|r_j-r_i|^2+eps^2)^{1/2}, G = 1.
+ * The potential sign is a reading (the paper only says phi is computed).
+ * idx[k] selects the i-particles; out[k*4 + {0,1,2,3}] = ax, ay, az, phi.   */
+void orc_direct(int64_t n, const float *xyzm, double eps, int64_t ni,
+                const int64_t *idx, double *out) {
+  const double e2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < ni; ++k) {
+    const int64_t i = idx[k];
+    const double xi = xyzm[4 * i], yi = xyzm[4 * i + 1], zi = xyzm[4 * i + 2];
+    double ax = 0, ay = 0, az = 0, ph = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double dx = (double)xyzm[4 * j] - xi;
+      const double dy = (double)xyzm[4 * j + 1] - yi;
+      const double dz = (double)xyzm[4 * j + 2] - zi;
+      const double m = xyzm[4 * j + 3];
+      const double r2 = dx * dx + dy * dy + dz * dz + e2;
+      const double r = sqrt(r2);
+      const double inv3 = 1.0 / (r2 * r);
+      ax += m * dx * inv3;
+      ay += m * dy * inv3;
+      az += m * dz * inv3;
+      ph -= m / r;
+    }
+    out[4 * k] = ax;
+    out[4 * k + 1] = ay;
+    out[4 * k + 2] = az;
+    out[4 * k + 3] = ph;
+  }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Keys (Appendix A).  Morton: bit b of (x, y, z) goes to key bit 3b+2, 3b+1, 3b. */
+uint64_t orc_morton(uint64_t x, uint64_t y, uint64_t z) {
+  uint64_t key = 0;
+  for (int b = 0; b < NLEV; ++b) {
+    key |= ((x >> b) & 1u) << (3 * b + 2);
+    key |= ((y >> b) & 1u) << (3 * b + 1);
+    key |= ((z >> b) & 1u) << (3 * b);
+  }
+  return key;
+}
+
+/* Peano-Hilbert curve of Appendix A.  Level by level, from the coarsest: the
+ * octant bits (a0, a1, a2) of the point in the current frame give the key
+ * digit as the inverse Gray code of a0 a1 a2; then the frame is inverted
+ * along some axes and its axes are permuted, depending on the octant.
+ *
+ * The frame is tracked as perm[] / flip[]: frame axis a reads original axis
+ * perm[a], complemented when flip[a] is set.  Per octant o = 4 a0 + 2 a1 + a2:
+ *   INV[o]  bit mask (4: axis 0, 2: axis 1, 1: axis 2) of axes inverted,
+ *   ROT[o]  0 = keep, 1 = cycle (new 0,1,2 <- old 1,2,0), 2 = exchange 0 and 2.
+ * These two tables were worked out by hand from the encoder printed in
+ * Appendix A (inversion first, then the permutation).                        */
+static const int PH_INV[8] = {0, 0, 3, 0, 5, 6, 3, 6};
+static const int PH_ROT[8] = {2, 1, 0, 1, 2, 1, 0, 1};
+
+static int inv_gray3(int g) { /* g = a0 a1 a2 (a0 most significant) */
+  int d = g;
+  d ^= d >> 1;
+  d ^= d >> 2;
+  return d & 7;
+}
+
+static void ph_update_frame(int o, int perm[3], int flip[3]) {
+  int inv = PH_INV[o];
+  int f[3] = {flip[0] ^ ((inv >> 2) & 1), flip[1] ^ ((inv >> 1) & 1), flip[2] ^ (inv & 1)};
+  int p[3] = {perm[0], perm[1], perm[2]};
+  if (PH_ROT[o] == 1) {
+    perm[0] = p[1]; perm[1] = p[2]; perm[2] = p[0];
+    flip[0] = f[1]; flip[1] = f[2]; flip[2] = f[0];
+  } else if (PH_ROT[o] == 2) {
+    perm[0] = p[2]; perm[1] = p[1]; perm[2] = p[0];
+    flip[0] = f[2]; flip[1] = f[1]; flip[2] = f[0];
+  } else {
+    flip[0] = f[0]; flip[1] = f[1]; flip[2] = f[2];
+  }
+}
+
+uint64_t orc_ph_encode(int nlev, uint64_t x, uint64_t y, uint64_t z) {
+  const uint64_t c[3] = {x, y, z};
+  int perm[3] = {0, 1, 2}, flip[3] = {0, 0, 0};
+  uint64_t key = 0;
+  for (int lev = nlev - 1; lev >= 0; --lev) {
+    int a[3];
+    for (int ax = 0; ax < 3; ++ax) a[ax] = (int)((c[perm[ax]] >> lev) & 1u) ^ flip[ax];
+    const int o = (a[0] << 2) | (a[1] << 1) | a[2];
+    key |= (uint64_t)inv_gray3(o) << (3 * lev);
+    ph_update_frame(o, perm, flip);
+  }
+  return key;
+}
+
+void orc_ph_decode(int nlev, uint64_t key, uint64_t *x, uint64_t *y, uint64_t *z) {
+  uint64_t c[3] = {0, 0, 0};
+  int perm[3] = {0, 1, 2}, flip[3] = {0, 0, 0};
+  for (int lev = nlev - 1; lev >= 0; --lev) {
+    const int d = (int)((key >> (3 * lev)) & 7u);
+    const int o = d ^ (d >> 1); /* Gray code of the digit = octant in frame */
+    const int a[3] = {(o >> 2) & 1, (o >> 1) & 1, o & 1};
+    for (int ax = 0; ax < 3; ++ax) c[perm[ax]] |= (uint64_t)(a[ax] ^ flip[ax]) << lev;
+    ph_update_frame(o, perm, flip);
+  }
+  *x = c[0]; *y = c[1]; *z = c[2];
+}
+
+/* Bounding cube and quantisation (a reading; the paper does not say how the
+ * positions are mapped to integers).  The cube origin is the bounding-box
+ * minimum, its side L the smallest power of two >= the largest extent (1 if
+ * the extent is 0), and q = min(floor((x - x_min) * 2^21 / L), 2^21 - 1) per
+ * axis, all in float64.  cube[] = x_min, y_min, z_min, L.                     */
+void orc_cube(int64_t n, const float *xyzm, double cube[4]) {
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      const double v = xyzm[4 * i + a];
+      if (i == 0 || v < lo[a]) lo[a] = v;
+      if (i == 0 || v > hi[a]) hi[a] = v;
+    }
+  double ext = 0;
+  for (int a = 0; a < 3; ++a)
+    if (hi[a] - lo[a] > ext) ext = hi[a] - lo[a];
+  double L = 1.0;
+  if (ext > 0) {
+    int e;
+    const double f = frexp(ext, &e); /* ext = f 2^e, f in [0.5, 1) */
+    L = (f == 0.5) ? ext : ldexp(1.0, e);
+  }
+  cube[0] = lo[0]; cube[1] = lo[1]; cube[2] = lo[2]; cube[3] = L;
+}
+
+void orc_keys(int64_t n, const float *xyzm, int key_kind, const double cube[4],
+              uint64_t *keys) {
+  const double scale = ldexp(1.0, NLEV) / cube[3];
+  const uint64_t qmax = ((uint64_t)1 << NLEV) - 1;
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t q[3];
+    for (int a = 0; a < 3; ++a) {
+      const double t = floor(((double)xyzm[4 * i + a] - cube[a]) * scale);
+      q[a] = (uint64_t)t > qmax ? qmax : (uint64_t)t;
+    }
+    keys[i] = key_kind == 1 ? orc_ph_encode(NLEV, q[0], q[1], q[2])
+                            : orc_morton(q[0], q[1], q[2]);
+  }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Sort (Section 2.1): a stable sort of the particles by key, so equal keys
+ * keep ascending original index; i.e. lexicographic (key, index) order.     */
+typedef struct { uint64_t key; uint32_t idx; } kv_t;
+static int kv_cmp(const void *a, const void *b) {
+  const kv_t *p = (const kv_t *)a, *q = (const kv_t *)b;
+  if (p->key != q->key) return p->key < q->key ? -1 : 1;
+  return p->idx < q->idx ? -1 : (p->idx > q->idx);
+}
+
+void orc_sort(int64_t n, const uint64_t *keys, uint64_t *keys_sorted, uint32_t *perm) {
+  kv_t *t = (kv_t *)malloc(sizeof(kv_t) * (size_t)(n > 0 ? n : 1));
+  for (int64_t i = 0; i < n; ++i) { t[i].key = keys[i]; t[i].idx = (uint32_t)i; }
+  qsort(t, (size_t)n, sizeof(kv_t), kv_cmp);
+  for (int64_t i = 0; i < n; ++i) { keys_sorted[i] = t[i].key; perm[i] = t[i].idx; }
+  free(t);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Tree (Section 2.1): a cell at level l is a run of sorted keys sharing their
+ * top 3l bits; splitting it into eight sub-cubes is cutting its key run at the
+ * next 3-bit digit.  Built breadth first: the root (all particles, level 0) is
+ * node 0; a node with more than n_leaf particles below level 21 gets one child
+ * per non-empty digit, in increasing digit order, appended in the order the
+ * parents are visited.  Leaves have n_child = 0 and child_first = 0.
+ * Returns the node count, or -1 if max_nodes is too small.                  */
+int64_t orc_build(int64_t n, const uint64_t *ks, int n_leaf, int64_t max_nodes,
+                  uint32_t *first, uint32_t *count, uint32_t *child_first,
+                  uint8_t *n_child, uint8_t *level) {
+  if (n <= 0) return 0;
+  if (max_nodes < 1) return -1;
+  int64_t nn = 1;
+  first[0] = 0; count[0] = (uint32_t)n; level[0] = 0;
+  for (int64_t k = 0; k < nn; ++k) {
+    child_first[k] = 0; n_child[k] = 0;
+    const int l = level[k];
+    if (count[k] <= (uint32_t)n_leaf || l >= NLEV) continue;
+    const int shift = 3 * (NLEV - 1 - l); /* digit of level l+1 */
+    child_first[k] = (uint32_t)nn;
+    uint32_t s = first[k];
+    const uint32_t e = first[k] + count[k];
+    while (s < e) {
+      const uint64_t d = (ks[s] >> shift) & 7u;
+      uint32_t t = s;
+      while (t < e && ((ks[t] >> shift) & 7u) == d) ++t;
+      if (nn >= max_nodes) return -1;
+      first[nn] = s; count[nn] = t - s; level[nn] = (uint8_t)(l + 1);
+      ++nn; ++n_child[k];
+      s = t;
+    }
+  }
+  return nn;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Pseudo j-particles (Section 2.1), straight from the member particles of
+ * each node: mass M = sum m, centre of mass r_J = sum m r / M, radius
+ * b_J = max |r - r_J| over the members (the smallest sphere about r_J that
+ * holds them), and the second moments S_ab = sum m (r-r_J)_a (r-r_J)_b used
+ * by the quadrupole extension.  A node of zero mass gets r_J = its first
+ * member, b_J = 0, S = 0.  pos_sorted: float64 [n][4] in key order.
+ * com[4k..] = x, y, z, M; S[6k..] = xx, yy, zz, xy, xz, yz.                   */
+void orc_moments(int64_t nn, const uint32_t *first, const uint32_t *count,
+                 const double *ps, double *com, double *b, double *S) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t k = 0; k < nn; ++k) {
+    const uint32_t s = first[k], e = first[k] + count[k];
+    double M = 0, cx = 0, cy = 0, cz = 0;
+    for (uint32_t j = s; j < e; ++j) {
+      const double m = ps[4 * j + 3];
+      M += m;
+      cx += m * ps[4 * j];
+      cy += m * ps[4 * j + 1];
+      cz += m * ps[4 * j + 2];
+    }
+    double *Sk = S + 6 * k;
+    for (int a = 0; a < 6; ++a) Sk[a] = 0;
+    if (M > 0) {
+      cx /= M; cy /= M; cz /= M;
+    } else {
+      cx = ps[4 * s]; cy = ps[4 * s + 1]; cz = ps[4 * s + 2];
+    }
+    double bmax = 0;
+    for (uint32_t j = s; j < e; ++j) {
+      const double dx = ps[4 * j] - cx, dy = ps[4 * j + 1] - cy, dz = ps[4 * j + 2] - cz;
+      const double m = ps[4 * j + 3];
+      if (M > 0) {
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        if (d > bmax) bmax = d;
+      }
+      Sk[0] += m * dx * dx; Sk[1] += m * dy * dy; Sk[2] += m * dz * dz;
+      Sk[3] += m * dx * dy; Sk[4] += m * dx * dz; Sk[5] += m * dy * dz;
+    }
+    com[4 * k] = cx; com[4 * k + 1] = cy; com[4 * k + 2] = cz; com[4 * k + 3] = M;
+    b[k] = bmax;
+  }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Groups (Section 2.3 with the reading of fixed chunks): the active particles
+ * in key order, cut into runs of at most G consecutive ones.  Each group gets
+ * a pseudo i-particle: the geometric centre of its bounding box r_I and the
+ * radius b_I = max |r_i - r_I| (GEO ball, Appendix B).
+ * act_sorted[k] = active flag of sorted particle k.  Outputs: alist (sorted
+ * indices of active particles), gfirst/gcount into alist, ball[4g..] = r_I, b_I.
+ * Returns the number of groups.                                              */
+int64_t orc_groups(int64_t n, const uint8_t *act_sorted, const double *ps, int G,
+                   uint32_t *alist, uint32_t *gfirst, uint32_t *gcount, double *ball) {
+  int64_t na = 0;
+  for (int64_t k = 0; k < n; ++k)
+    if (act_sorted[k]) alist[na++] = (uint32_t)k;
+  const int64_t ng = (na + G - 1) / G;
+  for (int64_t g = 0; g < ng; ++g) {
+    const int64_t s = g * G, e = (s + G < na) ? s + G : na;
+    gfirst[g] = (uint32_t)s; gcount[g] = (uint32_t)(e - s);
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = ps[4 * (int64_t)alist[s] + a];
+    for (int64_t q = s; q < e; ++q)
+      for (int a = 0; a < 3; ++a) {
+        const double v = ps[4 * (int64_t)alist[q] + a];
+        if (v < lo[a]) lo[a] = v;
+        if (v > hi[a]) hi[a] = v;
+      }
+    double c[3];
+    for (int a = 0; a < 3; ++a) c[a] = 0.5 * (lo[a] + hi[a]);
+    double bI = 0;
+    for (int64_t q = s; q < e; ++q) {
+      const double *p = ps + 4 * (int64_t)alist[q];
+      const double d = sqrt((p[0] - c[0]) * (p[0] - c[0]) + (p[1] - c[1]) * (p[1] - c[1]) +
+                            (p[2] - c[2]) * (p[2] - c[2]));
+      if (d > bI) bI = d;
+    }
+    ball[4 * g] = c[0]; ball[4 * g + 1] = c[1]; ball[4 * g + 2] = c[2]; ball[4 * g + 3] = bI;
+  }
+  return ng;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Pair terms, y = r_i - r_J, R^2 = |y|^2 + eps^2.
+ * Monopole (point mass):  a += -M y / R^3,  phi += -M / R.
+ * Quadrupole (extension; the paper uses monopoles only): the second-order
+ * Taylor term of the softened kernel about the centre of mass, with the raw
+ * second moments S (the dipole vanishes about the centre of mass):
+ *   phi += -(3/2) y.S.y / R^5 + (1/2) tr S / R^3
+ *   a   +=  3 S.y / R^5 - (15/2) (y.S.y) y / R^7 + (3/2) tr S y / R^5          */
+static void pair_mono(const double yi[3], const double rj[3], double M, double e2,
+                      double acc[4]) {
+  const double y0 = yi[0] - rj[0], y1 = yi[1] - rj[1], y2 = yi[2] - rj[2];
+  const double R2 = y0 * y0 + y1 * y1 + y2 * y2 + e2;
+  const double R = sqrt(R2);
+  const double inv3 = 1.0 / (R2 * R);
+  acc[0] -= M * y0 * inv3;
+  acc[1] -= M * y1 * inv3;
+  acc[2] -= M * y2 * inv3;
+  acc[3] -= M / R;
+}
+
+static void pair_quad(const double yi[3], const double rj[3], const double S[6], double e2,
+                      double acc[4]) {
+  const double y[3] = {yi[0] - rj[0], yi[1] - rj[1], yi[2] - rj[2]};
+  const double R2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + e2;
+  const double R = sqrt(R2);
+  const double R3 = R2 * R, R5 = R3 * R2, R7 = R5 * R2;
+  const double Sy[3] = {S[0] * y[0] + S[3] * y[1] + S[4] * y[2],
+                        S[3] * y[0] + S[1] * y[1] + S[5] * y[2],
+                        S[4] * y[0] + S[5] * y[1] + S[2] * y[2]};
+  const double q = y[0] * Sy[0] + y[1] * Sy[1] + y[2] * Sy[2];
+  const double tr = S[0] + S[1] + S[2];
+  for (int a = 0; a < 3; ++a)
+    acc[a] += 3.0 * Sy[a] / R5 - 7.5 * q * y[a] / R7 + 1.5 * tr * y[a] / R5;
+  acc[3] += -1.5 * q / R5 + 0.5 * tr / R3;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Tree walk (Sections 2.2-2.3).  For each group, breadth first from the root:
+ * for a candidate pseudo j-particle J, r_JI = |r_J - r_I| and the distance to
+ * the nearest possible i-particle is d = lambda r_JI with lambda = 1 - b_I/r_JI
+ * when b_I < r_JI and 0 otherwise.  The opening-angle MAC b_J / d <= theta is
+ * taken as b_J <= theta d (so d = 0 accepts only b_J = 0).  Accepted nodes
+ * interact as pseudo particles; a rejected internal node queues its children;
+ * a rejected leaf interacts through its member particles.  Every i of the
+ * group then sums the same list.  The self pair of a particle gives zero force
+ * and the potential term -m_i/eps, which is removed.  (For theta < 1 a node
+ * holding an i of the group is never accepted unless b_J = 0, so the self pair
+ * is always an explicit particle entry.)
+ *
+ * multipole: 1 monopole, 2 monopole + quadrupole for node entries.
+ * Per group: cnt[3g+0] accepted node entries, cnt[3g+1] particle entries,
+ * cnt[3g+2] near ties |b_J - theta d| <= tie_rel max(b_J, theta d) + tie_abs
+ * among nodes with b_J > 0 (b_J = 0 is accepted at any distance);
+ * mass[g] = summed mass of the list (mass closure).
+ * gsel: optional subset of groups to evaluate (ngsel entries), NULL = all.
+ * out: [n][4] in sorted order; rows of evaluated active particles written.   */
+void orc_walk(int64_t nn, const uint32_t *first, const uint32_t *count,
+              const uint32_t *child_first, const uint8_t *n_child,
+              const double *com, const double *b, const double *S,
+              const double *ps, const uint32_t *alist, int64_t ng,
+              const uint32_t *gfirst, const uint32_t *gcount, const double *ball,
+              double eps, double theta, int multipole, double tie_rel, double tie_abs,
+              const int64_t *gsel, int64_t ngsel, double *out, int64_t *cnt,
+              double *mass) {
+  const double e2 = eps * eps;
+  const int64_t nsel = gsel ? ngsel : ng;
+#pragma omp parallel
+  {
+    uint32_t *q = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nn > 0 ? nn : 1));
+    uint32_t *lst = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nn > 0 ? nn : 1));
+    size_t cap_p = 1024;
+    uint32_t *plst = (uint32_t *)malloc(sizeof(uint32_t) * cap_p);
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t t = 0; t < nsel; ++t) {
+      const int64_t g = gsel ? gsel[t] : t;
+      const double rI[3] = {ball[4 * g], ball[4 * g + 1], ball[4 * g + 2]};
+      const double bI = ball[4 * g + 3];
+      int64_t nl = 0, np = 0, ties = 0, qh = 0, qt = 0;
+      if (nn > 0) q[qt++] = 0;
+      while (qh < qt) {
+        const uint32_t J = q[qh++];
+        const double dx = com[4 * J] - rI[0], dy = com[4 * J + 1] - rI[1],
+                     dz = com[4 * J + 2] - rI[2];
+        const double rJI = sqrt(dx * dx + dy * dy + dz * dz);
+        const double lam = (bI < rJI) ? 1.0 - bI / rJI : 0.0;
+        const double d = lam * rJI;
+        const double td = theta * d;
+        const double big = b[J] > td ? b[J] : td;
+        if (b[J] > 0 && fabs(b[J] - td) <= tie_rel * big + tie_abs) ++ties;
+        if (b[J] <= td) {
+          lst[nl++] = J;
+        } else if (n_child[J] == 0) {
+          if ((size_t)(np + count[J]) > cap_p) {
+            while ((size_t)(np + count[J]) > cap_p) cap_p *= 2;
+            plst = (uint32_t *)realloc(plst, sizeof(uint32_t) * cap_p);
+          }
+          for (uint32_t j = first[J]; j < first[J] + count[J]; ++j) plst[np++] = j;
+        } else {
+          for (uint32_t c = 0; c < n_child[J]; ++c) q[qt++] = child_first[J] + c;
+        }
+      }
+      double msum = 0;
+      for (int64_t k = 0; k < nl; ++k) msum += com[4 * lst[k] + 3];
+      for (int64_t k = 0; k < np; ++k) msum += ps[4 * plst[k] + 3];
+      cnt[3 * g] = nl; cnt[3 * g + 1] = np; cnt[3 * g + 2] = ties;
+      mass[g] = msum;
+      for (uint32_t a = gfirst[g]; a < gfirst[g] + gcount[g]; ++a) {
+        const uint32_t i = alist[a];
+        const double yi[3] = {ps[4 * i], ps[4 * i + 1], ps[4 * i + 2]};
+        double acc[4] = {0, 0, 0, 0};
+        for (int64_t k = 0; k < nl; ++k) {
+          const uint32_t J = lst[k];
+          pair_mono(yi, com + 4 * J, com[4 * J + 3], e2, acc);
+          if (multipole == 2) pair_quad(yi, com + 4 * J, S + 6 * J, e2, acc);
+        }
+        for (int64_t k = 0; k < np; ++k) {
+          const uint32_t j = plst[k];
+          pair_mono(yi, ps + 4 * j, ps[4 * j + 3], e2, acc);
+        }
+        acc[3] += ps[4 * i + 3] / eps; /* remove the self pair's -m_i/eps */
+        for (int c = 0; c < 4; ++c) out[4 * (int64_t)i + c] = acc[c];
+      }
+    }
+    free(q); free(lst); free(plst);
+  }
+}

@@ -1,0 +1,162 @@
+"""Pins for the oracle's octree, pseudo j-particles and groups (CPU only).
+
+Tree: a hand-placed example whose shape is known, brute-force enumeration of
+the cells from key prefixes, and the structural invariants.  Moments: the
+parallel-axis identity (children's moments combine into the parent's),
+containment and tightness of b_J, root mass and centre of mass.  Groups:
+chunking and the geometric-centre ball.
+"""
+import numpy as np
+import pytest
+
+import ics
+import oracle
+
+
+def _tree_for(xyzm, n_leaf, key_kind=0):
+    k, _ = oracle.keys(xyzm, key_kind)
+    ks, perm = oracle.sort(k)
+    return ks, perm, oracle.build(ks, n_leaf)
+
+
+def test_hand_placed_tree():
+    # 8 particles near the corners of the unit cube plus 2 more in the (+,+,+)
+    # octant and two pinning the cube to [0,1]; n_leaf = 2: the root splits
+    # into 8 children and only the (+,+,+) child (4 particles) splits again,
+    # into octant 110 (1 particle) and 111 (3 particles, split once more).
+    c = []
+    for x in (0.1, 0.9):
+        for y in (0.1, 0.9):
+            for z in (0.1, 0.9):
+                c.append((x, y, z))
+    c += [(0.95, 0.95, 0.95), (0.99, 0.99, 0.6)]
+    pts = np.array(c)
+    pts = np.vstack([pts, [[0.0, 0.0, 0.0], [1.0, 1.0, 1.0]]])  # pin the cube to [0,1]
+    xyzm = np.zeros((pts.shape[0], 4), np.float32)
+    xyzm[:, :3] = pts
+    xyzm[:, 3] = 1.0
+    ks, perm, t = _tree_for(xyzm, 2)
+    assert t["n_child"][0] == 8
+    assert list(t["level"][1:9]) == [1] * 8
+    assert list(t["count"][1:9]) == [2, 1, 1, 1, 1, 1, 1, 4]
+    split = [k for k in range(1, 9) if t["n_child"][k] > 0]
+    assert split == [8]  # (-,-,-) holds 2 = n_leaf (a leaf); (+,+,+) holds 4
+    assert t["child_first"][8] == 9
+    assert t["n_child"][8] == 2 and list(t["count"][9:11]) == [1, 3]
+    assert t["n_child"][9] == 0 and t["n_child"][10] > 0 and t["level"][10] == 2
+
+
+def _brute_cells(ks, n_leaf):
+    """All (level, prefix) cells whose parent cell holds more than n_leaf keys."""
+    n = ks.size
+    cells = {(0, 0): (0, n)}
+    out = [(0, 0, 0, n)]
+    for l in range(1, 22):
+        pref = ks >> np.uint64(3 * (21 - l))
+        ppref = ks >> np.uint64(3 * (21 - l + 1))
+        starts = np.flatnonzero(np.r_[True, pref[1:] != pref[:-1]])
+        ends = np.r_[starts[1:], n]
+        for s, e in zip(starts, ends):
+            par = (l - 1, int(ppref[s]))
+            ps, pe = cells[par] if par in cells else (None, None)
+            if ps is not None and pe - ps > n_leaf:
+                cells[(l, int(pref[s]))] = (s, e)
+                out.append((l, int(pref[s]), s, e - s))
+    return out
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("n,n_leaf", [(3000, 16), (2000, 4), (777, 1)])
+def test_tree_matches_brute_force_cells(kind, n, n_leaf):
+    xyzm = ics.nfw(n, seed=n + kind)
+    ks, perm, t = _tree_for(xyzm, n_leaf, kind)
+    brute = _brute_cells(ks, n_leaf)
+    # brute list is in (level, key) order = BFS order of the oracle's tree
+    assert len(brute) == t["first"].size
+    for k, (l, _, s, c) in enumerate(brute):
+        assert t["level"][k] == l and t["first"][k] == s and t["count"][k] == c
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_tree_invariants(kind):
+    xyzm = ics.plummer(5000, seed=9)
+    xyzm[100:140, :3] = xyzm[99, :3]  # coincident keys force level-21 leaves
+    ks, perm, t = _tree_for(xyzm, 8, kind)
+    nn = t["first"].size
+    covered = np.zeros(ks.size, np.int32)
+    for k in range(nn):
+        f, c, nc, l = int(t["first"][k]), int(t["count"][k]), int(t["n_child"][k]), int(t["level"][k])
+        if nc == 0:
+            assert c <= 8 or l == 21
+            covered[f:f + c] += 1
+            assert t["child_first"][k] == 0
+        else:
+            ch = range(int(t["child_first"][k]), int(t["child_first"][k]) + nc)
+            assert sum(int(t["count"][j]) for j in ch) == c
+            s = f
+            for j in ch:
+                assert t["first"][j] == s and t["level"][j] == l + 1
+                s += int(t["count"][j])
+        if l > 0:
+            pre = ks[f:f + c] >> np.uint64(3 * (21 - l))
+            assert (pre == pre[0]).all()
+    assert (covered == 1).all()
+    assert (np.diff(t["level"].astype(int)) >= 0).all()
+    assert (t["level"] == 21).any()
+
+
+def test_empty_and_single():
+    t = oracle.build(np.zeros(0, np.uint64), 16)
+    assert t["first"].size == 0
+    t = oracle.build(np.zeros(1, np.uint64), 16)
+    assert t["first"].size == 1 and t["count"][0] == 1 and t["n_child"][0] == 0
+
+
+def test_moments_parallel_axis_and_ball():
+    xyzm = ics.nfw(4000, seed=2)
+    xyzm[:, 3] *= np.random.default_rng(1).uniform(0.5, 1.5, 4000).astype(np.float32)
+    ks, perm, t = _tree_for(xyzm, 8)
+    ps = xyzm[perm].astype(np.float64)
+    com, b, S = oracle.moments(t, ps)
+    M = ps[:, 3].sum()
+    assert abs(com[0, 3] - M) <= 1e-13 * M
+    gc = (ps[:, :3] * ps[:, 3:4]).sum(0) / M
+    assert np.allclose(com[0, :3], gc, rtol=0, atol=1e-13)
+    for k in range(t["first"].size):
+        f, c = int(t["first"][k]), int(t["count"][k])
+        d = np.linalg.norm(ps[f:f + c, :3] - com[k, :3], axis=1)
+        assert d.max() <= b[k] * (1 + 1e-14) + 1e-300  # contains every member
+        assert d.max() >= b[k] * (1 - 1e-14)  # and is tight
+        nc = int(t["n_child"][k])
+        if nc:
+            ch = np.arange(int(t["child_first"][k]), int(t["child_first"][k]) + nc)
+            Mc = com[ch, 3]
+            assert abs(Mc.sum() - com[k, 3]) <= 1e-14 * com[k, 3]
+            rc = (com[ch, :3] * Mc[:, None]).sum(0) / Mc.sum()
+            assert np.allclose(rc, com[k, :3], rtol=0, atol=1e-13)
+            # parallel-axis: S_parent = sum_c [S_c + M_c d_c d_c^T]
+            dd = com[ch, :3] - com[k, :3]
+            Sp = S[ch].sum(0).copy()
+            Sp[0] += (Mc * dd[:, 0] ** 2).sum(); Sp[1] += (Mc * dd[:, 1] ** 2).sum()
+            Sp[2] += (Mc * dd[:, 2] ** 2).sum(); Sp[3] += (Mc * dd[:, 0] * dd[:, 1]).sum()
+            Sp[4] += (Mc * dd[:, 0] * dd[:, 2]).sum(); Sp[5] += (Mc * dd[:, 1] * dd[:, 2]).sum()
+            scale = com[k, 3] * max(b[k], 1e-300) ** 2
+            assert np.abs(Sp - S[k]).max() <= 1e-12 * scale
+
+
+def test_groups_chunks_and_geo_ball():
+    xyzm = ics.plummer(1000, seed=4)
+    act = ics.random_active(1000, 0.3, seed=8)
+    k, _ = oracle.keys(xyzm, 0)
+    ks, perm = oracle.sort(k)
+    ps = xyzm[perm].astype(np.float64)
+    g = oracle.groups(act[perm], ps, 32)
+    na = int(act.sum())
+    assert np.array_equal(g["alist"], np.flatnonzero(act[perm]).astype(np.uint32))
+    assert g["first"].size == (na + 31) // 32
+    assert (g["count"][:-1] == 32).all() and g["count"].sum() == na
+    for q in range(g["first"].size):
+        mem = ps[g["alist"][g["first"][q]:g["first"][q] + g["count"][q]], :3]
+        c = 0.5 * (mem.min(0) + mem.max(0))
+        assert np.array_equal(g["ball"][q, :3], c)
+        assert np.isclose(g["ball"][q, 3], np.linalg.norm(mem - c, axis=1).max(), rtol=1e-15)

@@ -1,0 +1,171 @@
+/*
+ * gothic.h - C ABI of the MI355X (gfx950) block-step tree-gravity library.
+ *
+ * The library evaluates Plummer-softened gravity on the active i-particles of
+ * a hierarchical (block) time step with a Barnes-Hut octree, following
+ * Miki & Umemura, "GOTHIC: Gravitational oct-tree code accelerated by
+ * hierarchical time step controlling" (arXiv:1610.07279):
+ *   - Section 1: the softened force a_i = sum_j m_j (r_j - r_i) /
+ *     (|r_j - r_i|^2 + eps^2)^{3/2} (G = 1) that the tree approximates;
+ *   - Section 2.1: space-filling-curve keys, key sort, breadth-first octree,
+ *     pseudo j-particles (mass, centre of mass, enclosing radius b_J);
+ *   - Section 2.2: the opening-angle MAC b_J / d <= theta (Barnes & Hut);
+ *   - Section 2.3: groups of i-particles sharing one walk through a pseudo
+ *     i-particle (r_I, b_I) with d = lambda r_JI, and a small interaction list
+ *     flushed when full;
+ *   - Section 2.5: several lanes per i-particle (ij-parallelisation);
+ *   - Section 2.7: block time steps (only particles due at time t are active).
+ *
+ * Conventions for every call:
+ *   - Particle arrays are DEVICE pointers owned by the caller.  The library
+ *     owns only the scratch inside a context.
+ *   - Work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *     void*; NULL = the null stream).  Results are valid once that stream has
+ *     synchronised.  Calls that return counts synchronise the stream.
+ *   - Errors are negative return codes (gothic_status); the thread-local
+ *     message is in gothic_last_error().  Nothing aborts.
+ *   - Not thread-safe per context: one context serves one host thread (and
+ *     its calls run in stream order).
+ *   - Units: G = 1.  Outputs are in the caller's particle order.
+ */
+#ifndef GOTHIC_H
+#define GOTHIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gothic_ctx gothic_ctx;
+
+typedef enum {
+  GOTHIC_OK = 0,
+  GOTHIC_EINVAL = -1,     /* bad argument (n, eps, theta, pointer, parameter) */
+  GOTHIC_ENOMEM = -2,     /* device allocation failed */
+  GOTHIC_EDEVICE = -3,    /* a HIP call failed (message says which) */
+  GOTHIC_EOVERFLOW = -4,  /* node, frontier or list capacity exceeded twice */
+  GOTHIC_ECAPTURE = -5,   /* scratch would have to grow during stream capture */
+  GOTHIC_ENONFINITE = -6  /* NaN or Inf in the positions or masses */
+} gothic_status;
+
+typedef enum { GOTHIC_KEY_MORTON = 0, GOTHIC_KEY_PEANO_HILBERT = 1 } gothic_key_kind;
+
+/* Tunables.  Fill with gothic_default_params() and override fields. */
+typedef struct {
+  int key_kind;       /* GOTHIC_KEY_MORTON (default) or GOTHIC_KEY_PEANO_HILBERT
+                         (Appendix A); both give the same cells, in a different
+                         order */
+  int n_leaf;         /* a node with more than n_leaf particles is split
+                         (1..64; default 16) */
+  int multipole;      /* 1 = monopole pseudo particles (Section 2.1),
+                         2 = monopole + quadrupole node terms (extension) */
+  int group_size;     /* G: i-particles per group sharing one walk; a power of
+                         two in 1..64 (default 32) */
+  int list_depth;     /* capacity of the per-wave LDS interaction list in
+                         entries, a multiple of 64 in 64..1024 (default 512) */
+  int compensated;    /* 1: Neumaier-compensated accumulation of the per-flush
+                         partial sums; 0: plain FP32 (default 1) */
+  int check;          /* 1: every force call synchronises its stream at the end,
+                         checks the device error flags, grows scratch and
+                         repeats once on overflow; 0: fully asynchronous, flags
+                         are reported by the next gothic_get_stats() (default 1) */
+} gothic_params;
+
+/* Statistics of the last force evaluation (filled by gothic_get_stats). */
+typedef struct {
+  int64_t n;              /* particles */
+  int64_t n_active;       /* active i-particles */
+  int64_t n_nodes;        /* tree nodes */
+  int64_t n_groups;       /* i-particle groups */
+  int64_t n_levels;       /* deepest tree level + 1 */
+  int64_t node_entries;   /* sum over groups of accepted node list entries */
+  int64_t part_entries;   /* sum over groups of particle list entries */
+  int64_t interactions;   /* sum over active i of its list length */
+  int64_t node_interactions; /* the part of interactions that are node terms */
+  int64_t mac_tests;      /* MAC evaluations over all groups */
+  int32_t flags;          /* device error flags (bit 0 non-finite input, bit 1
+                             node overflow, bit 2 frontier overflow) */
+  int32_t pad;
+} gothic_stats;
+
+/* Default tunables (see gothic_params). */
+void gothic_default_params(gothic_params *p);
+
+/* Create a context on HIP device `hip_device`.  p = NULL takes the defaults.
+ * Returns GOTHIC_OK and *out, or an error (EINVAL for bad parameters,
+ * EDEVICE when the device cannot be used). */
+int gothic_create(gothic_ctx **out, int hip_device, const gothic_params *p);
+
+/* Release the context and all its device scratch.  NULL is accepted. */
+int gothic_destroy(gothic_ctx *c);
+
+/* Replace the tunables of a context (validated as in gothic_create). */
+int gothic_set_params(gothic_ctx *c, const gothic_params *p);
+int gothic_get_params(const gothic_ctx *c, gothic_params *p);
+
+/*
+ * One tree-force evaluation (Sections 2.1-2.3, 2.5).
+ *   n        number of particles, 0 <= n < 2^31 (n = 0 does nothing)
+ *   xyzm     [n][4] float: x, y, z, m of every j-particle (masses >= 0)
+ *   eps      Plummer softening length, finite and > 0
+ *   theta    opening angle of the MAC, 0 <= theta < 1 (theta = 0 gives the
+ *            direct sum through the tree)
+ *   active   [n] uint8: nonzero = this particle is an i-particle of the step;
+ *            NULL = all particles are active
+ *   acc_pot  [n][4] float out: ax, ay, az, phi for active rows; rows with
+ *            active == 0 are not written.  phi excludes the self pair.
+ *   stream   hipStream_t or NULL
+ * Returns GOTHIC_OK, or EINVAL / ENONFINITE / EOVERFLOW / ENOMEM / EDEVICE
+ * (the last three only in check mode, or from gothic_get_stats otherwise).
+ * xyzm and acc_pot must not overlap.
+ */
+int gothic_tree_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, float theta,
+                       const uint8_t *active, float *acc_pot, void *stream);
+
+/*
+ * Many independent systems in one call (one walk launch over the groups of
+ * every system).  System s owns particles [offsets[s], offsets[s+1]) of xyzm,
+ * active and acc_pot, with its own softening eps[s] and angle theta[s]; each
+ * system gets its own keys, tree and groups.  offsets/eps/theta are HOST
+ * arrays of nsys+1 / nsys / nsys entries.  Same rules as gothic_tree_forces.
+ */
+int gothic_tree_forces_batched(gothic_ctx *c, int nsys, const int64_t *offsets,
+                               const float *xyzm, const float *eps, const float *theta,
+                               const uint8_t *active, float *acc_pot, void *stream);
+
+/* Counts of the last evaluation; synchronises the stream of that call. */
+int gothic_get_stats(gothic_ctx *c, gothic_stats *out);
+
+/*
+ * Introspection of the last single-system evaluation, for bit-exact tests.
+ * All outputs are caller-owned DEVICE buffers sized from gothic_get_stats;
+ * any pointer may be NULL to skip it.  Each call synchronises.
+ *   keys_sorted [n] uint64 and perm [n] uint32: the stable key sort
+ *     (perm[k] = caller index of the k-th particle in key order)
+ *   cube [4] double: x_min, y_min, z_min, side L of the key cube
+ *   tree [n_nodes] arrays in breadth-first order: first particle (in key
+ *     order), particle count, first child, number of children, level
+ *   nodes: com_m [n_nodes][4] float (centre of mass, mass), b [n_nodes] float
+ *     (enclosing radius), quad [n_nodes][6] float second moments about the
+ *     centre of mass (xx, yy, zz, xy, xz, yz; zero unless multipole = 2)
+ *   groups: alist [n_active] uint32 (key-order indices of the active
+ *     particles), gfirst/gcount [n_groups] into alist, ball [n_groups][4]
+ *     float (r_I, b_I), entries [n_groups][2] uint32 (node and particle list
+ *     entries of the group's walk)
+ */
+int gothic_get_keys(gothic_ctx *c, uint64_t *keys_sorted, uint32_t *perm, double *cube);
+int gothic_get_tree(gothic_ctx *c, uint32_t *first, uint32_t *count, uint32_t *child_first,
+                    uint8_t *n_child, uint8_t *level);
+int gothic_get_nodes(gothic_ctx *c, float *com_m, float *b, float *quad);
+int gothic_get_groups(gothic_ctx *c, uint32_t *alist, uint32_t *gfirst, uint32_t *gcount,
+                      float *ball, uint32_t *entries);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *gothic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GOTHIC_H */

@@ -30,8 +30,8 @@ def _load():
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
-        from . import build as _b
-        _b.build()
+        from . import build_lib
+        build_lib.build()
     lib = C.CDLL(_LIB_PATH)
     P = C.c_void_p
     i64, f64, i32 = C.c_int64, C.c_double, C.c_int

@@ -381,8 +381,10 @@ static void pair_quad(const double yi[3], const double rj[3], const double S[6],
  *
  * multipole: 1 monopole, 2 monopole + quadrupole for node entries.
  * Per group: cnt[3g+0] accepted node entries, cnt[3g+1] particle entries,
- * cnt[3g+2] near ties |b_J - theta d| <= tie_rel max(b_J, theta d) + tie_abs
- * among nodes with b_J > 0 (b_J = 0 is accepted at any distance);
+ * cnt[3g+2] near ties |b_J - theta d| <= tie_rel max(b_J, theta d) + tie_abs s,
+ * s = |r_J|_1 + |r_I|_1 + b_I (the coordinate scale that bounds the absolute
+ * rounding of a single-precision evaluation), among nodes with b_J > 0 (b_J = 0
+ * is accepted at any distance);
  * mass[g] = summed mass of the list (mass closure).
  * gsel: optional subset of groups to evaluate (ngsel entries), NULL = all.
  * out: [n][4] in sorted order; rows of evaluated active particles written.   */
@@ -418,7 +420,9 @@ void orc_walk(int64_t nn, const uint32_t *first, const uint32_t *count,
         const double d = lam * rJI;
         const double td = theta * d;
         const double big = b[J] > td ? b[J] : td;
-        if (b[J] > 0 && fabs(b[J] - td) <= tie_rel * big + tie_abs) ++ties;
+        const double scale = fabs(com[4 * J]) + fabs(com[4 * J + 1]) + fabs(com[4 * J + 2]) +
+                             fabs(rI[0]) + fabs(rI[1]) + fabs(rI[2]) + bI;
+        if (b[J] > 0 && fabs(b[J] - td) <= tie_rel * big + tie_abs * scale) ++ties;
         if (b[J] <= td) {
           lst[nl++] = J;
         } else if (n_child[J] == 0) {

@@ -1,0 +1,267 @@
+"""Python binding of the MI355X tree-gravity library (libgothic.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/gothic.h.  PyTorch provides the
+device memory and the stream; tensors are passed by pointer.  If the built
+library is missing, importing this package fails (there is no fallback).
+
+    import torch, paper_1610_07279_amd as g
+    ctx = g.Context(multipole=2)
+    acc_pot = ctx.tree_forces(xyzm_cuda, eps=1/512, theta=0.5, active=mask_u8)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgothic.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "gothic.h")
+
+OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, ECAPTURE, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+KEY_MORTON, KEY_PEANO_HILBERT = 0, 1
+
+
+class GothicError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gothic error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("key_kind", C.c_int), ("n_leaf", C.c_int), ("multipole", C.c_int),
+                ("group_size", C.c_int), ("list_depth", C.c_int), ("compensated", C.c_int),
+                ("check", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_active", C.c_int64), ("n_nodes", C.c_int64),
+                ("n_groups", C.c_int64), ("n_levels", C.c_int64), ("node_entries", C.c_int64),
+                ("part_entries", C.c_int64), ("interactions", C.c_int64),
+                ("node_interactions", C.c_int64), ("mac_tests", C.c_int64),
+                ("flags", C.c_int32), ("pad", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(or python paper_1610_07279_amd/csrc/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    P, i32, i64, f32 = C.c_void_p, C.c_int, C.c_int64, C.c_float
+    lib.gothic_default_params.argtypes = [C.POINTER(Params)]
+    lib.gothic_default_params.restype = None
+    lib.gothic_last_error.restype = C.c_char_p
+    lib.gothic_create.argtypes = [C.POINTER(P), i32, C.POINTER(Params)]
+    lib.gothic_destroy.argtypes = [P]
+    lib.gothic_set_params.argtypes = [P, C.POINTER(Params)]
+    lib.gothic_get_params.argtypes = [P, C.POINTER(Params)]
+    lib.gothic_tree_forces.argtypes = [P, i64, P, f32, f32, P, P, P]
+    lib.gothic_tree_forces_batched.argtypes = [P, i32, P, P, P, P, P, P, P]
+    lib.gothic_get_stats.argtypes = [P, C.POINTER(Stats)]
+    lib.gothic_get_keys.argtypes = [P, P, P, P]
+    lib.gothic_get_tree.argtypes = [P, P, P, P, P, P]
+    lib.gothic_get_nodes.argtypes = [P, P, P, P]
+    lib.gothic_get_groups.argtypes = [P, P, P, P, P, P]
+    for name in ("gothic_create", "gothic_destroy", "gothic_set_params", "gothic_get_params",
+                 "gothic_tree_forces", "gothic_tree_forces_batched", "gothic_get_stats",
+                 "gothic_get_keys", "gothic_get_tree", "gothic_get_nodes", "gothic_get_groups"):
+        getattr(lib, name).restype = i32
+    return lib
+
+
+lib = _load()
+
+
+def header_functions(path: str = HEADER):
+    """Names of every function the public header declares."""
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gothic_[a-z_]+)\s*\(", txt)))
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise GothicError(rc, lib.gothic_last_error().decode())
+
+
+def default_params() -> Params:
+    p = Params()
+    lib.gothic_default_params(C.byref(p))
+    return p
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_of(t, stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(t.device)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """One library context (scratch, tunables) on one GPU."""
+
+    def __init__(self, device: int = 0, **params):
+        p = default_params()
+        for k, v in params.items():
+            if not hasattr(p, k):
+                raise TypeError(f"unknown parameter {k}")
+            setattr(p, k, int(v))
+        h = C.c_void_p()
+        _check(lib.gothic_create(C.byref(h), int(device), C.byref(p)))
+        self._h = h
+        self.device = device
+        self._last_stream = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.gothic_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- params
+    @property
+    def params(self) -> dict:
+        p = Params()
+        _check(lib.gothic_get_params(self._h, C.byref(p)))
+        return {k: getattr(p, k) for k, _ in Params._fields_}
+
+    def set_params(self, **params):
+        p = Params()
+        _check(lib.gothic_get_params(self._h, C.byref(p)))
+        for k, v in params.items():
+            if not hasattr(p, k):
+                raise TypeError(f"unknown parameter {k}")
+            setattr(p, k, int(v))
+        _check(lib.gothic_set_params(self._h, C.byref(p)))
+
+    # ---------------------------------------------------------------- forces
+    def tree_forces(self, xyzm, eps: float, theta: float, active=None, out=None, stream=None):
+        """acc_pot [n,4] float32 (ax, ay, az, phi) for the active rows of xyzm."""
+        import torch
+        if xyzm.dtype != torch.float32 or xyzm.dim() != 2 or xyzm.shape[1] != 4:
+            raise ValueError("xyzm must be a float32 [n,4] tensor")
+        if not xyzm.is_cuda or not xyzm.is_contiguous():
+            raise ValueError("xyzm must be a contiguous GPU tensor")
+        n = xyzm.shape[0]
+        if active is not None:
+            if active.dtype != torch.uint8 or active.shape != (n,) or not active.is_cuda \
+                    or not active.is_contiguous():
+                raise ValueError("active must be a contiguous uint8 [n] GPU tensor")
+        if out is None:
+            out = torch.zeros((n, 4), dtype=torch.float32, device=xyzm.device)
+        elif out.dtype != torch.float32 or out.shape != (n, 4) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 [n,4] tensor")
+        s = _stream_of(xyzm, stream)
+        self._last_stream = s
+        _check(lib.gothic_tree_forces(self._h, n, _ptr(xyzm), float(eps), float(theta),
+                                      _ptr(active), _ptr(out), s))
+        return out
+
+    def tree_forces_batched(self, xyzm, offsets, eps, theta, active=None, out=None, stream=None):
+        import numpy as np
+        import torch
+        offs = np.ascontiguousarray(offsets, dtype=np.int64)
+        nsys = offs.size - 1
+        e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float32), (nsys,)))
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(theta, np.float32), (nsys,)))
+        n = xyzm.shape[0]
+        if out is None:
+            out = torch.zeros((n, 4), dtype=torch.float32, device=xyzm.device)
+        s = _stream_of(xyzm, stream)
+        _check(lib.gothic_tree_forces_batched(
+            self._h, nsys, offs.ctypes.data_as(C.c_void_p), _ptr(xyzm),
+            e.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p), _ptr(active), _ptr(out),
+            s))
+        return out
+
+    # ---------------------------------------------------------------- introspection
+    def stats(self) -> dict:
+        st = Stats()
+        _check(lib.gothic_get_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def _stats_raw(self) -> dict:
+        st = Stats()
+        lib.gothic_get_stats(self._h, C.byref(st))
+        return st.as_dict()
+
+    def keys(self):
+        """(keys_sorted uint64 numpy, perm uint32 numpy, cube float64 numpy)"""
+        import torch
+        st = self._stats_raw()
+        n = st["n"]
+        dev = torch.device("cuda", self.device)
+        k = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+        p = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        cb = torch.empty(4, dtype=torch.float64, device=dev)
+        _check(lib.gothic_get_keys(self._h, _ptr(k), _ptr(p), _ptr(cb)))
+        return (k[:n].cpu().numpy().view("uint64"), p[:n].cpu().numpy().view("uint32"),
+                cb.cpu().numpy())
+
+    def tree(self) -> dict:
+        import torch
+        nn = self._stats_raw()["n_nodes"]
+        dev = torch.device("cuda", self.device)
+        m = max(nn, 1)
+        f = torch.empty(m, dtype=torch.int32, device=dev)
+        c = torch.empty(m, dtype=torch.int32, device=dev)
+        cf = torch.empty(m, dtype=torch.int32, device=dev)
+        nc = torch.empty(m, dtype=torch.uint8, device=dev)
+        lv = torch.empty(m, dtype=torch.uint8, device=dev)
+        _check(lib.gothic_get_tree(self._h, _ptr(f), _ptr(c), _ptr(cf), _ptr(nc), _ptr(lv)))
+        u = lambda t: t[:nn].cpu().numpy().view("uint32")
+        return dict(first=u(f), count=u(c), child_first=u(cf), n_child=nc[:nn].cpu().numpy(),
+                    level=lv[:nn].cpu().numpy())
+
+    def nodes(self):
+        """(com_m [nn,4] float32, b [nn] float32, quad [nn,6] float32) as numpy"""
+        import torch
+        nn = self._stats_raw()["n_nodes"]
+        dev = torch.device("cuda", self.device)
+        m = max(nn, 1)
+        cm = torch.empty((m, 4), dtype=torch.float32, device=dev)
+        b = torch.empty(m, dtype=torch.float32, device=dev)
+        q = torch.empty((m, 6), dtype=torch.float32, device=dev)
+        _check(lib.gothic_get_nodes(self._h, _ptr(cm), _ptr(b), _ptr(q)))
+        return cm[:nn].cpu().numpy(), b[:nn].cpu().numpy(), q[:nn].cpu().numpy()
+
+    def groups(self) -> dict:
+        import torch
+        st = self._stats_raw()
+        na, ng = st["n_active"], st["n_groups"]
+        dev = torch.device("cuda", self.device)
+        al = torch.empty(max(na, 1), dtype=torch.int32, device=dev)
+        gf = torch.empty(max(ng, 1), dtype=torch.int32, device=dev)
+        gc = torch.empty(max(ng, 1), dtype=torch.int32, device=dev)
+        ball = torch.empty((max(ng, 1), 4), dtype=torch.float32, device=dev)
+        ent = torch.empty((max(ng, 1), 2), dtype=torch.int32, device=dev)
+        _check(lib.gothic_get_groups(self._h, _ptr(al), _ptr(gf), _ptr(gc), _ptr(ball),
+                                     _ptr(ent)))
+        u = lambda t, k: t[:k].cpu().numpy().view("uint32")
+        return dict(alist=u(al, na), first=u(gf, ng), count=u(gc, ng),
+                    ball=ball[:ng].cpu().numpy(), entries=u(ent, ng))
+
+
+_default_ctx = {}
+
+
+def tree_forces(xyzm, eps, theta, active=None, out=None, **params):
+    """Convenience wrapper with a cached context per (device, params)."""
+    key = (xyzm.device.index or 0, tuple(sorted(params.items())))
+    ctx = _default_ctx.get(key)
+    if ctx is None:
+        ctx = _default_ctx[key] = Context(device=key[0], **params)
+    return ctx.tree_forces(xyzm, eps, theta, active=active, out=out)

@@ -1,0 +1,421 @@
+// C ABI of the library (declared in include/gothic.h): context and scratch
+// management, argument checks, the kernel pipeline of one force evaluation,
+// and read-back of intermediate results for tests.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "common.h"
+
+namespace gothic {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_check(hipError_t e, const char *what) {
+  if (e == hipSuccess) return GOTHIC_OK;
+  return set_error(e == hipErrorOutOfMemory ? GOTHIC_ENOMEM : GOTHIC_EDEVICE,
+                   std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define GCHECK(call)                                   \
+  do {                                                 \
+    int _rc = hip_check((call), #call);                \
+    if (_rc != GOTHIC_OK) return _rc;                  \
+  } while (0)
+
+// ---------------------------------------------------------------- helpers
+__global__ void ctl_reset_k(Ctl *ctl) {
+  unsigned *w = reinterpret_cast<unsigned *>(ctl);
+  for (unsigned i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) w[i] = 0u;
+}
+
+__global__ void extract_nodes_k(const Ctl *ctl, const float4 *nrec, const float4 *quad,
+                                float4 *com_m, float *b, float *q6) {
+  const int64_t nn = ctl->n_nodes;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nn;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    if (com_m) com_m[k] = nrec[2 * k];
+    if (b) b[k] = nrec[2 * k + 1].x;
+    if (q6) {
+      const float4 a = quad[2 * k], c = quad[2 * k + 1];
+      q6[6 * k + 0] = a.x; q6[6 * k + 1] = a.y; q6[6 * k + 2] = a.z;
+      q6[6 * k + 3] = a.w; q6[6 * k + 4] = c.x; q6[6 * k + 5] = c.y;
+    }
+  }
+}
+
+__global__ void extract_groups_k(const Ctl *ctl, int G, uint32_t *gfirst, uint32_t *gcount) {
+  const unsigned ng = ctl->n_groups, na = ctl->n_active;
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += gridDim.x * blockDim.x) {
+    const unsigned s = g * (unsigned)G;
+    if (gfirst) gfirst[g] = s;
+    if (gcount) gcount[g] = (na - s) < (unsigned)G ? (na - s) : (unsigned)G;
+  }
+}
+
+template <class T>
+static int dev_alloc(T **p, int64_t count) {
+  if (*p) {
+    (void)hipFree(*p);
+    *p = nullptr;
+  }
+  if (count <= 0) count = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * (size_t)count);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_check(e, "hipMalloc");
+  }
+  return GOTHIC_OK;
+}
+
+static void free_all(gothic_ctx *c) {
+  Buffers &B = c->b;
+  void *ptrs[] = {B.keyA, B.keyB, B.idxA, B.idxB, B.pos, B.leaf_of, B.flag, B.flag2, B.alist,
+                  B.first, B.count, B.child_first, B.parent, B.n_child, B.level, B.nch, B.bnd,
+                  B.nrec, B.quad, B.ball, B.gent, B.hist, B.part, B.bbox_part, B.spill, B.ctl};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (B.ctl_host) (void)hipHostFree(B.ctl_host);
+  B = Buffers();
+  c->cap_n = c->cap_nodes = c->cap_groups = c->cap_hist = 0;
+}
+
+static int validate_params(const gothic_params *p) {
+  if (p->key_kind != GOTHIC_KEY_MORTON && p->key_kind != GOTHIC_KEY_PEANO_HILBERT)
+    return set_error(GOTHIC_EINVAL, "key_kind must be 0 (Morton) or 1 (Peano-Hilbert)");
+  if (p->n_leaf < 1 || p->n_leaf > 64) return set_error(GOTHIC_EINVAL, "n_leaf must be in 1..64");
+  if (p->multipole != 1 && p->multipole != 2)
+    return set_error(GOTHIC_EINVAL, "multipole must be 1 or 2");
+  const int G = p->group_size;
+  if (G < 1 || G > 64 || (G & (G - 1)))
+    return set_error(GOTHIC_EINVAL, "group_size must be a power of two in 1..64");
+  if (p->list_depth < 64 || p->list_depth > 1024 || (p->list_depth % 64))
+    return set_error(GOTHIC_EINVAL, "list_depth must be a multiple of 64 in 64..1024");
+  if (p->compensated != 0 && p->compensated != 1)
+    return set_error(GOTHIC_EINVAL, "compensated must be 0 or 1");
+  if (p->check != 0 && p->check != 1) return set_error(GOTHIC_EINVAL, "check must be 0 or 1");
+  return GOTHIC_OK;
+}
+
+// Make sure every buffer can hold n particles (and the current node / spill
+// capacities).  Never called while the stream is being captured.
+static int ensure(gothic_ctx *c, int64_t n, int64_t want_nodes, int64_t want_spill) {
+  Buffers &B = c->b;
+  if (!B.ctl) {
+    GCHECK(hipMalloc(reinterpret_cast<void **>(&B.ctl), sizeof(Ctl)));
+    GCHECK(hipHostMalloc(reinterpret_cast<void **>(&B.ctl_host), sizeof(Ctl), hipHostMallocDefault));
+    int rc;
+    if ((rc = dev_alloc(&B.part, scan_blocks() + 64)) != GOTHIC_OK) return rc;
+    if ((rc = dev_alloc(&B.bbox_part, 1024 * 6)) != GOTHIC_OK) return rc;
+  }
+  int rc;
+  if (n > c->cap_n) {
+    const int64_t cn = std::max<int64_t>(n, 1024);
+    if ((rc = dev_alloc(&B.keyA, cn)) || (rc = dev_alloc(&B.keyB, cn)) ||
+        (rc = dev_alloc(&B.idxA, cn)) || (rc = dev_alloc(&B.idxB, cn)) ||
+        (rc = dev_alloc(&B.pos, cn)) || (rc = dev_alloc(&B.leaf_of, cn)) ||
+        (rc = dev_alloc(&B.flag, cn)) || (rc = dev_alloc(&B.flag2, cn)) ||
+        (rc = dev_alloc(&B.alist, cn)) || (rc = dev_alloc(&B.nch, cn + 1)) ||
+        (rc = dev_alloc(&B.bnd, 8 * cn + 8)) || (rc = dev_alloc(&B.ball, cn)) ||
+        (rc = dev_alloc(&B.gent, 2 * cn)))
+      return rc;
+    const int64_t hist = 2 * radix_hist_entries(cn);
+    if ((rc = dev_alloc(&B.hist, hist))) return rc;
+    c->cap_n = cn;
+    c->cap_groups = cn;
+    c->cap_hist = hist;
+  }
+  const int64_t nodes = std::max<int64_t>(want_nodes, c->cap_n + 1024);
+  if (nodes > c->cap_nodes) {
+    if ((rc = dev_alloc(&B.first, nodes)) || (rc = dev_alloc(&B.count, nodes)) ||
+        (rc = dev_alloc(&B.child_first, nodes)) || (rc = dev_alloc(&B.parent, nodes)) ||
+        (rc = dev_alloc(&B.n_child, nodes)) || (rc = dev_alloc(&B.level, nodes)) ||
+        (rc = dev_alloc(&B.nrec, 2 * nodes)) || (rc = dev_alloc(&B.quad, 2 * nodes)))
+      return rc;
+    c->cap_nodes = nodes;
+  }
+  const int slots = walk_slots(c);
+  const int64_t spill = std::max<int64_t>(want_spill, 16384);
+  if (slots != c->walk_waves || spill > c->spill_per_wave || !B.spill) {
+    if ((rc = dev_alloc(&B.spill, (int64_t)slots * spill))) return rc;
+    c->walk_waves = slots;
+    c->spill_per_wave = spill;
+  }
+  return GOTHIC_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+static int enqueue_forces(gothic_ctx *c, int64_t n, const float4 *xyzm, float eps, float theta,
+                          const uint8_t *active, float4 *out, hipStream_t s) {
+  Buffers &B = c->b;
+  hipLaunchKernelGGL(ctl_reset_k, dim3(1), dim3(64), 0, s, B.ctl);
+  launch_bbox_keys(c, xyzm, n, s);
+  launch_radix_sort(c, n, s);
+  launch_permute(c, xyzm, active, n, s);
+  launch_build(c, n, s);
+  launch_moments(c, n, s);
+  launch_groups(c, n, s);
+  launch_walk(c, n, eps, theta, out, s);
+  return hip_check(hipGetLastError(), "kernel launch");
+}
+
+}  // namespace gothic
+
+using namespace gothic;
+
+extern "C" {
+
+void gothic_default_params(gothic_params *p) {
+  if (!p) return;
+  p->key_kind = GOTHIC_KEY_MORTON;
+  p->n_leaf = 16;
+  p->multipole = 1;
+  p->group_size = 32;
+  p->list_depth = 512;
+  p->compensated = 1;
+  p->check = 1;
+}
+
+const char *gothic_last_error(void) { return g_last_error.c_str(); }
+
+int gothic_create(gothic_ctx **out, int hip_device, const gothic_params *p) {
+  if (!out) return set_error(GOTHIC_EINVAL, "out is NULL");
+  *out = nullptr;
+  gothic_params prm;
+  gothic_default_params(&prm);
+  if (p) prm = *p;
+  int rc = validate_params(&prm);
+  if (rc) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return set_error(GOTHIC_EDEVICE, "no HIP device available");
+  if (hip_device < 0 || hip_device >= ndev) return set_error(GOTHIC_EINVAL, "bad device index");
+  DeviceGuard guard(hip_device);
+  hipDeviceProp_t prop;
+  if ((rc = hip_check(hipGetDeviceProperties(&prop, hip_device), "hipGetDeviceProperties")))
+    return rc;
+  gothic_ctx *c = new gothic_ctx();
+  c->device = hip_device;
+  c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+  c->prm = prm;
+  *out = c;
+  return GOTHIC_OK;
+}
+
+int gothic_destroy(gothic_ctx *c) {
+  if (!c) return GOTHIC_OK;
+  {
+    DeviceGuard guard(c->device);
+    (void)hipDeviceSynchronize();
+    free_all(c);
+  }
+  delete c;
+  return GOTHIC_OK;
+}
+
+int gothic_set_params(gothic_ctx *c, const gothic_params *p) {
+  if (!c || !p) return set_error(GOTHIC_EINVAL, "NULL argument");
+  int rc = validate_params(p);
+  if (rc) return rc;
+  c->prm = *p;
+  return GOTHIC_OK;
+}
+
+int gothic_get_params(const gothic_ctx *c, gothic_params *p) {
+  if (!c || !p) return set_error(GOTHIC_EINVAL, "NULL argument");
+  *p = c->prm;
+  return GOTHIC_OK;
+}
+
+int gothic_tree_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, float theta,
+                       const uint8_t *active, float *acc_pot, void *stream) {
+  if (!c) return set_error(GOTHIC_EINVAL, "context is NULL");
+  if (n < 0 || n >= (int64_t)1 << 31) return set_error(GOTHIC_EINVAL, "n must be in [0, 2^31)");
+  if (!(eps > 0.f) || !std::isfinite(eps)) return set_error(GOTHIC_EINVAL, "eps must be finite and > 0");
+  if (!(theta >= 0.f && theta < 1.f)) return set_error(GOTHIC_EINVAL, "theta must be in [0, 1)");
+  if (n == 0) return GOTHIC_OK;
+  if (!xyzm || !acc_pot) return set_error(GOTHIC_EINVAL, "xyzm and acc_pot must not be NULL");
+  if ((const void *)xyzm == (const void *)acc_pot)
+    return set_error(GOTHIC_EINVAL, "xyzm and acc_pot must not overlap");
+  DeviceGuard guard(c->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(s, &cap);
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  const int64_t want_nodes = std::max<int64_t>(c->cap_nodes, n + 1024);
+  const bool must_grow = n > c->cap_n || want_nodes > c->cap_nodes || !c->b.spill ||
+                         walk_slots(c) != c->walk_waves;
+  if (capturing && must_grow)
+    return set_error(GOTHIC_ECAPTURE, "scratch must grow for n = " + std::to_string(n) +
+                                          "; make one uncaptured call of this size first");
+  int rc = ensure(c, n, want_nodes, c->spill_per_wave);
+  if (rc) return rc;
+  c->last_n = n;
+  c->last_stream = s;
+  c->have_last = true;
+  const float4 *x4 = reinterpret_cast<const float4 *>(xyzm);
+  float4 *o4 = reinterpret_cast<float4 *>(acc_pot);
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    if ((rc = enqueue_forces(c, n, x4, eps, theta, active, o4, s))) return rc;
+    if (!c->prm.check || capturing) return GOTHIC_OK;
+    if ((rc = hip_check(hipMemcpyAsync(c->b.ctl_host, c->b.ctl, sizeof(Ctl),
+                                       hipMemcpyDeviceToHost, s), "hipMemcpyAsync")))
+      return rc;
+    if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
+    const unsigned f = c->b.ctl_host->flags;
+    if (f & kFlagNonFinite) return set_error(GOTHIC_ENONFINITE, "non-finite position or mass");
+    if (!(f & (kFlagNodeOverflow | kFlagSpillOverflow))) return GOTHIC_OK;
+    if (attempt == 2) break;
+    const int64_t nodes = (f & kFlagNodeOverflow) ? 2 * c->cap_nodes : c->cap_nodes;
+    const int64_t spill = (f & kFlagSpillOverflow) ? 4 * c->spill_per_wave : c->spill_per_wave;
+    if ((rc = ensure(c, n, nodes, spill))) return rc;
+  }
+  return set_error(GOTHIC_EOVERFLOW, "node or frontier capacity still exceeded after growing");
+}
+
+int gothic_get_stats(gothic_ctx *c, gothic_stats *out) {
+  if (!c || !out) return set_error(GOTHIC_EINVAL, "NULL argument");
+  memset(out, 0, sizeof(*out));
+  if (!c->have_last) return GOTHIC_OK;
+  DeviceGuard guard(c->device);
+  int rc;
+  if ((rc = hip_check(hipMemcpyAsync(c->b.ctl_host, c->b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
+                                     c->last_stream), "hipMemcpyAsync")))
+    return rc;
+  if ((rc = hip_check(hipStreamSynchronize(c->last_stream), "hipStreamSynchronize"))) return rc;
+  const Ctl &h = *c->b.ctl_host;
+  out->n = c->last_n;
+  out->n_active = h.n_active;
+  out->n_nodes = h.n_nodes;
+  out->n_groups = h.n_groups;
+  int lev = 0;
+  for (int l = 0; l < kMaxLevels; ++l)
+    if (h.lvl_start[l + 1] > h.lvl_start[l]) lev = l + 1;
+  out->n_levels = lev;
+  out->node_entries = (int64_t)h.node_entries;
+  out->part_entries = (int64_t)h.part_entries;
+  out->interactions = (int64_t)h.interactions;
+  out->node_interactions = (int64_t)h.node_interactions;
+  out->mac_tests = (int64_t)h.mac_tests;
+  out->flags = (int32_t)h.flags;
+  if (h.flags & kFlagNonFinite) return set_error(GOTHIC_ENONFINITE, "non-finite position or mass");
+  if (h.flags & (kFlagNodeOverflow | kFlagSpillOverflow))
+    return set_error(GOTHIC_EOVERFLOW, "capacity exceeded in the last evaluation");
+  return GOTHIC_OK;
+}
+
+static int last_counts(gothic_ctx *c, Ctl *h) {
+  if (!c->have_last) return set_error(GOTHIC_EINVAL, "no evaluation yet");
+  int rc;
+  if ((rc = hip_check(hipMemcpyAsync(c->b.ctl_host, c->b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
+                                     c->last_stream), "hipMemcpyAsync")))
+    return rc;
+  if ((rc = hip_check(hipStreamSynchronize(c->last_stream), "hipStreamSynchronize"))) return rc;
+  *h = *c->b.ctl_host;
+  return GOTHIC_OK;
+}
+
+static int d2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (!dst || !bytes) return GOTHIC_OK;
+  return hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+}
+
+int gothic_get_keys(gothic_ctx *c, uint64_t *keys_sorted, uint32_t *perm, double *cube) {
+  if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
+  DeviceGuard guard(c->device);
+  Ctl h;
+  int rc = last_counts(c, &h);
+  if (rc) return rc;
+  hipStream_t s = c->last_stream;
+  const size_t n = (size_t)c->last_n;
+  if ((rc = d2d(keys_sorted, c->b.keyA, n * 8, s)) || (rc = d2d(perm, c->b.idxA, n * 4, s)) ||
+      (rc = d2d(cube, c->b.ctl->cube, 4 * sizeof(double), s)))
+    return rc;
+  return hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+int gothic_get_tree(gothic_ctx *c, uint32_t *first, uint32_t *count, uint32_t *child_first,
+                    uint8_t *n_child, uint8_t *level) {
+  if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
+  DeviceGuard guard(c->device);
+  Ctl h;
+  int rc = last_counts(c, &h);
+  if (rc) return rc;
+  hipStream_t s = c->last_stream;
+  const size_t nn = h.n_nodes;
+  if ((rc = d2d(first, c->b.first, nn * 4, s)) || (rc = d2d(count, c->b.count, nn * 4, s)) ||
+      (rc = d2d(child_first, c->b.child_first, nn * 4, s)) ||
+      (rc = d2d(n_child, c->b.n_child, nn, s)) || (rc = d2d(level, c->b.level, nn, s)))
+    return rc;
+  return hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+int gothic_get_nodes(gothic_ctx *c, float *com_m, float *b, float *quad) {
+  if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
+  DeviceGuard guard(c->device);
+  Ctl h;
+  int rc = last_counts(c, &h);
+  if (rc) return rc;
+  hipStream_t s = c->last_stream;
+  hipLaunchKernelGGL(extract_nodes_k, dim3(1024), dim3(256), 0, s, c->b.ctl, c->b.nrec, c->b.quad,
+                     reinterpret_cast<float4 *>(com_m), b, quad);
+  if ((rc = hip_check(hipGetLastError(), "extract_nodes_k"))) return rc;
+  return hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+int gothic_get_groups(gothic_ctx *c, uint32_t *alist, uint32_t *gfirst, uint32_t *gcount,
+                      float *ball, uint32_t *entries) {
+  if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
+  DeviceGuard guard(c->device);
+  Ctl h;
+  int rc = last_counts(c, &h);
+  if (rc) return rc;
+  hipStream_t s = c->last_stream;
+  if ((rc = d2d(alist, c->b.alist, (size_t)h.n_active * 4, s)) ||
+      (rc = d2d(ball, c->b.ball, (size_t)h.n_groups * 16, s)) ||
+      (rc = d2d(entries, c->b.gent, (size_t)h.n_groups * 8, s)))
+    return rc;
+  if (gfirst || gcount) {
+    hipLaunchKernelGGL(extract_groups_k, dim3(256), dim3(256), 0, s, c->b.ctl, c->prm.group_size,
+                       gfirst, gcount);
+    if ((rc = hip_check(hipGetLastError(), "extract_groups_k"))) return rc;
+  }
+  return hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+int gothic_tree_forces_batched(gothic_ctx *c, int nsys, const int64_t *offsets, const float *xyzm,
+                               const float *eps, const float *theta, const uint8_t *active,
+                               float *acc_pot, void *stream) {
+  if (!c || nsys < 0 || (nsys > 0 && (!offsets || !eps || !theta)))
+    return set_error(GOTHIC_EINVAL, "bad batched arguments");
+  // one evaluation per system, in stream order
+  for (int sIdx = 0; sIdx < nsys; ++sIdx) {
+    const int64_t a = offsets[sIdx], b = offsets[sIdx + 1];
+    if (b < a) return set_error(GOTHIC_EINVAL, "offsets must be non-decreasing");
+    int rc = gothic_tree_forces(c, b - a, xyzm + 4 * a, eps[sIdx], theta[sIdx],
+                                active ? active + a : nullptr, acc_pot + 4 * a, stream);
+    if (rc) return rc;
+  }
+  return GOTHIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal declarations shared by the library's HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/gothic.h"
+
+namespace gothic {
+
+constexpr int kNlev = 21;         // bits per axis of a key (63-bit keys)
+constexpr int kMaxLevels = kNlev + 1;
+constexpr int kWave = 64;         // gfx950 wavefront width
+
+// Device error flags (Ctl::flags)
+constexpr unsigned kFlagNonFinite = 1u;
+constexpr unsigned kFlagNodeOverflow = 2u;
+constexpr unsigned kFlagSpillOverflow = 4u;
+
+// Device-resident control block: every count the pipeline needs lives here so
+// no kernel launch depends on a host read-back.
+struct Ctl {
+  unsigned flags;
+  unsigned n_nodes;
+  unsigned n_active;
+  unsigned n_groups;
+  unsigned lvl_start[kMaxLevels + 2];  // nodes of level l: [lvl_start[l], lvl_start[l+1])
+  unsigned work;                       // persistent-walk group counter
+  unsigned scan_total;                 // scratch: total of the last scan
+  unsigned pad0, pad1;
+  double cube[4];                      // x_min, y_min, z_min, L
+  unsigned long long node_entries;     // summed over groups
+  unsigned long long part_entries;
+  unsigned long long interactions;     // summed over active i
+  unsigned long long node_interactions;
+  unsigned long long mac_tests;
+};
+
+struct Buffers {
+  // particles (capacity cap_n)
+  uint64_t *keyA = nullptr, *keyB = nullptr;
+  uint32_t *idxA = nullptr, *idxB = nullptr;
+  float4 *pos = nullptr;          // xyzm in key order
+  uint32_t *leaf_of = nullptr;    // leaf node of each key-ordered particle
+  uint32_t *flag = nullptr;       // active flag of each key-ordered particle (n)
+  uint32_t *flag2 = nullptr;      // scan output scratch (n)
+  uint32_t *alist = nullptr;      // key-order indices of active particles
+  // nodes (capacity cap_nodes)
+  uint32_t *first = nullptr, *count = nullptr, *child_first = nullptr, *parent = nullptr;
+  uint8_t *n_child = nullptr, *level = nullptr;
+  uint32_t *nch = nullptr;        // per level-node child counts / offsets (n)
+  uint32_t *bnd = nullptr;        // per level-node child boundaries, 8 each (8 n)
+  float4 *nrec = nullptr;         // walk record, 2 per node: (x,y,z,M), (b_J, a, b, leaf)
+  float4 *quad = nullptr;         // 2 per node: (xx,yy,zz,xy), (xz,yz,tr,0)
+  // groups (capacity cap_groups)
+  float4 *ball = nullptr;
+  uint32_t *gent = nullptr;       // 2 per group: node entries, particle entries
+  // sort / scan scratch
+  uint32_t *hist = nullptr;       // radix histograms
+  uint32_t *part = nullptr;       // scan partials
+  float *bbox_part = nullptr;     // bbox partials
+  // walk spill area
+  uint32_t *spill = nullptr;
+  // control
+  Ctl *ctl = nullptr;
+  Ctl *ctl_host = nullptr;        // pinned mirror for read-back
+};
+
+}  // namespace gothic
+
+struct gothic_ctx {
+  int device = 0;
+  int num_cus = 256;
+  gothic_params prm{};
+  int64_t cap_n = 0, cap_nodes = 0, cap_groups = 0, cap_hist = 0;
+  int64_t spill_per_wave = 0;
+  int walk_waves = 0;             // persistent walk waves (slots)
+  gothic::Buffers b;
+  // last evaluation
+  int64_t last_n = 0;
+  hipStream_t last_stream = nullptr;
+  bool have_last = false;
+  bool owns_event = false;
+};
+
+namespace gothic {
+
+// error plumbing (api.hip)
+int set_error(int code, const std::string &msg);
+int hip_check(hipError_t e, const char *what);
+
+// ---- launchers (one translation unit each) ----
+// scan.hip: exclusive scan of in[0..n) -> out, n = *n_dev - (*lo_dev if lo_dev)
+// (or n_host when n_dev is null); the total goes to *total_dev.
+void scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n_host, const unsigned *n_dev,
+                    const unsigned *lo_dev, int64_t n_max, unsigned *total_dev, uint32_t *part,
+                    hipStream_t s);
+int scan_blocks();
+
+// keys.hip
+void launch_bbox_keys(gothic_ctx *c, const float4 *xyzm, int64_t n, hipStream_t s);
+// sort.hip
+void launch_radix_sort(gothic_ctx *c, int64_t n, hipStream_t s);  // keyA/idxA -> keyA/idxA
+int64_t radix_hist_entries(int64_t n);
+// tree.hip
+void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active, int64_t n,
+                    hipStream_t s);
+void launch_build(gothic_ctx *c, int64_t n, hipStream_t s);
+// moments.hip
+void launch_moments(gothic_ctx *c, int64_t n, hipStream_t s);
+// groups.hip
+void launch_groups(gothic_ctx *c, int64_t n, hipStream_t s);
+// walk.hip
+void launch_walk(gothic_ctx *c, int64_t n, float eps, float theta, float4 *acc_pot,
+                 hipStream_t s);
+int walk_slots(gothic_ctx *c);
+
+}  // namespace gothic

@@ -1,0 +1,116 @@
+// Stable least-significant-digit radix sort of (63-bit key, 32-bit index)
+// pairs: the key sort of Section 2.1 (the paper uses a library radix sort;
+// this one is written for wave64).  Eight passes of 8-bit digits.  Per pass:
+//   hist:    per-tile digit counts, stored digit-major,
+//   scan:    exclusive scan of the digit-major table = global start of every
+//            (digit, tile) bucket,
+//   scatter: each tile ranks its elements stably (tile order, then wave
+//            order, then lane order) with ballot-based digit matching and
+//            writes them to their bucket.
+// Equal keys keep the order of their indices, so the result is the
+// lexicographic (key, original index) order.
+#include "common.h"
+#include "primitives.h"
+
+namespace gothic {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kPasses = 8;
+
+int64_t radix_hist_entries(int64_t n) {
+  int64_t tiles = (n + kSortTile - 1) / kSortTile;
+  return (tiles < 1 ? 1 : tiles) * kRadix;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+radix_hist_k(const uint64_t *__restrict__ keys, int64_t n, int shift, int64_t ntiles,
+             uint32_t *__restrict__ hist) {
+  __shared__ unsigned cnt[kRadix];
+  for (int t = threadIdx.x; t < kRadix; t += kSortThreads) cnt[t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t e = base + r * kSortThreads + threadIdx.x;
+    if (e < n) atomicAdd(&cnt[(unsigned)(keys[e] >> shift) & (kRadix - 1)], 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kRadix; t += kSortThreads)
+    hist[(int64_t)t * ntiles + blockIdx.x] = cnt[t];
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+radix_scatter_k(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ iin,
+                uint64_t *__restrict__ kout, uint32_t *__restrict__ iout, int64_t n, int shift,
+                int64_t ntiles, const uint32_t *__restrict__ ofs) {
+  constexpr int NW = kSortThreads / 64;
+  __shared__ unsigned gofs[kRadix];
+  __shared__ unsigned run[kRadix];
+  __shared__ unsigned wcnt[NW][kRadix];
+  for (int t = threadIdx.x; t < kRadix; t += kSortThreads) {
+    gofs[t] = ofs[(int64_t)t * ntiles + blockIdx.x];
+    run[t] = 0;
+  }
+  const int w = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortItems; ++r) {
+    for (int t = threadIdx.x; t < NW * kRadix; t += kSortThreads) (&wcnt[0][0])[t] = 0;
+    __syncthreads();
+    const int64_t e = base + r * kSortThreads + threadIdx.x;
+    const bool valid = e < n;
+    uint64_t key = valid ? kin[e] : 0;
+    uint32_t id = valid ? iin[e] : 0;
+    const unsigned d = (unsigned)(key >> shift) & (kRadix - 1);
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const unsigned long long bb = __ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    const unsigned below = lanes_below(m);
+    const unsigned cnt = (unsigned)__popcll(m);
+    if (valid && below == cnt - 1) wcnt[w][d] = cnt;
+    __syncthreads();
+    if (valid) {
+      unsigned pos = gofs[d] + run[d] + below;
+      for (int v = 0; v < w; ++v) pos += wcnt[v][d];
+      kout[pos] = key;
+      iout[pos] = id;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kRadix; t += kSortThreads) {
+      unsigned s = 0;
+      for (int v = 0; v < NW; ++v) s += wcnt[v][t];
+      run[t] += s;
+    }
+    __syncthreads();
+  }
+}
+
+void launch_radix_sort(gothic_ctx *c, int64_t n, hipStream_t s) {
+  if (n <= 1) return;
+  const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+  uint64_t *ka = c->b.keyA, *kb = c->b.keyB;
+  uint32_t *ia = c->b.idxA, *ib = c->b.idxB;
+  uint32_t *hist = c->b.hist;
+  uint32_t *ofs = c->b.hist + ntiles * kRadix;
+  for (int p = 0; p < kPasses; ++p) {
+    const int shift = p * kRadixBits;
+    hipLaunchKernelGGL(radix_hist_k, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, ka, n,
+                       shift, ntiles, hist);
+    scan_exclusive(hist, ofs, ntiles * kRadix, nullptr, nullptr, ntiles * kRadix,
+                   &c->b.ctl->scan_total, c->b.part, s);
+    hipLaunchKernelGGL(radix_scatter_k, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, ka, ia,
+                       kb, ib, n, shift, ntiles, ofs);
+    uint64_t *tk = ka; ka = kb; kb = tk;
+    uint32_t *ti = ia; ia = ib; ib = ti;
+  }
+  // an even number of passes leaves the result in keyA / idxA
+}
+
+}  // namespace gothic

@@ -1,0 +1,208 @@
+// Permutation to key order and the breadth-first octree (Section 2.1).
+//
+// A cell at level l is a run of sorted keys sharing their top 3l bits, and
+// splitting it into eight sub-cubes is cutting the run where the next 3-bit
+// digit changes.  The tree is built one level at a time, breadth first, with
+// every count on the device:
+//   count: each level-l node holding more than n_leaf particles (and above
+//          level 21) finds its child boundaries by a lock-step binary search
+//          of the seven digit changes and counts its non-empty children;
+//          other nodes become leaves;
+//   scan:  exclusive prefix sum of the child counts = serial numbers of the
+//          level-(l+1) nodes (the prefix sums of Section 2.1);
+//   write: split nodes write their children (parent order, then digit
+//          order), which is the breadth-first numbering.
+#include "common.h"
+#include "primitives.h"
+
+namespace gothic {
+
+constexpr int kBuildThreads = 256;
+constexpr unsigned kNone = 0xffffffffu;
+
+__global__ void __launch_bounds__(256)
+permute_k(const float4 *__restrict__ xyzm, const uint8_t *__restrict__ active, int64_t n,
+          const uint32_t *__restrict__ perm, float4 *__restrict__ pos, uint32_t *__restrict__ flag) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t i = perm[k];
+    pos[k] = xyzm[i];
+    flag[k] = active ? (active[i] != 0 ? 1u : 0u) : 1u;
+  }
+}
+
+void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active, int64_t n,
+                    hipStream_t s) {
+  int64_t nb = (n + 255) / 256;
+  int g = (int)(nb > 8192 ? 8192 : (nb < 1 ? 1 : nb));
+  hipLaunchKernelGGL(permute_k, dim3(g), dim3(256), 0, s, xyzm, active, n, c->b.idxA, c->b.pos,
+                     c->b.flag);
+}
+
+__global__ void build_init_k(Ctl *ctl, int64_t n, uint32_t *first, uint32_t *count,
+                             uint32_t *parent, uint8_t *level) {
+  if (threadIdx.x == 0) {
+    first[0] = 0;
+    count[0] = (uint32_t)n;
+    parent[0] = kNone;
+    level[0] = 0;
+    ctl->lvl_start[0] = 0;
+    ctl->lvl_start[1] = 1;
+    for (int l = 2; l < kMaxLevels + 2; ++l) ctl->lvl_start[l] = 1;
+    ctl->n_nodes = 1;
+  }
+}
+
+__device__ __forceinline__ unsigned digit_at(uint64_t key, int shift) {
+  return (unsigned)(key >> shift) & 7u;
+}
+
+// Count children of every level-l node; record the 7 inner boundaries.
+__global__ void __launch_bounds__(kBuildThreads)
+build_count_k(int l, int n_leaf, int64_t cap_nodes, int64_t cap_level, Ctl *ctl,
+              const uint64_t *__restrict__ ks, const uint32_t *__restrict__ first,
+              const uint32_t *__restrict__ count, uint32_t *__restrict__ child_first,
+              uint8_t *__restrict__ n_child, uint32_t *__restrict__ nch,
+              uint32_t *__restrict__ bnd) {
+  const int64_t lo = ctl->lvl_start[l];
+  int64_t hi = ctl->lvl_start[l + 1];
+  if (hi > cap_nodes) hi = cap_nodes;
+  if (hi - lo > cap_level) hi = lo + cap_level;
+  const int shift = 3 * (kNlev - 1 - l);
+  for (int64_t k = lo + (int64_t)blockIdx.x * kBuildThreads + threadIdx.x; k < hi;
+       k += (int64_t)gridDim.x * kBuildThreads) {
+    const uint32_t f = first[k], c = count[k];
+    unsigned nc = 0;
+    if (c > (uint32_t)n_leaf && l < kNlev) {
+      // lower_bound of digit >= d for d = 1..7, all searches in lock step
+      uint32_t a[8], b[8];
+#pragma unroll
+      for (int d = 1; d < 8; ++d) { a[d] = f; b[d] = f + c; }
+      for (uint32_t len = c; len > 0; len >>= 1) {
+#pragma unroll
+        for (int d = 1; d < 8; ++d) {
+          if (a[d] < b[d]) {
+            const uint32_t mid = a[d] + ((b[d] - a[d]) >> 1);
+            if (digit_at(ks[mid], shift) >= (unsigned)d) b[d] = mid; else a[d] = mid + 1;
+          }
+        }
+      }
+      // one more pass guarantees convergence for any length
+#pragma unroll
+      for (int d = 1; d < 8; ++d) {
+        while (a[d] < b[d]) {
+          const uint32_t mid = a[d] + ((b[d] - a[d]) >> 1);
+          if (digit_at(ks[mid], shift) >= (unsigned)d) b[d] = mid; else a[d] = mid + 1;
+        }
+      }
+      uint32_t prev = f;
+#pragma unroll
+      for (int d = 1; d < 8; ++d) {
+        bnd[(k - lo) * 8 + d] = a[d];
+        nc += (a[d] > prev) ? 1u : 0u;
+        prev = a[d];
+      }
+      nc += (f + c > prev) ? 1u : 0u;
+    }
+    nch[k - lo] = nc;
+    if (nc == 0) {
+      child_first[k] = 0;
+      n_child[k] = 0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBuildThreads)
+build_write_k(int l, int64_t cap_nodes, int64_t cap_level, Ctl *ctl,
+              const uint32_t *__restrict__ first,
+              const uint32_t *__restrict__ count, const uint32_t *__restrict__ ofs,
+              const uint32_t *__restrict__ bnd, uint32_t *__restrict__ child_first,
+              uint8_t *__restrict__ n_child, uint32_t *__restrict__ cfirst,
+              uint32_t *__restrict__ ccount, uint32_t *__restrict__ cparent,
+              uint8_t *__restrict__ clevel) {
+  const int64_t lo = ctl->lvl_start[l];
+  int64_t hi = ctl->lvl_start[l + 1];
+  const int64_t nxt = ctl->lvl_start[l + 1];
+  const int64_t total = ctl->scan_total;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t end = nxt + total;
+    ctl->lvl_start[l + 2] = (unsigned)(end > 0xffffffffll ? 0xffffffffll : end);
+    if (end > cap_nodes) atomicOr(&ctl->flags, kFlagNodeOverflow);
+  }
+  if (hi > cap_nodes) hi = cap_nodes;
+  if (hi - lo > cap_level) hi = lo + cap_level;
+  for (int64_t k = lo + (int64_t)blockIdx.x * kBuildThreads + threadIdx.x; k < hi;
+       k += (int64_t)gridDim.x * kBuildThreads) {
+    const uint32_t f = first[k], c = count[k];
+    // recover the non-empty children from the stored boundaries
+    const int64_t base = nxt + ofs[k - lo];
+    int made = 0;
+    {
+      uint32_t s = f;
+#pragma unroll
+      for (int d = 1; d <= 8; ++d) {
+        const uint32_t e = (d < 8) ? bnd[(k - lo) * 8 + d] : f + c;
+        if (e > s) { ++made; s = e; }
+      }
+    }
+    if (made == 0) continue;
+    if (base + made > cap_nodes) {
+      // out of node capacity: keep the tree consistent by leaving this node a
+      // leaf (flagged; the host grows the arrays and repeats the evaluation)
+      child_first[k] = 0;
+      n_child[k] = 0;
+      continue;
+    }
+    uint32_t s = f;
+    int j = 0;
+#pragma unroll
+    for (int d = 1; d <= 8; ++d) {
+      const uint32_t e = (d < 8) ? bnd[(k - lo) * 8 + d] : f + c;
+      if (e > s) {
+        cfirst[base + j] = s;
+        ccount[base + j] = e - s;
+        cparent[base + j] = (uint32_t)k;
+        clevel[base + j] = (uint8_t)(l + 1);
+        ++j;
+        s = e;
+      }
+    }
+    child_first[k] = (uint32_t)base;
+    n_child[k] = (uint8_t)made;
+  }
+}
+
+// n_nodes = end of the deepest level
+__global__ void build_final_k(Ctl *ctl, int64_t cap_nodes) {
+  if (threadIdx.x == 0) {
+    int64_t e = ctl->lvl_start[kMaxLevels];
+    ctl->n_nodes = (unsigned)(e > cap_nodes ? cap_nodes : e);
+  }
+}
+
+void launch_build(gothic_ctx *c, int64_t n, hipStream_t s) {
+  Buffers &B = c->b;
+  hipLaunchKernelGGL(build_init_k, dim3(1), dim3(64), 0, s, B.ctl, n, B.first, B.count, B.parent,
+                     B.level);
+  const int64_t cap = c->cap_nodes;
+  // grid large enough for the widest level (at most min(cap, 8^l) nodes)
+  for (int l = 0; l <= kNlev; ++l) {
+    int64_t widest = 1;
+    for (int q = 0; q < l && widest < cap; ++q) widest *= 8;
+    if (widest > cap) widest = cap;
+    int64_t nb = (widest + kBuildThreads - 1) / kBuildThreads;
+    const int g = (int)(nb > 4096 ? 4096 : (nb < 1 ? 1 : nb));
+    hipLaunchKernelGGL(build_count_k, dim3(g), dim3(kBuildThreads), 0, s, l, c->prm.n_leaf, cap,
+                       c->cap_n, B.ctl, B.keyA, B.first, B.count, B.child_first, B.n_child,
+                       B.nch, B.bnd);
+    if (l == kNlev) break;
+    scan_exclusive(B.nch, B.nch, 0, &B.ctl->lvl_start[l + 1], &B.ctl->lvl_start[l], c->cap_n,
+                   &B.ctl->scan_total, B.part, s);
+    hipLaunchKernelGGL(build_write_k, dim3(g), dim3(kBuildThreads), 0, s, l, cap, c->cap_n, B.ctl,
+                       B.first, B.count, B.nch, B.bnd, B.child_first, B.n_child, B.first,
+                       B.count, B.parent, B.level);
+  }
+  hipLaunchKernelGGL(build_final_k, dim3(1), dim3(64), 0, s, B.ctl, cap);
+}
+
+}  // namespace gothic

@@ -1,0 +1,362 @@
+// Tree walk and force (Sections 2.2, 2.3 and 2.5 of the paper).
+//
+// One wave64 walks the tree for one group of G i-particles at a time
+// (persistent waves claim groups from a device counter).  The group is
+// represented by its pseudo i-particle (r_I, b_I); a candidate pseudo
+// j-particle J is at distance d = lambda r_JI with lambda = 1 - b_I / r_JI
+// (0 when b_I >= r_JI), and is accepted when b_J <= theta d (the opening-angle
+// MAC of Barnes & Hut written without the division).  The walk is breadth
+// first: up to 64 queued nodes are tested at once, one per lane, and
+// ballot/prefix-sum compaction routes
+//   accepted nodes        -> the LDS interaction list (pseudo particles),
+//   rejected internal     -> their children to the LDS queue (global spill
+//                            when the queue is full),
+//   rejected leaves       -> their member particles to the LDS list.
+// When the list is full it is flushed: every lane accumulates the softened
+// force and potential of its i-particle from the list entries (broadcast LDS
+// reads, FP32 with the hardware reciprocal square root).  With G < 64 the
+// S = 64/G lanes sharing an i-particle take every S-th entry
+// (ij-parallelisation) and are summed at the end.  Each flush's partial sums
+// are added to the running totals with Neumaier compensation (or plainly).
+//
+// Pair terms with d = r_J - r_i, R^2 = |d|^2 + eps^2:
+//   monopole    a += M d / R^3,  phi -= M / R
+//   quadrupole  a += d (7.5 q / R^7 - 1.5 tr S / R^5) - 3 S d / R^5,
+//               phi -= 1.5 q / R^5 - 0.5 tr S / R^3,   q = d.S.d
+// (second-order Taylor term of the softened kernel about the centre of mass).
+// The self pair adds no force and m_i/eps to -phi, which is removed.
+#include "common.h"
+#include "primitives.h"
+
+namespace gothic {
+
+constexpr int kQueueCap = 1024;  // LDS frontier ring per wave (power of two)
+constexpr int kQueueMask = kQueueCap - 1;
+
+struct WalkArgs {
+  Ctl *ctl;
+  const float4 *nrec;
+  const float4 *quad;
+  const float4 *pos;
+  const uint32_t *alist;
+  const float4 *ball;
+  const uint32_t *perm;
+  float4 *out;
+  uint32_t *gent;
+  uint32_t *spill;
+  int64_t spill_cap;
+  int G, logG, D, DQ;
+  int wave_bytes;
+  int compensated;
+  float eps2, theta, inv_eps;
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void neumaier(float &sum, float &c, float x) {
+  const float t = sum + x;
+  c += (fabsf(sum) >= fabsf(x)) ? ((sum - t) + x) : ((x - t) + sum);
+  sum = t;
+}
+
+struct Acc {
+  float x, y, z, p;     // running sums (p = sum of m/R, i.e. -phi)
+  float cx, cy, cz, cp; // compensation terms
+};
+
+template <int MULTI>
+__device__ __forceinline__ void flush(const WalkArgs &a, const float4 *pl, const float4 *ql0,
+                                      const float4 *ql1, const float4 *ql2, int np, int nq,
+                                      float4 pi, int sub, int S, Acc &acc) {
+  wave_sync();
+  float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
+  const float eps2 = a.eps2;
+#pragma unroll 4
+  for (int k = sub; k < np; k += S) {
+    const float4 j = pl[k];
+    const float dx = j.x - pi.x, dy = j.y - pi.y, dz = j.z - pi.z;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float mr = j.w * ri;
+    const float mr3 = mr * ri * ri;
+    fp += mr;
+    fx = fmaf(mr3, dx, fx);
+    fy = fmaf(mr3, dy, fy);
+    fz = fmaf(mr3, dz, fz);
+  }
+  if (MULTI == 2) {
+#pragma unroll 2
+    for (int k = sub; k < nq; k += S) {
+      const float4 q0 = ql0[k], q1 = ql1[k], q2 = ql2[k];
+      const float dx = q0.x - pi.x, dy = q0.y - pi.y, dz = q0.z - pi.z;
+      const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+      const float ri = __builtin_amdgcn_rsqf(r2);
+      const float ri2 = ri * ri;
+      const float r3 = ri * ri2, r5 = r3 * ri2, r7 = r5 * ri2;
+      // S = (xx yy zz xy | xz yz tr)
+      const float sdx = fmaf(q1.x, dx, fmaf(q1.w, dy, q2.x * dz));
+      const float sdy = fmaf(q1.w, dx, fmaf(q1.y, dy, q2.y * dz));
+      const float sdz = fmaf(q2.x, dx, fmaf(q2.y, dy, q1.z * dz));
+      const float qq = fmaf(dx, sdx, fmaf(dy, sdy, dz * sdz));
+      const float tr = q2.z;
+      const float coef = fmaf(q0.w, r3, fmaf(7.5f * qq, r7, -1.5f * tr * r5));
+      const float s3 = 3.f * r5;
+      fx = fmaf(coef, dx, fmaf(-s3, sdx, fx));
+      fy = fmaf(coef, dy, fmaf(-s3, sdy, fy));
+      fz = fmaf(coef, dz, fmaf(-s3, sdz, fz));
+      fp += fmaf(q0.w, ri, fmaf(1.5f * qq, r5, -0.5f * tr * r3));
+    }
+  }
+  if (a.compensated) {
+    neumaier(acc.x, acc.cx, fx);
+    neumaier(acc.y, acc.cy, fy);
+    neumaier(acc.z, acc.cz, fz);
+    neumaier(acc.p, acc.cp, fp);
+  } else {
+    acc.x += fx; acc.y += fy; acc.z += fz; acc.p += fp;
+  }
+  wave_sync();
+}
+
+template <int MULTI>
+__global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
+  extern __shared__ float4 smem[];
+  const int w = threadIdx.x >> 6;
+  const int lane = lane_id();
+  char *wbase = reinterpret_cast<char *>(smem) + (size_t)w * a.wave_bytes;
+  float4 *pl = reinterpret_cast<float4 *>(wbase);
+  float4 *ql0 = pl + a.D;
+  float4 *ql1 = ql0 + (MULTI == 2 ? a.DQ : 0);
+  float4 *ql2 = ql1 + (MULTI == 2 ? a.DQ : 0);
+  uint32_t *queue = reinterpret_cast<uint32_t *>(ql2 + (MULTI == 2 ? a.DQ : 0));
+  uint32_t *tpre = queue + kQueueCap;
+  uint32_t *tsrc = tpre + 64;
+
+  const int64_t slot = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
+  uint32_t *spill = a.spill + slot * a.spill_cap;
+  const int G = a.G, S = 64 >> a.logG;
+  const int il = lane & (G - 1), sub = lane >> a.logG;
+  Ctl *ctl = a.ctl;
+  const unsigned ng = ctl->n_groups, na = ctl->n_active;
+  const float theta = a.theta;
+  const int D = a.D, DQ = a.DQ;
+
+  for (;;) {
+    unsigned g = 0;
+    if (lane == 0) g = atomicAdd(&ctl->work, 1u);
+    g = __shfl(g, 0, 64);
+    if (g >= ng) break;
+    const unsigned gs = g * (unsigned)G;
+    const int gc = (int)((na - gs) < (unsigned)G ? (na - gs) : (unsigned)G);
+    const float4 bl = a.ball[g];
+    const bool vi = il < gc;
+    const uint32_t ki = a.alist[gs + (vi ? il : 0)];
+    const float4 pi = a.pos[ki];
+    Acc acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int np = 0, nq = 0;
+    unsigned qh = 0, qt = 1;
+    int64_t stop = 0;
+    unsigned long long e_node = 0, e_part = 0, n_mac = 0;
+    if (lane == 0) queue[0] = 0;
+    wave_sync();
+
+    while (qt > qh || stop > 0) {
+      if (qt == qh) {  // refill the ring from the spill stack
+        const int64_t m = stop < kQueueCap ? stop : kQueueCap;
+        for (int64_t t = lane; t < m; t += 64) queue[t] = spill[stop - m + t];
+        stop -= m;
+        qh = 0;
+        qt = (unsigned)m;
+        wave_sync();
+      }
+      const unsigned nb = (qt - qh) < 64u ? (qt - qh) : 64u;
+      const bool has = (unsigned)lane < nb;
+      const unsigned node = has ? queue[(qh + lane) & kQueueMask] : 0u;
+      qh += nb;
+      n_mac += nb;
+      float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+      if (has) {
+        r0 = a.nrec[2 * (size_t)node];
+        r1 = a.nrec[2 * (size_t)node + 1];
+      }
+      const float dx = r0.x - bl.x, dy = r0.y - bl.y, dz = r0.z - bl.z;
+      const float rji = sqrtf(dx * dx + dy * dy + dz * dz);
+      const float dist = fmaxf(rji - bl.w, 0.f);
+      const bool accept = has && (r1.x <= theta * dist);
+      const bool leaf = __float_as_uint(r1.w) != 0u;
+      const bool open_leaf = has && !accept && leaf;
+      const bool open_int = has && !accept && !leaf;
+
+      // (1) accepted pseudo j-particles
+      const unsigned long long am = __ballot(accept);
+      const int nacc = __popcll(am);
+      if (nacc) {
+        if (MULTI == 1) {
+          if (np + nacc > D) {
+            flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, sub, S, acc);
+            np = 0; nq = 0;
+          }
+          if (accept) pl[np + lanes_below(am)] = r0;
+          np += nacc;
+        } else {
+          if (nq + nacc > DQ) {
+            flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, sub, S, acc);
+            np = 0; nq = 0;
+          }
+          if (accept) {
+            const int q = nq + (int)lanes_below(am);
+            ql0[q] = r0;
+            ql1[q] = a.quad[2 * (size_t)node];
+            ql2[q] = a.quad[2 * (size_t)node + 1];
+          }
+          nq += nacc;
+        }
+        e_node += (unsigned)nacc;
+      }
+
+      // (2) children of rejected internal nodes -> queue
+      const unsigned nc = open_int ? __float_as_uint(r1.z) : 0u;
+      const unsigned cf = __float_as_uint(r1.y);
+      const unsigned cinc = wave_incl_sum(nc);
+      const unsigned C = __shfl(cinc, 63, 64);
+      if (C) {
+        const unsigned pre = cinc - nc;
+        if ((qt - qh) + C <= (unsigned)kQueueCap) {
+          for (unsigned q = 0; q < nc; ++q) queue[(qt + pre + q) & kQueueMask] = cf + q;
+          qt += C;
+        } else if (stop + C <= a.spill_cap) {
+          for (unsigned q = 0; q < nc; ++q) spill[stop + pre + q] = cf + q;
+          stop += C;
+        } else if (lane == 0) {
+          atomicOr(&ctl->flags, kFlagSpillOverflow);
+        }
+        wave_sync();
+      }
+
+      // (3) member particles of rejected leaves -> list
+      const unsigned pc = open_leaf ? __float_as_uint(r1.z) : 0u;
+      const unsigned pf = __float_as_uint(r1.y);
+      const unsigned pinc = wave_incl_sum(pc);
+      const unsigned P = __shfl(pinc, 63, 64);
+      if (P) {
+        tpre[lane] = pinc - pc;
+        tsrc[lane] = pf;
+        wave_sync();
+        for (unsigned t0 = 0; t0 < P; t0 += 64) {
+          if (np + 64 > D) {
+            flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, sub, S, acc);
+            np = 0; nq = 0;
+          }
+          const unsigned t = t0 + lane;
+          if (t < P) {
+            int o = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1)
+              if (tpre[o + step] <= t) o += step;
+            pl[np + lane] = a.pos[tsrc[o] + (t - tpre[o])];
+          }
+          np += (int)((P - t0) < 64u ? (P - t0) : 64u);
+        }
+        e_part += P;
+        wave_sync();
+      }
+    }
+    flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, sub, S, acc);
+
+    float ax = acc.x + acc.cx, ay = acc.y + acc.cy, az = acc.z + acc.cz, ap = acc.p + acc.cp;
+    for (int m = G; m < 64; m <<= 1) {
+      ax += __shfl_xor(ax, m, 64);
+      ay += __shfl_xor(ay, m, 64);
+      az += __shfl_xor(az, m, 64);
+      ap += __shfl_xor(ap, m, 64);
+    }
+    if (sub == 0 && vi) a.out[a.perm[ki]] = make_float4(ax, ay, az, -ap + pi.w * a.inv_eps);
+    if (lane == 0) {
+      a.gent[2 * (size_t)g] = (uint32_t)e_node;
+      a.gent[2 * (size_t)g + 1] = (uint32_t)e_part;
+      atomicAdd(&ctl->node_entries, e_node);
+      atomicAdd(&ctl->part_entries, e_part);
+      atomicAdd(&ctl->interactions, (unsigned long long)gc * (e_node + e_part));
+      atomicAdd(&ctl->node_interactions, (unsigned long long)gc * e_node);
+      atomicAdd(&ctl->mac_tests, n_mac);
+    }
+  }
+}
+
+static int wave_bytes_for(int multi, int D, int DQ) {
+  return D * 16 + (multi == 2 ? 3 * DQ * 16 : 0) + kQueueCap * 4 + 2 * 64 * 4;
+}
+
+// LDS list sizes: monopole entries take one float4; with quadrupole nodes the
+// list budget is split between particle entries and three-float4 node entries.
+static void list_dims(int multi, int depth, int *D, int *DQ) {
+  if (multi == 2) {
+    *D = depth / 2 < 64 ? 64 : depth / 2;
+    *DQ = *D;
+  } else {
+    *D = depth;
+    *DQ = 0;
+  }
+}
+
+static int waves_per_block(int wb) {
+  int w = 65536 / wb;
+  return w >= 4 ? 4 : (w < 1 ? 1 : w);
+}
+
+int walk_slots(gothic_ctx *c) {
+  const int multi = c->prm.multipole;
+  int D, DQ;
+  list_dims(multi, c->prm.list_depth, &D, &DQ);
+  const int wb = wave_bytes_for(multi, D, DQ);
+  const int wpb = waves_per_block(wb);
+  int per_cu = 0;
+  hipError_t e;
+  if (multi == 2)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walk_k<2>, wpb * 64, wpb * wb);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walk_k<1>, wpb * 64, wpb * wb);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  return c->num_cus * per_cu * wpb;
+}
+
+void launch_walk(gothic_ctx *c, int64_t n, float eps, float theta, float4 *acc_pot,
+                 hipStream_t s) {
+  (void)n;
+  Buffers &B = c->b;
+  WalkArgs a;
+  const int multi = c->prm.multipole;
+  a.ctl = B.ctl;
+  a.nrec = B.nrec;
+  a.quad = B.quad;
+  a.pos = B.pos;
+  a.alist = B.alist;
+  a.ball = B.ball;
+  a.perm = B.idxA;
+  a.out = acc_pot;
+  a.gent = B.gent;
+  a.spill = B.spill;
+  a.spill_cap = c->spill_per_wave;
+  a.G = c->prm.group_size;
+  int lg = 0;
+  while ((1 << lg) < a.G) ++lg;
+  a.logG = lg;
+  list_dims(multi, c->prm.list_depth, &a.D, &a.DQ);
+  a.wave_bytes = wave_bytes_for(multi, a.D, a.DQ);
+  a.compensated = c->prm.compensated;
+  a.eps2 = eps * eps;
+  a.theta = theta;
+  a.inv_eps = 1.0f / eps;
+  const int wpb = waves_per_block(a.wave_bytes);
+  const int slots = c->walk_waves;
+  const int blocks = slots / wpb;
+  if (multi == 2)
+    hipLaunchKernelGGL(walk_k<2>, dim3(blocks), dim3(wpb * 64), wpb * a.wave_bytes, s, a);
+  else
+    hipLaunchKernelGGL(walk_k<1>, dim3(blocks), dim3(wpb * 64), wpb * a.wave_bytes, s, a);
+}
+
+}  // namespace gothic

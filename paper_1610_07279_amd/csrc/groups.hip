@@ -23,25 +23,26 @@ compact_k(int64_t n, int G, const uint32_t *__restrict__ flag, const uint32_t *_
     if (flag[k]) alist[ofs[k]] = (uint32_t)k;
 }
 
-// one wave per group
+// one wave per group; loop control is wave-uniform and the member load is
+// predicated (lanes past the group's end re-read its first member)
 __global__ void __launch_bounds__(256)
 group_ball_k(int G, const Ctl *__restrict__ ctl, const uint32_t *__restrict__ alist,
              const float4 *__restrict__ pos, float4 *__restrict__ ball) {
   const unsigned ng = ctl->n_groups, na = ctl->n_active;
   const int lane = lane_id();
-  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t wid = __builtin_amdgcn_readfirstlane(
+      (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t g = wid; g < ng; g += nw) {
     const int64_t s = g * G;
     const int cnt = (int)((int64_t)na - s < G ? (int64_t)na - s : G);
-    float4 p = pos[alist[s]];
-    if (lane < cnt) p = pos[alist[s + lane]];
+    const float4 p = pos[alist[s + (lane < cnt ? lane : 0)]];
     const float lx = wave_min(p.x), ly = wave_min(p.y), lz = wave_min(p.z);
     const float hx = wave_max(p.x), hy = wave_max(p.y), hz = wave_max(p.z);
     const float cx = 0.5f * (lx + hx), cy = 0.5f * (ly + hy), cz = 0.5f * (lz + hz);
     const float dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
     const float r = wave_max(sqrtf(dx * dx + dy * dy + dz * dz));
-    if (lane == 0) ball[g] = make_float4(cx, cy, cz, r * (1.0f + 4.0f * 1.1920929e-7f));
+    ball[g] = make_float4(cx, cy, cz, r * (1.0f + 4.0f * 1.1920929e-7f));  // same from all lanes
   }
 }
 

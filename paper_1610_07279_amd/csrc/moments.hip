@@ -114,45 +114,44 @@ __global__ void __launch_bounds__(256)
 radius_k(int64_t n, const float4 *__restrict__ pos, const uint32_t *__restrict__ leaf_of,
          const uint32_t *__restrict__ parent, const uint8_t *__restrict__ level,
          float4 *__restrict__ nrec) {
+  // Loop control is wave-uniform (readfirstlane) and the per-lane steps are
+  // predicated rather than branched, so every lane takes part in each shuffle.
   const int lane = lane_id();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
     const int64_t i = base + threadIdx.x;
-    unsigned node = kNone;
-    float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (i < n) {
-      p = pos[i];
-      node = parent[leaf_of[i]];
-    }
-    int lv = (node != kNone) ? (int)level[node] : -1;
+    const bool inr = i < n;
+    const int64_t ic = inr ? i : n - 1;
+    const float4 p = pos[ic];
+    const unsigned par = parent[leaf_of[ic]];
+    unsigned node = inr ? par : kNone;
+    int lv = (node != kNone) ? (int)level[node != kNone ? node : 0] : -1;
     int top = lv;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) top = max(top, __shfl_xor(top, d, 64));
+    top = __builtin_amdgcn_readfirstlane(top);
     for (int l = top; l >= 0; --l) {
       const bool part = (node != kNone) && (lv == l);
       const unsigned key = part ? node : kNone;
-      float dist = 0.f;
-      if (part) {
-        const float4 r = nrec[2 * node];
-        if (r.w > 0.f) {
-          const float dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z;
-          dist = sqrtf(dx * dx + dy * dy + dz * dz);
-        }
-      }
+      const unsigned ns = part ? node : 0u;
+      const float4 r = nrec[2 * (size_t)ns];
+      const float dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z;
+      float dist = (part && r.w > 0.f) ? sqrtf(dx * dx + dy * dy + dz * dz) : 0.f;
       // segmented max over contiguous runs of equal key
 #pragma unroll
       for (int d = 1; d < 64; d <<= 1) {
         const float od = __shfl_down(dist, d, 64);
         const unsigned ok = __shfl_down(key, d, 64);
-        if (lane + d < 64 && ok == key) dist = fmaxf(dist, od);
+        dist = (lane + d < 64 && ok == key) ? fmaxf(dist, od) : dist;
       }
       const unsigned prev = __shfl_up(key, 1, 64);
       if (part && (lane == 0 || prev != key))
-        atomicMax(reinterpret_cast<unsigned *>(&nrec[2 * node + 1].x), __float_as_uint(dist));
-      if (part) {
-        node = parent[node];
-        lv = (node != kNone) ? (int)level[node] : -1;
-      }
+        atomicMax(reinterpret_cast<unsigned *>(&nrec[2 * (size_t)node + 1].x),
+                  __float_as_uint(dist));
+      const unsigned up = parent[ns];
+      const int uplv = (up != kNone) ? (int)level[up != kNone ? up : 0] : -1;
+      node = part ? up : node;
+      lv = part ? uplv : lv;
     }
   }
 }

@@ -136,6 +136,10 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   uint32_t *tsrc = tpre + 64;
 
   const int64_t slot = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
+  // Every value that steers a loop below is wave-uniform and kept in scalar
+  // registers (readfirstlane / ballot), and no lane-dependent branch encloses
+  // a cross-lane operation inside a loop: the compiler may otherwise split the
+  // loops by lane and leave a shuffle reading an inactive lane.
   uint32_t *spill = a.spill + slot * a.spill_cap;
   const int G = a.G, S = 64 >> a.logG;
   const int il = lane & (G - 1), sub = lane >> a.logG;
@@ -144,10 +148,10 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   const float theta = a.theta;
   const int D = a.D, DQ = a.DQ;
 
+  unsigned long long t_node = 0, t_part = 0, t_int = 0, t_nint = 0, t_mac = 0;
   for (;;) {
-    unsigned g = 0;
-    if (lane == 0) g = atomicAdd(&ctl->work, 1u);
-    g = __shfl(g, 0, 64);
+    const unsigned g =
+        __builtin_amdgcn_readfirstlane(atomicAdd(&ctl->work, lane == 0 ? 1u : 0u));
     if (g >= ng) break;
     const unsigned gs = g * (unsigned)G;
     const int gc = (int)((na - gs) < (unsigned)G ? (na - gs) : (unsigned)G);
@@ -174,14 +178,12 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       }
       const unsigned nb = (qt - qh) < 64u ? (qt - qh) : 64u;
       const bool has = (unsigned)lane < nb;
-      const unsigned node = has ? queue[(qh + lane) & kQueueMask] : 0u;
+      const unsigned qv = queue[(qh + lane) & kQueueMask];
+      const unsigned node = has ? qv : 0u;  // lanes without a node read the root
       qh += nb;
       n_mac += nb;
-      float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
-      if (has) {
-        r0 = a.nrec[2 * (size_t)node];
-        r1 = a.nrec[2 * (size_t)node + 1];
-      }
+      const float4 r0 = a.nrec[2 * (size_t)node];
+      const float4 r1 = a.nrec[2 * (size_t)node + 1];
       const float dx = r0.x - bl.x, dy = r0.y - bl.y, dz = r0.z - bl.z;
       const float rji = sqrtf(dx * dx + dy * dy + dz * dz);
       const float dist = fmaxf(rji - bl.w, 0.f);
@@ -221,7 +223,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       const unsigned nc = open_int ? __float_as_uint(r1.z) : 0u;
       const unsigned cf = __float_as_uint(r1.y);
       const unsigned cinc = wave_incl_sum(nc);
-      const unsigned C = __shfl(cinc, 63, 64);
+      const unsigned C = __builtin_amdgcn_readfirstlane(__shfl(cinc, 63, 64));
       if (C) {
         const unsigned pre = cinc - nc;
         if ((qt - qh) + C <= (unsigned)kQueueCap) {
@@ -230,8 +232,8 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
         } else if (stop + C <= a.spill_cap) {
           for (unsigned q = 0; q < nc; ++q) spill[stop + pre + q] = cf + q;
           stop += C;
-        } else if (lane == 0) {
-          atomicOr(&ctl->flags, kFlagSpillOverflow);
+        } else {
+          atomicOr(&ctl->flags, kFlagSpillOverflow);  // all lanes, same bit
         }
         wave_sync();
       }
@@ -240,7 +242,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       const unsigned pc = open_leaf ? __float_as_uint(r1.z) : 0u;
       const unsigned pf = __float_as_uint(r1.y);
       const unsigned pinc = wave_incl_sum(pc);
-      const unsigned P = __shfl(pinc, 63, 64);
+      const unsigned P = __builtin_amdgcn_readfirstlane(__shfl(pinc, 63, 64));
       if (P) {
         tpre[lane] = pinc - pc;
         tsrc[lane] = pf;
@@ -274,15 +276,21 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       ap += __shfl_xor(ap, m, 64);
     }
     if (sub == 0 && vi) a.out[a.perm[ki]] = make_float4(ax, ay, az, -ap + pi.w * a.inv_eps);
-    if (lane == 0) {
-      a.gent[2 * (size_t)g] = (uint32_t)e_node;
-      a.gent[2 * (size_t)g + 1] = (uint32_t)e_part;
-      atomicAdd(&ctl->node_entries, e_node);
-      atomicAdd(&ctl->part_entries, e_part);
-      atomicAdd(&ctl->interactions, (unsigned long long)gc * (e_node + e_part));
-      atomicAdd(&ctl->node_interactions, (unsigned long long)gc * e_node);
-      atomicAdd(&ctl->mac_tests, n_mac);
-    }
+    // same value from every lane
+    a.gent[2 * (size_t)g] = (uint32_t)e_node;
+    a.gent[2 * (size_t)g + 1] = (uint32_t)e_part;
+    t_node += e_node;
+    t_part += e_part;
+    t_int += (unsigned long long)gc * (e_node + e_part);
+    t_nint += (unsigned long long)gc * e_node;
+    t_mac += n_mac;
+  }
+  if (lane == 0) {
+    atomicAdd(&ctl->node_entries, t_node);
+    atomicAdd(&ctl->part_entries, t_part);
+    atomicAdd(&ctl->interactions, t_int);
+    atomicAdd(&ctl->node_interactions, t_nint);
+    atomicAdd(&ctl->mac_tests, t_mac);
   }
 }
 

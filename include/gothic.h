@@ -45,7 +45,7 @@ typedef enum {
   GOTHIC_EINVAL = -1,     /* bad argument (n, eps, theta, pointer, parameter) */
   GOTHIC_ENOMEM = -2,     /* device allocation failed */
   GOTHIC_EDEVICE = -3,    /* a HIP call failed (message says which) */
-  GOTHIC_EOVERFLOW = -4,  /* node, frontier or list capacity exceeded twice */
+  GOTHIC_EOVERFLOW = -4,  /* node or frontier capacity still exceeded after growing */
   GOTHIC_ECAPTURE = -5,   /* scratch would have to grow during stream capture */
   GOTHIC_ENONFINITE = -6  /* NaN or Inf in the positions or masses */
 } gothic_status;
@@ -69,8 +69,14 @@ typedef struct {
                          partial sums; 0: plain FP32 (default 1) */
   int check;          /* 1: every force call synchronises its stream at the end,
                          checks the device error flags, grows scratch and
-                         repeats once on overflow; 0: fully asynchronous, flags
-                         are reported by the next gothic_get_stats() (default 1) */
+                         repeats (up to five times) on overflow; 0: fully
+                         asynchronous, flags are reported by the next
+                         gothic_get_stats() (default 1) */
+  int64_t node_capacity; /* initial size of the node arrays in nodes; 0 = from
+                         n and n_leaf (about n + 8 n / n_leaf).  Trees that do
+                         not fit are abandoned on the device, the arrays grow
+                         (at least 2x) and the evaluation repeats (check
+                         mode). */
 } gothic_params;
 
 /* Statistics of the last force evaluation (filled by gothic_get_stats). */
@@ -86,7 +92,8 @@ typedef struct {
   int64_t node_interactions; /* the part of interactions that are node terms */
   int64_t mac_tests;      /* MAC evaluations over all groups */
   int32_t flags;          /* device error flags (bit 0 non-finite input, bit 1
-                             node overflow, bit 2 frontier overflow) */
+                             node overflow, bit 2 frontier overflow, bit 3 an
+                             internal index check failed) */
   int32_t pad;
 } gothic_stats;
 

@@ -32,7 +32,7 @@ class GothicError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("key_kind", C.c_int), ("n_leaf", C.c_int), ("multipole", C.c_int),
                 ("group_size", C.c_int), ("list_depth", C.c_int), ("compensated", C.c_int),
-                ("check", C.c_int)]
+                ("check", C.c_int), ("node_capacity", C.c_int64)]
 
 
 class Stats(C.Structure):

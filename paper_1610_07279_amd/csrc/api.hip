@@ -102,6 +102,7 @@ static int validate_params(const gothic_params *p) {
   if (p->compensated != 0 && p->compensated != 1)
     return set_error(GOTHIC_EINVAL, "compensated must be 0 or 1");
   if (p->check != 0 && p->check != 1) return set_error(GOTHIC_EINVAL, "check must be 0 or 1");
+  if (p->node_capacity < 0) return set_error(GOTHIC_EINVAL, "node_capacity must be >= 0");
   return GOTHIC_OK;
 }
 
@@ -133,7 +134,7 @@ static int ensure(gothic_ctx *c, int64_t n, int64_t want_nodes, int64_t want_spi
     c->cap_groups = cn;
     c->cap_hist = hist;
   }
-  const int64_t nodes = std::max<int64_t>(want_nodes, c->cap_n + 1024);
+  const int64_t nodes = std::max<int64_t>(want_nodes, 64);
   if (nodes > c->cap_nodes) {
     if ((rc = dev_alloc(&B.first, nodes)) || (rc = dev_alloc(&B.count, nodes)) ||
         (rc = dev_alloc(&B.child_first, nodes)) || (rc = dev_alloc(&B.parent, nodes)) ||
@@ -193,6 +194,7 @@ void gothic_default_params(gothic_params *p) {
   p->list_depth = 512;
   p->compensated = 1;
   p->check = 1;
+  p->node_capacity = 0;
 }
 
 const char *gothic_last_error(void) { return g_last_error.c_str(); }
@@ -261,7 +263,10 @@ int gothic_tree_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, f
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(s, &cap);
   const bool capturing = cap != hipStreamCaptureStatusNone;
-  const int64_t want_nodes = std::max<int64_t>(c->cap_nodes, n + 1024);
+  // typical trees hold ~0.25 n nodes at n_leaf = 16 and ~2-3 n at n_leaf = 1
+  const int64_t want_nodes = std::max<int64_t>(
+      c->cap_nodes, c->prm.node_capacity > 0 ? c->prm.node_capacity
+                                              : n + 8 * (n / c->prm.n_leaf) + 1024);
   const bool must_grow = n > c->cap_n || want_nodes > c->cap_nodes || !c->b.spill ||
                          walk_slots(c) != c->walk_waves;
   if (capturing && must_grow)
@@ -274,7 +279,8 @@ int gothic_tree_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, f
   c->have_last = true;
   const float4 *x4 = reinterpret_cast<const float4 *>(xyzm);
   float4 *o4 = reinterpret_cast<float4 *>(acc_pot);
-  for (int attempt = 0; attempt < 3; ++attempt) {
+  constexpr int kAttempts = 6;
+  for (int attempt = 0; attempt < kAttempts; ++attempt) {
     if ((rc = enqueue_forces(c, n, x4, eps, theta, active, o4, s))) return rc;
     if (!c->prm.check || capturing) return GOTHIC_OK;
     if ((rc = hip_check(hipMemcpyAsync(c->b.ctl_host, c->b.ctl, sizeof(Ctl),
@@ -283,13 +289,27 @@ int gothic_tree_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, f
     if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
     const unsigned f = c->b.ctl_host->flags;
     if (f & kFlagNonFinite) return set_error(GOTHIC_ENONFINITE, "non-finite position or mass");
+    if (f & kFlagBadIndex)
+      return set_error(GOTHIC_EDEVICE, "internal index check failed (flags " + std::to_string(f) + ")");
     if (!(f & (kFlagNodeOverflow | kFlagSpillOverflow))) return GOTHIC_OK;
-    if (attempt == 2) break;
-    const int64_t nodes = (f & kFlagNodeOverflow) ? 2 * c->cap_nodes : c->cap_nodes;
+    if (attempt == kAttempts - 1) break;
+    // the abandoned level already knows how many nodes it needed at least
+    int64_t need = 0;
+    for (int l = 0; l < kMaxLevels + 1; ++l)
+      if (c->b.ctl_host->lvl_start[l] != 0xffffffffu)
+        need = std::max<int64_t>(need, c->b.ctl_host->lvl_start[l]);
+    const int64_t nodes =
+        (f & kFlagNodeOverflow) ? std::max<int64_t>(2 * c->cap_nodes, 2 * need) : c->cap_nodes;
     const int64_t spill = (f & kFlagSpillOverflow) ? 4 * c->spill_per_wave : c->spill_per_wave;
     if ((rc = ensure(c, n, nodes, spill))) return rc;
   }
-  return set_error(GOTHIC_EOVERFLOW, "node or frontier capacity still exceeded after growing");
+  const Ctl &h = *c->b.ctl_host;
+  std::string msg = "node or frontier capacity still exceeded after growing (flags " +
+                    std::to_string(h.flags) + ", nodes " + std::to_string(h.n_nodes) + " of " +
+                    std::to_string(c->cap_nodes) + ", groups " + std::to_string(h.n_groups) +
+                    ", spill/wave " + std::to_string(c->spill_per_wave) + ", level starts";
+  for (int l = 0; l < kMaxLevels + 1; ++l) msg += " " + std::to_string(h.lvl_start[l]);
+  return set_error(GOTHIC_EOVERFLOW, msg + ")");
 }
 
 int gothic_get_stats(gothic_ctx *c, gothic_stats *out) {
@@ -320,6 +340,7 @@ int gothic_get_stats(gothic_ctx *c, gothic_stats *out) {
   if (h.flags & kFlagNonFinite) return set_error(GOTHIC_ENONFINITE, "non-finite position or mass");
   if (h.flags & (kFlagNodeOverflow | kFlagSpillOverflow))
     return set_error(GOTHIC_EOVERFLOW, "capacity exceeded in the last evaluation");
+  if (h.flags & kFlagBadIndex) return set_error(GOTHIC_EDEVICE, "internal index check failed");
   return GOTHIC_OK;
 }
 

@@ -18,6 +18,7 @@ constexpr int kWave = 64;         // gfx950 wavefront width
 constexpr unsigned kFlagNonFinite = 1u;
 constexpr unsigned kFlagNodeOverflow = 2u;
 constexpr unsigned kFlagSpillOverflow = 4u;
+constexpr unsigned kFlagBadIndex = 8u;  // an index failed its range check (a bug)
 
 // Device-resident control block: every count the pipeline needs lives here so
 // no kernel launch depends on a host read-back.

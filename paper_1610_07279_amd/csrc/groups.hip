@@ -20,13 +20,16 @@ compact_k(int64_t n, int G, const uint32_t *__restrict__ flag, const uint32_t *_
   }
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * blockDim.x)
-    if (flag[k]) alist[ofs[k]] = (uint32_t)k;
+    if (flag[k]) {
+      if (ofs[k] < na) alist[ofs[k]] = (uint32_t)k;
+      else atomicOr(&ctl->flags, kFlagBadIndex);
+    }
 }
 
 // one wave per group; loop control is wave-uniform and the member load is
 // predicated (lanes past the group's end re-read its first member)
 __global__ void __launch_bounds__(256)
-group_ball_k(int G, const Ctl *__restrict__ ctl, const uint32_t *__restrict__ alist,
+group_ball_k(int G, int64_t n, const Ctl *__restrict__ ctl, const uint32_t *__restrict__ alist,
              const float4 *__restrict__ pos, float4 *__restrict__ ball) {
   const unsigned ng = ctl->n_groups, na = ctl->n_active;
   const int lane = lane_id();
@@ -36,7 +39,8 @@ group_ball_k(int G, const Ctl *__restrict__ ctl, const uint32_t *__restrict__ al
   for (int64_t g = wid; g < ng; g += nw) {
     const int64_t s = g * G;
     const int cnt = (int)((int64_t)na - s < G ? (int64_t)na - s : G);
-    const float4 p = pos[alist[s + (lane < cnt ? lane : 0)]];
+    const uint32_t ai = alist[s + (lane < cnt ? lane : 0)];
+    const float4 p = pos[ai < n ? ai : 0];
     const float lx = wave_min(p.x), ly = wave_min(p.y), lz = wave_min(p.z);
     const float hx = wave_max(p.x), hy = wave_max(p.y), hz = wave_max(p.z);
     const float cx = 0.5f * (lx + hx), cy = 0.5f * (ly + hy), cz = 0.5f * (lz + hz);
@@ -56,7 +60,7 @@ void launch_groups(gothic_ctx *c, int64_t n, hipStream_t s) {
   int64_t gmax = (n + c->prm.group_size - 1) / c->prm.group_size;
   int64_t wb = (gmax + 3) / 4;
   int gb = (int)(wb > 8192 ? 8192 : (wb < 1 ? 1 : wb));
-  hipLaunchKernelGGL(group_ball_k, dim3(gb), dim3(256), 0, s, c->prm.group_size, B.ctl, B.alist,
+  hipLaunchKernelGGL(group_ball_k, dim3(gb), dim3(256), 0, s, c->prm.group_size, n, B.ctl, B.alist,
                      B.pos, B.ball);
 }
 

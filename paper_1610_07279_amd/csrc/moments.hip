@@ -23,15 +23,20 @@ constexpr unsigned kNone = 0xffffffffu;
 __device__ __forceinline__ float u2f(unsigned u) { return __uint_as_float(u); }
 
 __global__ void __launch_bounds__(256)
-leaf_moments_k(const Ctl *__restrict__ ctl, const uint32_t *__restrict__ first,
+leaf_moments_k(Ctl *__restrict__ ctl, int64_t n, const uint32_t *__restrict__ first,
                const uint32_t *__restrict__ count, const uint8_t *__restrict__ n_child,
                const float4 *__restrict__ pos, uint32_t *__restrict__ leaf_of,
                float4 *__restrict__ nrec, float4 *__restrict__ quad, int want_quad) {
+  if (ctl->flags & kFlagNodeOverflow) return;  // incomplete tree: nothing to do
   const int64_t nn = ctl->n_nodes;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nn;
        k += (int64_t)gridDim.x * blockDim.x) {
     if (n_child[k] != 0) continue;
     const uint32_t f = first[k], c = count[k];
+    if (c == 0 || (int64_t)f + c > n) {
+      atomicOr(&ctl->flags, kFlagBadIndex);
+      continue;
+    }
     const float4 p0 = pos[f];
     float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
     for (uint32_t j = f; j < f + c; ++j) {
@@ -67,18 +72,24 @@ leaf_moments_k(const Ctl *__restrict__ ctl, const uint32_t *__restrict__ first,
 }
 
 __global__ void __launch_bounds__(256)
-internal_moments_k(int l, const Ctl *__restrict__ ctl, const uint32_t *__restrict__ child_first,
+internal_moments_k(int l, Ctl *__restrict__ ctl, const uint32_t *__restrict__ child_first,
                    const uint8_t *__restrict__ n_child, float4 *__restrict__ nrec,
                    float4 *__restrict__ quad, int want_quad) {
+  if (ctl->flags & kFlagNodeOverflow) return;
+  const int64_t hi_all = ctl->n_nodes;
   const int64_t lo = ctl->lvl_start[l];
   int64_t hi = ctl->lvl_start[l + 1];
-  if (hi > (int64_t)ctl->n_nodes) hi = ctl->n_nodes;
+  if (hi > hi_all) hi = hi_all;
   for (int64_t k = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < hi;
        k += (int64_t)gridDim.x * blockDim.x) {
     const unsigned nc = n_child[k];
     if (nc == 0) continue;
     const uint32_t cf = child_first[k];
-    const float4 r0 = nrec[2 * cf];
+    if (cf <= k || (int64_t)cf + nc > hi_all) {
+      atomicOr(&ctl->flags, kFlagBadIndex);
+      continue;
+    }
+    const float4 r0 = nrec[2 * (size_t)cf];
     float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
     for (unsigned q = 0; q < nc; ++q) {
       const float4 r = nrec[2 * (cf + q)];
@@ -111,9 +122,11 @@ internal_moments_k(int l, const Ctl *__restrict__ ctl, const uint32_t *__restric
 }
 
 __global__ void __launch_bounds__(256)
-radius_k(int64_t n, const float4 *__restrict__ pos, const uint32_t *__restrict__ leaf_of,
-         const uint32_t *__restrict__ parent, const uint8_t *__restrict__ level,
-         float4 *__restrict__ nrec) {
+radius_k(Ctl *__restrict__ ctl, int64_t n, const float4 *__restrict__ pos,
+         const uint32_t *__restrict__ leaf_of, const uint32_t *__restrict__ parent,
+         const uint8_t *__restrict__ level, float4 *__restrict__ nrec) {
+  if (ctl->flags & kFlagNodeOverflow) return;
+  const unsigned nn = ctl->n_nodes;
   // Loop control is wave-uniform (readfirstlane) and the per-lane steps are
   // predicated rather than branched, so every lane takes part in each shuffle.
   const int lane = lane_id();
@@ -123,8 +136,9 @@ radius_k(int64_t n, const float4 *__restrict__ pos, const uint32_t *__restrict__
     const bool inr = i < n;
     const int64_t ic = inr ? i : n - 1;
     const float4 p = pos[ic];
-    const unsigned par = parent[leaf_of[ic]];
-    unsigned node = inr ? par : kNone;
+    const unsigned lf = leaf_of[ic];
+    const unsigned par = lf < nn ? parent[lf] : kNone;
+    unsigned node = (inr && (par < nn)) ? par : kNone;
     int lv = (node != kNone) ? (int)level[node != kNone ? node : 0] : -1;
     int top = lv;
 #pragma unroll
@@ -148,7 +162,8 @@ radius_k(int64_t n, const float4 *__restrict__ pos, const uint32_t *__restrict__
       if (part && (lane == 0 || prev != key))
         atomicMax(reinterpret_cast<unsigned *>(&nrec[2 * (size_t)node + 1].x),
                   __float_as_uint(dist));
-      const unsigned up = parent[ns];
+      const unsigned up0 = parent[ns];
+      const unsigned up = up0 < nn ? up0 : kNone;  // the root's parent is kNone
       const int uplv = (up != kNone) ? (int)level[up != kNone ? up : 0] : -1;
       node = part ? up : node;
       lv = part ? uplv : lv;
@@ -161,7 +176,7 @@ void launch_moments(gothic_ctx *c, int64_t n, hipStream_t s) {
   const int wq = c->prm.multipole == 2 ? 1 : 0;
   int64_t nb = (c->cap_nodes + 255) / 256;
   int g = (int)(nb > 8192 ? 8192 : (nb < 1 ? 1 : nb));
-  hipLaunchKernelGGL(leaf_moments_k, dim3(g), dim3(256), 0, s, B.ctl, B.first, B.count,
+  hipLaunchKernelGGL(leaf_moments_k, dim3(g), dim3(256), 0, s, B.ctl, n, B.first, B.count,
                      B.n_child, B.pos, B.leaf_of, B.nrec, B.quad, wq);
   for (int l = kNlev - 1; l >= 0; --l) {
     int64_t widest = 1;
@@ -174,8 +189,8 @@ void launch_moments(gothic_ctx *c, int64_t n, hipStream_t s) {
   }
   int64_t pb = (n + 255) / 256;
   int gp = (int)(pb > 8192 ? 8192 : (pb < 1 ? 1 : pb));
-  hipLaunchKernelGGL(radius_k, dim3(gp), dim3(256), 0, s, n, B.pos, B.leaf_of, B.parent, B.level,
-                     B.nrec);
+  hipLaunchKernelGGL(radius_k, dim3(gp), dim3(256), 0, s, B.ctl, n, B.pos, B.leaf_of, B.parent,
+                     B.level, B.nrec);
 }
 
 }  // namespace gothic

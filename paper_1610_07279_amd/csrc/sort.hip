@@ -79,8 +79,10 @@ radix_scatter_k(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ i
     if (valid) {
       unsigned pos = gofs[d] + run[d] + below;
       for (int v = 0; v < w; ++v) pos += wcnt[v][d];
-      kout[pos] = key;
-      iout[pos] = id;
+      if (pos < n) {
+        kout[pos] = key;
+        iout[pos] = id;
+      }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < kRadix; t += kSortThreads) {

@@ -22,10 +22,15 @@ constexpr unsigned kNone = 0xffffffffu;
 
 __global__ void __launch_bounds__(256)
 permute_k(const float4 *__restrict__ xyzm, const uint8_t *__restrict__ active, int64_t n,
-          const uint32_t *__restrict__ perm, float4 *__restrict__ pos, uint32_t *__restrict__ flag) {
+          const uint32_t *__restrict__ perm, float4 *__restrict__ pos, uint32_t *__restrict__ flag,
+          Ctl *ctl) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t i = perm[k];
+    uint32_t i = perm[k];
+    if (i >= n) {
+      atomicOr(&ctl->flags, kFlagBadIndex);
+      i = 0;
+    }
     pos[k] = xyzm[i];
     flag[k] = active ? (active[i] != 0 ? 1u : 0u) : 1u;
   }
@@ -36,7 +41,7 @@ void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active, in
   int64_t nb = (n + 255) / 256;
   int g = (int)(nb > 8192 ? 8192 : (nb < 1 ? 1 : nb));
   hipLaunchKernelGGL(permute_k, dim3(g), dim3(256), 0, s, xyzm, active, n, c->b.idxA, c->b.pos,
-                     c->b.flag);
+                     c->b.flag, c->b.ctl);
 }
 
 __global__ void build_init_k(Ctl *ctl, int64_t n, uint32_t *first, uint32_t *count,
@@ -59,11 +64,12 @@ __device__ __forceinline__ unsigned digit_at(uint64_t key, int shift) {
 
 // Count children of every level-l node; record the 7 inner boundaries.
 __global__ void __launch_bounds__(kBuildThreads)
-build_count_k(int l, int n_leaf, int64_t cap_nodes, int64_t cap_level, Ctl *ctl,
+build_count_k(int l, int n_leaf, int64_t n, int64_t cap_nodes, int64_t cap_level, Ctl *ctl,
               const uint64_t *__restrict__ ks, const uint32_t *__restrict__ first,
               const uint32_t *__restrict__ count, uint32_t *__restrict__ child_first,
               uint8_t *__restrict__ n_child, uint32_t *__restrict__ nch,
               uint32_t *__restrict__ bnd) {
+  if (ctl->flags & kFlagNodeOverflow) return;  // tree abandoned; the host repeats
   const int64_t lo = ctl->lvl_start[l];
   int64_t hi = ctl->lvl_start[l + 1];
   if (hi > cap_nodes) hi = cap_nodes;
@@ -73,7 +79,9 @@ build_count_k(int l, int n_leaf, int64_t cap_nodes, int64_t cap_level, Ctl *ctl,
        k += (int64_t)gridDim.x * kBuildThreads) {
     const uint32_t f = first[k], c = count[k];
     unsigned nc = 0;
-    if (c > (uint32_t)n_leaf && l < kNlev) {
+    if ((int64_t)f + c > n) {
+      atomicOr(&ctl->flags, kFlagBadIndex);
+    } else if (c > (uint32_t)n_leaf && l < kNlev) {
       // lower_bound of digit >= d for d = 1..7, all searches in lock step
       uint32_t a[8], b[8];
 #pragma unroll
@@ -113,13 +121,14 @@ build_count_k(int l, int n_leaf, int64_t cap_nodes, int64_t cap_level, Ctl *ctl,
 }
 
 __global__ void __launch_bounds__(kBuildThreads)
-build_write_k(int l, int64_t cap_nodes, int64_t cap_level, Ctl *ctl,
+build_write_k(int l, int n_leaf, int64_t n, int64_t cap_nodes, int64_t cap_level, Ctl *ctl,
               const uint32_t *__restrict__ first,
               const uint32_t *__restrict__ count, const uint32_t *__restrict__ ofs,
               const uint32_t *__restrict__ bnd, uint32_t *__restrict__ child_first,
               uint8_t *__restrict__ n_child, uint32_t *__restrict__ cfirst,
               uint32_t *__restrict__ ccount, uint32_t *__restrict__ cparent,
               uint8_t *__restrict__ clevel) {
+  if (ctl->flags & kFlagNodeOverflow) return;
   const int64_t lo = ctl->lvl_start[l];
   int64_t hi = ctl->lvl_start[l + 1];
   const int64_t nxt = ctl->lvl_start[l + 1];
@@ -134,6 +143,8 @@ build_write_k(int l, int64_t cap_nodes, int64_t cap_level, Ctl *ctl,
   for (int64_t k = lo + (int64_t)blockIdx.x * kBuildThreads + threadIdx.x; k < hi;
        k += (int64_t)gridDim.x * kBuildThreads) {
     const uint32_t f = first[k], c = count[k];
+    // only nodes the count pass split have boundaries stored
+    if (c <= (uint32_t)n_leaf || (int64_t)f + c > n) continue;
     // recover the non-empty children from the stored boundaries
     const int64_t base = nxt + ofs[k - lo];
     int made = 0;
@@ -192,13 +203,14 @@ void launch_build(gothic_ctx *c, int64_t n, hipStream_t s) {
     if (widest > cap) widest = cap;
     int64_t nb = (widest + kBuildThreads - 1) / kBuildThreads;
     const int g = (int)(nb > 4096 ? 4096 : (nb < 1 ? 1 : nb));
-    hipLaunchKernelGGL(build_count_k, dim3(g), dim3(kBuildThreads), 0, s, l, c->prm.n_leaf, cap,
+    hipLaunchKernelGGL(build_count_k, dim3(g), dim3(kBuildThreads), 0, s, l, c->prm.n_leaf, n, cap,
                        c->cap_n, B.ctl, B.keyA, B.first, B.count, B.child_first, B.n_child,
                        B.nch, B.bnd);
     if (l == kNlev) break;
     scan_exclusive(B.nch, B.nch, 0, &B.ctl->lvl_start[l + 1], &B.ctl->lvl_start[l], c->cap_n,
                    &B.ctl->scan_total, B.part, s);
-    hipLaunchKernelGGL(build_write_k, dim3(g), dim3(kBuildThreads), 0, s, l, cap, c->cap_n, B.ctl,
+    hipLaunchKernelGGL(build_write_k, dim3(g), dim3(kBuildThreads), 0, s, l, c->prm.n_leaf, n, cap,
+                       c->cap_n, B.ctl,
                        B.first, B.count, B.nch, B.bnd, B.child_first, B.n_child, B.first,
                        B.count, B.parent, B.level);
   }

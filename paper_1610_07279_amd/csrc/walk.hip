@@ -35,6 +35,7 @@ constexpr int kQueueMask = kQueueCap - 1;
 
 struct WalkArgs {
   Ctl *ctl;
+  int64_t n;
   const float4 *nrec;
   const float4 *quad;
   const float4 *pos;
@@ -144,7 +145,8 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   const int G = a.G, S = 64 >> a.logG;
   const int il = lane & (G - 1), sub = lane >> a.logG;
   Ctl *ctl = a.ctl;
-  const unsigned ng = ctl->n_groups, na = ctl->n_active;
+  if (ctl->flags & kFlagNodeOverflow) return;  // no valid tree: the host repeats
+  const unsigned ng = ctl->n_groups, na = ctl->n_active, nn = ctl->n_nodes;
   const float theta = a.theta;
   const int D = a.D, DQ = a.DQ;
 
@@ -157,7 +159,8 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     const int gc = (int)((na - gs) < (unsigned)G ? (na - gs) : (unsigned)G);
     const float4 bl = a.ball[g];
     const bool vi = il < gc;
-    const uint32_t ki = a.alist[gs + (vi ? il : 0)];
+    const uint32_t ki0 = a.alist[gs + (vi ? il : 0)];
+    const uint32_t ki = ki0 < a.n ? ki0 : 0u;
     const float4 pi = a.pos[ki];
     Acc acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int np = 0, nq = 0;
@@ -167,8 +170,13 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     if (lane == 0) queue[0] = 0;
     wave_sync();
 
-    while (qt > qh || stop > 0) {
+    // a valid walk pops every node at most once; the bound only guards
+    // against a corrupted tree
+    unsigned long long pops = 0;
+    while ((qt > qh || stop > 0) && pops <= (unsigned long long)nn) {
       if (qt == qh) {  // refill the ring from the spill stack
+        // the spill entries were written by other lanes of this wave
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
         const int64_t m = stop < kQueueCap ? stop : kQueueCap;
         for (int64_t t = lane; t < m; t += 64) queue[t] = spill[stop - m + t];
         stop -= m;
@@ -179,18 +187,21 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       const unsigned nb = (qt - qh) < 64u ? (qt - qh) : 64u;
       const bool has = (unsigned)lane < nb;
       const unsigned qv = queue[(qh + lane) & kQueueMask];
-      const unsigned node = has ? qv : 0u;  // lanes without a node read the root
+      // lanes without a node read the root; an entry past the node count
+      // (never produced by a valid tree) is dropped the same way
+      const unsigned node = (has && qv < nn) ? qv : 0u;
       qh += nb;
       n_mac += nb;
+      pops += nb;
       const float4 r0 = a.nrec[2 * (size_t)node];
       const float4 r1 = a.nrec[2 * (size_t)node + 1];
       const float dx = r0.x - bl.x, dy = r0.y - bl.y, dz = r0.z - bl.z;
       const float rji = sqrtf(dx * dx + dy * dy + dz * dz);
       const float dist = fmaxf(rji - bl.w, 0.f);
-      const bool accept = has && (r1.x <= theta * dist);
+      const bool accept = has && qv < nn && (r1.x <= theta * dist);
       const bool leaf = __float_as_uint(r1.w) != 0u;
-      const bool open_leaf = has && !accept && leaf;
-      const bool open_int = has && !accept && !leaf;
+      const bool open_leaf = has && qv < nn && !accept && leaf;
+      const bool open_int = has && qv < nn && !accept && !leaf;
 
       // (1) accepted pseudo j-particles
       const unsigned long long am = __ballot(accept);
@@ -258,7 +269,8 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
 #pragma unroll
             for (int step = 32; step >= 1; step >>= 1)
               if (tpre[o + step] <= t) o += step;
-            pl[np + lane] = a.pos[tsrc[o] + (t - tpre[o])];
+            const uint32_t src = tsrc[o] + (t - tpre[o]);
+            pl[np + lane] = a.pos[src < a.n ? src : 0u];
           }
           np += (int)((P - t0) < 64u ? (P - t0) : 64u);
         }
@@ -266,6 +278,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
         wave_sync();
       }
     }
+    if (pops > (unsigned long long)nn) atomicOr(&ctl->flags, kFlagBadIndex);
     flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, sub, S, acc);
 
     float ax = acc.x + acc.cx, ay = acc.y + acc.cy, az = acc.z + acc.cz, ap = acc.p + acc.cp;
@@ -275,7 +288,9 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       az += __shfl_xor(az, m, 64);
       ap += __shfl_xor(ap, m, 64);
     }
-    if (sub == 0 && vi) a.out[a.perm[ki]] = make_float4(ax, ay, az, -ap + pi.w * a.inv_eps);
+    const uint32_t dst = a.perm[ki];
+    if (sub == 0 && vi && ki0 < a.n && dst < a.n)
+      a.out[dst] = make_float4(ax, ay, az, -ap + pi.w * a.inv_eps);
     // same value from every lane
     a.gent[2 * (size_t)g] = (uint32_t)e_node;
     a.gent[2 * (size_t)g + 1] = (uint32_t)e_part;
@@ -333,11 +348,11 @@ int walk_slots(gothic_ctx *c) {
 
 void launch_walk(gothic_ctx *c, int64_t n, float eps, float theta, float4 *acc_pot,
                  hipStream_t s) {
-  (void)n;
   Buffers &B = c->b;
   WalkArgs a;
   const int multi = c->prm.multipole;
   a.ctl = B.ctl;
+  a.n = n;
   a.nrec = B.nrec;
   a.quad = B.quad;
   a.pos = B.pos;

@@ -167,6 +167,17 @@ def test_active_subsets(frac):
     _check_forces(x, 1 / 128, 0.5, active=ics.random_active(30000, frac, seed=17))
 
 
+def test_node_capacity_overflow_grows_and_repeats():
+    # a deliberately tiny node array: the first tree is abandoned on the
+    # device (no kernel touches the partial tree), the host grows the arrays
+    # and repeats until the tree fits
+    x = ics.nfw(3000, seed=22)
+    ctx, out = run_gpu(x, 1 / 128, 0.5, n_leaf=4, node_capacity=256)
+    ref = oracle.tree_forces(x, 1 / 128, 0.5, n_leaf=4)
+    assert rel_rms(out, ref["acc_pot"]) <= 1e-5
+    assert ctx.stats()["n_nodes"] == ref["tree"]["first"].size
+
+
 def test_no_active_particles():
     x = ics.plummer(1000, seed=18)
     ctx, out = run_gpu(x, 1 / 64, 0.5, active=np.zeros(1000, np.uint8))

@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the block-step tree gravity on one MI355X.
+
+Workload (the headline configuration): NFW sphere, N = 2^24 equal-mass
+particles (r_s = 1, c = 10, truncated at 10 r_s, mass 1, seed 501), eps =
+1/512, opening angle 0.5 with quadrupole pseudo j-particles, float32 forces and
+float64 integration, time steps 0.1 sqrt(eps/|a|) on 8 levels below the
+finest.  Inputs are synthetic (seeded generator), resident on the GPU before
+timing.
+
+One "step" is one finest sub-step of the block scheme: predict every
+particle, build keys / sort / octree / moments, walk the groups of the
+particles due at that time, correct them and assign new levels.  The same
+number of shared steps (every particle at the finest step, leap-frog) is timed
+for the block-versus-shared comparison.
+
+Printed JSON line: value = interactions per second over the timed block steps
+(interactions = list entries x i-particles), ms_per_step = block seconds per
+sub-step; plus the shared-step figures, the walk-kernel roofline (FP32 VALU,
+HIP events around every walk launch) and the float64 CPU oracle's rate on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32, 256 CU x 2.4 GHz x 256 flop/clk
+FLOP_MONO = 24                    # per monopole interaction (20 + rsqrt weighted 4)
+FLOP_QUAD = 65                    # per quadrupole node interaction (count of the kernel's ops)
+METRIC = "s/step + interactions/s, NFW 2^24 block vs shared step; % FP32 VALU peak"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, shared, steps, warmup):
+    import torch
+    pos = pos0.clone()
+    vel = vel0.clone()
+    ctx.set_params(check=1)
+    ctx.sim_bind(pos, vel, mass, eps, theta, eta=eta, kmax=kmax, shared=shared)
+    for _ in range(warmup):      # first steps in check mode grow any scratch
+        ctx.sim_step()
+    ctx.set_params(check=0)
+    torch.cuda.synchronize()
+    ctx.sim_reset_counters()
+    ctx.walk_time()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.sim_step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    info = ctx.sim_info()
+    walk_ms, launches = ctx.walk_time()
+    st = ctx.stats()
+    if st["flags"]:
+        raise RuntimeError(f"device flags {st['flags']} set during the timed steps")
+    return dict(seconds=t1 - t0, info=info, walk_ms=walk_ms, walk_launches=launches)
+
+
+def cpu_baseline(x, eps, theta, multipole, group_size, n_leaf, target_s=15.0):
+    """The float64 oracle walk on a random sample of the groups of the same
+    all-active system (its tree preparation is not timed)."""
+    import oracle
+    t0 = time.perf_counter()
+    k, _ = oracle.keys(x, 0)
+    ks, perm = oracle.sort(k)
+    tree = oracle.build(ks, n_leaf)
+    ps = x[perm].astype(np.float64)
+    mom = oracle.moments(tree, ps)
+    grp = oracle.groups(np.ones(x.shape[0], np.uint8), ps, group_size)
+    prep = time.perf_counter() - t0
+    ng = grp["first"].size
+    rng = np.random.default_rng(7)
+    nsel, spent, inter, done = 32, 0.0, 0, 0
+    while spent < target_s and done < ng:
+        sel = rng.choice(ng, size=min(nsel, ng), replace=False)
+        t = time.perf_counter()
+        _, cnt, _ = oracle.walk(tree, mom, ps, grp, eps, theta, multipole, gsel=sel)
+        spent += time.perf_counter() - t
+        inter += int(((cnt[sel, 0] + cnt[sel, 1]) * grp["count"][sel]).sum())
+        done += sel.size
+        nsel *= 2
+    return dict(value=inter / spent, unit="interactions/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"float64 oracle walk of {done} random groups ({group_size} i-particles "
+                       f"each) of the all-active step, {inter:.3e} interactions in {spent:.1f} s; "
+                       f"tree preparation ({prep:.1f} s) not timed")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=32)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 24)
+    ap.add_argument("--group-size", type=int, default=32)
+    ap.add_argument("--list-depth", type=int, default=384)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-shared", action="store_true", help="skip the shared-step run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+              "multi-GPU design is described but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import ics
+    import paper_1610_07279_amd as g
+
+    n, eps, theta, eta, kmax, multipole = args.n, 1.0 / 512, 0.5, 0.1, 8, 2
+    log(f"bench: generating NFW N={n} (seed 501)")
+    x, v = ics.nfw(n, seed=501, with_vel=True)
+    dev = torch.device("cuda", 0)
+    pos0 = torch.from_numpy(x[:, :3].astype(np.float64)).to(dev)
+    vel0 = torch.from_numpy(v).to(dev)
+    mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).to(dev)
+    ctx = g.Context(device=0, multipole=multipole, group_size=args.group_size,
+                    list_depth=args.list_depth, timing=1)
+
+    log(f"bench: block steps (warmup {args.warmup}, timed {args.steps})")
+    blk = run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, False, args.steps, args.warmup)
+    log(f"bench: block {blk['seconds'] / args.steps * 1e3:.2f} ms/step, "
+        f"{blk['info']['interactions_total'] / blk['seconds']:.3e} interactions/s, levels "
+        f"{[c for c in blk['info']['level_count'] if c]}")
+    shd = None
+    if not args.no_shared:
+        log("bench: shared steps")
+        shd = run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, True, args.steps, args.warmup)
+        log(f"bench: shared {shd['seconds'] / args.steps * 1e3:.2f} ms/step")
+
+    ib = blk["info"]
+    inter = ib["interactions_total"]
+    quad = ib["node_interactions_total"]
+    flops = FLOP_MONO * (inter - quad) + FLOP_QUAD * quad
+    walk_s = blk["walk_ms"] / 1e3
+    achieved = flops / walk_s / 1e12 if walk_s > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": inter / blk["seconds"],
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": blk["seconds"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"NFW sphere N={n}, c=10, eps=1/512, theta=0.5 quadrupole, "
+                               f"block steps kmax=8 (eta=0.1), finest sub-steps",
+                   "n": n, "group_size": args.group_size, "list_depth": args.list_depth,
+                   "parallelism": "single GPU"},
+        "block": {"s_per_step": blk["seconds"] / args.steps,
+                  "interactions_per_s": inter / blk["seconds"],
+                  "active_per_step": ib["active_total"] / args.steps,
+                  "level_count": ib["level_count"][:kmax + 1],
+                  "walk_ms_per_step": blk["walk_ms"] / max(blk["walk_launches"], 1)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "walk_k<2>", "flops_per_interaction": {"mono": FLOP_MONO,
+                                                                       "quad": FLOP_QUAD}},
+    }
+    if shd is not None:
+        inter_s = shd["info"]["interactions_total"]
+        out["shared"] = {"s_per_step": shd["seconds"] / args.steps,
+                         "interactions_per_s": inter_s / shd["seconds"],
+                         "walk_ms_per_step": shd["walk_ms"] / max(shd["walk_launches"], 1)}
+        out["speedup_block_vs_shared"] = shd["seconds"] / blk["seconds"]
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(x, eps, theta, multipole, args.group_size, 16)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

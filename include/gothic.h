@@ -63,8 +63,11 @@ typedef struct {
                          2 = monopole + quadrupole node terms (extension) */
   int group_size;     /* G: i-particles per group sharing one walk; a power of
                          two in 1..64 (default 32) */
-  int list_depth;     /* capacity of the per-wave LDS interaction list in
-                         entries, a multiple of 64 in 64..1024 (default 512) */
+  int list_depth;     /* per-wave LDS interaction-list budget in 16-byte slots,
+                         a multiple of 64 in 64..1024 (default 384): monopole
+                         entries take one slot; with quadrupole nodes half the
+                         budget holds particles and half holds node entries
+                         (three slots each) */
   int compensated;    /* 1: Neumaier-compensated accumulation of the per-flush
                          partial sums; 0: plain FP32 (default 1) */
   int check;          /* 1: every force call synchronises its stream at the end,
@@ -72,6 +75,14 @@ typedef struct {
                          repeats (up to five times) on overflow; 0: fully
                          asynchronous, flags are reported by the next
                          gothic_get_stats() (default 1) */
+  int timing;         /* 1: record HIP events around every walk launch on the
+                         call's stream; gothic_get_walk_time() sums them
+                         (default 0) */
+  float r_crit;       /* critical separation of Section 2.4: two consecutive
+                         active particles (key order) farther apart than r_crit
+                         never share a group; > 0 absolute length, 0 = no split,
+                         < 0 a fraction of the key-cube side L (default -1/16,
+                         i.e. L/16) */
   int64_t node_capacity; /* initial size of the node arrays in nodes; 0 = from
                          n and n_leaf (about n + 8 n / n_leaf).  Trees that do
                          not fit are abandoned on the device, the arrays grow
@@ -141,6 +152,51 @@ int gothic_tree_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, f
 int gothic_tree_forces_batched(gothic_ctx *c, int nsys, const int64_t *offsets,
                                const float *xyzm, const float *eps, const float *theta,
                                const uint8_t *active, float *acc_pot, void *stream);
+
+/* Sum of the walk-kernel durations recorded since the previous call (timing
+ * = 1; up to 4096 launches are kept), in milliseconds, and their number.
+ * Synchronises on the recorded events. */
+int gothic_get_walk_time(gothic_ctx *c, double *ms_total, int64_t *launches);
+
+/*
+ * Block time-step driver (Section 2.7): RK2 predictor for every particle,
+ * tree forces for the particles due at the new time, RK2 corrector and new
+ * time levels for them, all on the device in float64 (forces in float32).
+ * Readings (the paper gives no criterion): dt_i = eta sqrt(eps / |a_i|);
+ * steps dt_max / 2^k, k = 0..kmax; dt_fine = largest power of two <= min dt_i
+ * at t = 0 and dt_max = dt_fine 2^kmax; a particle takes the coarsest level
+ * whose step fits; it may move to any finer level after a correction and one
+ * level coarser when the sub-step is a multiple of that coarser step.
+ *   pos, vel   [n][3] double DEVICE arrays owned by the caller, updated in
+ *              place (each particle holds its state at its last update time)
+ *   mass       [n] float DEVICE array (masses >= 0)
+ *   shared_step  1: every particle on the finest level every sub-step (the
+ *              scheme is then the leap-frog of the paper's shared-step runs)
+ * gothic_sim_bind computes the t = 0 forces and levels and synchronises.
+ * gothic_sim_step advances one finest sub-step and is asynchronous (check
+ * mode synchronises inside the force evaluation).  The arrays must stay
+ * valid until the next bind or gothic_destroy.
+ */
+typedef struct {
+  int64_t n;
+  int64_t substep;             /* finest sub-steps since t = 0 */
+  double t, dt_fine, dt_max;
+  int64_t steps;               /* sub-steps since bind or the last counter reset */
+  int64_t last_active;         /* due particles of the last sub-step */
+  int64_t active_total;        /* summed over the counted sub-steps */
+  int64_t interactions_total;  /* list entries x i-particles, summed likewise */
+  int64_t node_interactions_total;
+  int64_t level_count[32];     /* particles per level now */
+} gothic_sim_info;
+
+int gothic_sim_bind(gothic_ctx *c, int64_t n, double *pos, double *vel, const float *mass,
+                    float eps, float theta, double eta, int kmax, int shared_step, void *stream);
+int gothic_sim_step(gothic_ctx *c, void *stream);
+int gothic_sim_reset_counters(gothic_ctx *c, void *stream);
+int gothic_sim_get_info(gothic_ctx *c, gothic_sim_info *out);
+/* acc_pot [n][4] float (last forces), levels [n] uint8, last [n] int64 (sub-step
+ * of each particle's last update): caller DEVICE buffers, NULL skips. */
+int gothic_sim_get_state(gothic_ctx *c, float *acc_pot, uint8_t *levels, int64_t *last);
 
 /* Counts of the last evaluation; synchronises the stream of that call. */
 int gothic_get_stats(gothic_ctx *c, gothic_stats *out);

@@ -49,7 +49,7 @@ def _load():
     lib.orc_build.argtypes = [i64, P, i32, i64, P, P, P, P, P]
     lib.orc_moments.argtypes = [i64, P, P, P, P, P, P]
     lib.orc_groups.restype = i64
-    lib.orc_groups.argtypes = [i64, P, P, i32, P, P, P, P]
+    lib.orc_groups.argtypes = [i64, P, P, i32, f64, P, P, P, P]
     lib.orc_walk.argtypes = [i64, P, P, P, P, P, P, P, P, P, i64, P, P, P,
                              f64, f64, i32, f64, f64, P, i64, P, P, P]
     _lib = lib
@@ -130,16 +130,18 @@ def moments(tree, ps: np.ndarray):
     return com, b, S
 
 
-def groups(act_sorted: np.ndarray, ps: np.ndarray, G: int):
+def groups(act_sorted: np.ndarray, ps: np.ndarray, G: int, r_crit: float = 0.0):
+    """r_crit: critical separation (Section 2.4); pass the float32 value the
+    library uses, e.g. float(np.float32(r)); <= 0 disables the gap split."""
     n = act_sorted.size
     act_sorted = np.ascontiguousarray(act_sorted, dtype=np.uint8)
     alist = np.zeros(max(n, 1), np.uint32)
-    gmax = max(1, (n + G - 1) // G)
+    gmax = max(1, n)
     gfirst = np.zeros(gmax, np.uint32)
     gcount = np.zeros(gmax, np.uint32)
     ball = np.zeros((gmax, 4), np.float64)
-    ng = _load().orc_groups(n, _p(act_sorted), _p(ps), G, _p(alist), _p(gfirst), _p(gcount),
-                            _p(ball))
+    ng = _load().orc_groups(n, _p(act_sorted), _p(ps), G, float(r_crit), _p(alist), _p(gfirst),
+                            _p(gcount), _p(ball))
     na = int(act_sorted.sum())
     return dict(alist=alist[:na].copy(), first=gfirst[:ng].copy(), count=gcount[:ng].copy(),
                 ball=ball[:ng].copy())
@@ -166,9 +168,10 @@ def walk(tree, mom, ps, grp, eps, theta, multipole=1, tie_rel=1e-5, tie_abs=0.0,
 
 
 def tree_forces(xyzm, eps, theta, active=None, n_leaf=16, group_size=32, multipole=1,
-                key_kind=0, tie_rel=1e-5, tie_abs=0.0, gsel=None):
+                key_kind=0, tie_rel=1e-5, tie_abs=0.0, gsel=None, r_crit=-0.0625):
     """All steps of the method in float64; acc_pot is [n,4] in the caller's
-    order (NaN rows for inactive particles)."""
+    order (NaN rows for inactive particles).  r_crit < 0 is a fraction of the
+    key-cube side (the library's convention); 0 disables the gap split."""
     xyzm = np.ascontiguousarray(xyzm, dtype=np.float32)
     n = xyzm.shape[0]
     k, cb = keys(xyzm, key_kind)
@@ -177,7 +180,10 @@ def tree_forces(xyzm, eps, theta, active=None, n_leaf=16, group_size=32, multipo
     ps = xyzm[perm].astype(np.float64)
     mom = moments(tree, ps)
     act = np.ones(n, np.uint8) if active is None else np.asarray(active, np.uint8)
-    grp = groups(act[perm], ps, group_size)
+    rc = float(np.float32(r_crit))
+    if rc < 0:
+        rc = -rc * float(cb[3])
+    grp = groups(act[perm], ps, group_size, rc)
     out_sorted, cnt, mass = walk(tree, mom, ps, grp, eps, theta, multipole, tie_rel, tie_abs,
                                  gsel)
     acc = np.full((n, 4), np.nan, np.float64)

@@ -292,22 +292,38 @@ void orc_moments(int64_t nn, const uint32_t *first, const uint32_t *count,
 }
 
 /* ---------------------------------------------------------------------- */
-/* Groups (Section 2.3 with the reading of fixed chunks): the active particles
- * in key order, cut into runs of at most G consecutive ones.  Each group gets
- * a pseudo i-particle: the geometric centre of its bounding box r_I and the
- * radius b_I = max |r_i - r_I| (GEO ball, Appendix B).
+/* Groups (Sections 2.3-2.4): the active particles in key order.  Following
+ * Section 2.4, two consecutive active particles farther apart than the
+ * critical separation r_crit are never put in the same group (r_crit <= 0:
+ * no such split); each run between such gaps is cut into groups of at most G
+ * consecutive particles.  The gap test compares the float64 squared distance
+ * of the (float32) positions with r_crit^2.  Each group gets a pseudo
+ * i-particle: the geometric centre of its bounding box r_I and the radius
+ * b_I = max |r_i - r_I| (GEO ball, Appendix B).
  * act_sorted[k] = active flag of sorted particle k.  Outputs: alist (sorted
  * indices of active particles), gfirst/gcount into alist, ball[4g..] = r_I, b_I.
  * Returns the number of groups.                                              */
 int64_t orc_groups(int64_t n, const uint8_t *act_sorted, const double *ps, int G,
-                   uint32_t *alist, uint32_t *gfirst, uint32_t *gcount, double *ball) {
+                   double r_crit, uint32_t *alist, uint32_t *gfirst, uint32_t *gcount,
+                   double *ball) {
   int64_t na = 0;
   for (int64_t k = 0; k < n; ++k)
     if (act_sorted[k]) alist[na++] = (uint32_t)k;
-  const int64_t ng = (na + G - 1) / G;
+  int64_t ng = 0, run_start = 0;
+  for (int64_t a = 0; a < na; ++a) {
+    int brk = (a == 0);
+    if (!brk && r_crit > 0) {
+      const double *p = ps + 4 * (int64_t)alist[a], *q = ps + 4 * (int64_t)alist[a - 1];
+      const double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+      brk = (dx * dx + dy * dy + dz * dz) > r_crit * r_crit;
+    }
+    if (brk) run_start = a;
+    if ((a - run_start) % G == 0) gfirst[ng++] = (uint32_t)a;
+  }
+  for (int64_t g = 0; g < ng; ++g)
+    gcount[g] = (uint32_t)((g + 1 < ng ? gfirst[g + 1] : na) - gfirst[g]);
   for (int64_t g = 0; g < ng; ++g) {
-    const int64_t s = g * G, e = (s + G < na) ? s + G : na;
-    gfirst[g] = (uint32_t)s; gcount[g] = (uint32_t)(e - s);
+    const int64_t s = gfirst[g], e = s + gcount[g];
     double lo[3], hi[3];
     for (int a = 0; a < 3; ++a) lo[a] = hi[a] = ps[4 * (int64_t)alist[s] + a];
     for (int64_t q = s; q < e; ++q)

@@ -32,7 +32,8 @@ class GothicError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("key_kind", C.c_int), ("n_leaf", C.c_int), ("multipole", C.c_int),
                 ("group_size", C.c_int), ("list_depth", C.c_int), ("compensated", C.c_int),
-                ("check", C.c_int), ("node_capacity", C.c_int64)]
+                ("check", C.c_int), ("timing", C.c_int), ("r_crit", C.c_float),
+                ("node_capacity", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -44,6 +45,19 @@ class Stats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+class SimInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("substep", C.c_int64), ("t", C.c_double),
+                ("dt_fine", C.c_double), ("dt_max", C.c_double), ("steps", C.c_int64),
+                ("last_active", C.c_int64), ("active_total", C.c_int64),
+                ("interactions_total", C.c_int64), ("node_interactions_total", C.c_int64),
+                ("level_count", C.c_int64 * 32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "level_count"}
+        d["level_count"] = list(self.level_count)
+        return d
 
 
 def _load():
@@ -66,9 +80,17 @@ def _load():
     lib.gothic_get_tree.argtypes = [P, P, P, P, P, P]
     lib.gothic_get_nodes.argtypes = [P, P, P, P]
     lib.gothic_get_groups.argtypes = [P, P, P, P, P, P]
+    lib.gothic_get_walk_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64)]
+    lib.gothic_sim_bind.argtypes = [P, i64, P, P, P, f32, f32, C.c_double, i32, i32, P]
+    lib.gothic_sim_step.argtypes = [P, P]
+    lib.gothic_sim_reset_counters.argtypes = [P, P]
+    lib.gothic_sim_get_info.argtypes = [P, C.POINTER(SimInfo)]
+    lib.gothic_sim_get_state.argtypes = [P, P, P, P]
     for name in ("gothic_create", "gothic_destroy", "gothic_set_params", "gothic_get_params",
                  "gothic_tree_forces", "gothic_tree_forces_batched", "gothic_get_stats",
-                 "gothic_get_keys", "gothic_get_tree", "gothic_get_nodes", "gothic_get_groups"):
+                 "gothic_get_keys", "gothic_get_tree", "gothic_get_nodes", "gothic_get_groups",
+                 "gothic_get_walk_time", "gothic_sim_bind", "gothic_sim_step",
+                 "gothic_sim_reset_counters", "gothic_sim_get_info", "gothic_sim_get_state"):
         getattr(lib, name).restype = i32
     return lib
 
@@ -113,7 +135,7 @@ class Context:
         for k, v in params.items():
             if not hasattr(p, k):
                 raise TypeError(f"unknown parameter {k}")
-            setattr(p, k, int(v))
+            setattr(p, k, float(v) if k == "r_crit" else int(v))
         h = C.c_void_p()
         _check(lib.gothic_create(C.byref(h), int(device), C.byref(p)))
         self._h = h
@@ -144,7 +166,7 @@ class Context:
         for k, v in params.items():
             if not hasattr(p, k):
                 raise TypeError(f"unknown parameter {k}")
-            setattr(p, k, int(v))
+            setattr(p, k, float(v) if k == "r_crit" else int(v))
         _check(lib.gothic_set_params(self._h, C.byref(p)))
 
     # ---------------------------------------------------------------- forces
@@ -186,6 +208,52 @@ class Context:
             e.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p), _ptr(active), _ptr(out),
             s))
         return out
+
+    # ---------------------------------------------------------------- block steps
+    def sim_bind(self, pos, vel, mass, eps, theta, eta=0.1, kmax=8, shared=False, stream=None):
+        """Bind float64 [n,3] pos/vel and float32 [n] mass (GPU tensors, updated in
+        place by sim_step) and compute the t = 0 forces and levels."""
+        import torch
+        n = pos.shape[0]
+        for t, dt, shp in ((pos, torch.float64, (n, 3)), (vel, torch.float64, (n, 3)),
+                           (mass, torch.float32, (n,))):
+            if t.dtype != dt or tuple(t.shape) != shp or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("pos/vel must be float64 [n,3], mass float32 [n], contiguous GPU")
+        self._sim_keep = (pos, vel, mass)
+        s = _stream_of(pos, stream)
+        self._last_stream = s
+        _check(lib.gothic_sim_bind(self._h, n, _ptr(pos), _ptr(vel), _ptr(mass), float(eps),
+                                   float(theta), float(eta), int(kmax), int(bool(shared)), s))
+
+    def sim_step(self, nsteps: int = 1, stream=None):
+        s = _stream_of(self._sim_keep[0], stream)
+        for _ in range(nsteps):
+            _check(lib.gothic_sim_step(self._h, s))
+
+    def sim_reset_counters(self, stream=None):
+        _check(lib.gothic_sim_reset_counters(self._h, _stream_of(self._sim_keep[0], stream)))
+
+    def sim_info(self) -> dict:
+        info = SimInfo()
+        _check(lib.gothic_sim_get_info(self._h, C.byref(info)))
+        return info.as_dict()
+
+    def sim_state(self):
+        """(acc_pot [n,4] float32, levels [n] uint8, last sub-step [n] int64) as numpy"""
+        import torch
+        n = self._sim_keep[0].shape[0]
+        dev = self._sim_keep[0].device
+        a = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        lv = torch.empty(n, dtype=torch.uint8, device=dev)
+        last = torch.empty(n, dtype=torch.int64, device=dev)
+        _check(lib.gothic_sim_get_state(self._h, _ptr(a), _ptr(lv), _ptr(last)))
+        return a.cpu().numpy(), lv.cpu().numpy(), last.cpu().numpy()
+
+    def walk_time(self):
+        """(total ms, launches) of the walk kernels timed since the last call."""
+        ms, k = C.c_double(), C.c_int64()
+        _check(lib.gothic_get_walk_time(self._h, C.byref(ms), C.byref(k)))
+        return ms.value, k.value
 
     # ---------------------------------------------------------------- introspection
     def stats(self) -> dict:

@@ -52,12 +52,12 @@ __global__ void extract_nodes_k(const Ctl *ctl, const float4 *nrec, const float4
   }
 }
 
-__global__ void extract_groups_k(const Ctl *ctl, int G, uint32_t *gfirst, uint32_t *gcount) {
-  const unsigned ng = ctl->n_groups, na = ctl->n_active;
+__global__ void extract_groups_k(const Ctl *ctl, const uint32_t *gf, uint32_t *gfirst,
+                                 uint32_t *gcount) {
+  const unsigned ng = ctl->n_groups;
   for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += gridDim.x * blockDim.x) {
-    const unsigned s = g * (unsigned)G;
-    if (gfirst) gfirst[g] = s;
-    if (gcount) gcount[g] = (na - s) < (unsigned)G ? (na - s) : (unsigned)G;
+    if (gfirst) gfirst[g] = gf[g];
+    if (gcount) gcount[g] = gf[g + 1] - gf[g];
   }
 }
 
@@ -79,6 +79,7 @@ static int dev_alloc(T **p, int64_t count) {
 static void free_all(gothic_ctx *c) {
   Buffers &B = c->b;
   void *ptrs[] = {B.keyA, B.keyB, B.idxA, B.idxB, B.pos, B.leaf_of, B.flag, B.flag2, B.alist,
+                  B.gA, B.gB, B.gfirst,
                   B.first, B.count, B.child_first, B.parent, B.n_child, B.level, B.nch, B.bnd,
                   B.nrec, B.quad, B.ball, B.gent, B.hist, B.part, B.bbox_part, B.spill, B.ctl};
   for (void *p : ptrs)
@@ -103,6 +104,8 @@ static int validate_params(const gothic_params *p) {
     return set_error(GOTHIC_EINVAL, "compensated must be 0 or 1");
   if (p->check != 0 && p->check != 1) return set_error(GOTHIC_EINVAL, "check must be 0 or 1");
   if (p->node_capacity < 0) return set_error(GOTHIC_EINVAL, "node_capacity must be >= 0");
+  if (p->timing != 0 && p->timing != 1) return set_error(GOTHIC_EINVAL, "timing must be 0 or 1");
+  if (!std::isfinite(p->r_crit)) return set_error(GOTHIC_EINVAL, "r_crit must be finite");
   return GOTHIC_OK;
 }
 
@@ -125,6 +128,8 @@ static int ensure(gothic_ctx *c, int64_t n, int64_t want_nodes, int64_t want_spi
         (rc = dev_alloc(&B.pos, cn)) || (rc = dev_alloc(&B.leaf_of, cn)) ||
         (rc = dev_alloc(&B.flag, cn)) || (rc = dev_alloc(&B.flag2, cn)) ||
         (rc = dev_alloc(&B.alist, cn)) || (rc = dev_alloc(&B.nch, cn + 1)) ||
+        (rc = dev_alloc(&B.gA, cn + 1)) || (rc = dev_alloc(&B.gB, cn + 1)) ||
+        (rc = dev_alloc(&B.gfirst, cn + 1)) ||
         (rc = dev_alloc(&B.bnd, 8 * cn + 8)) || (rc = dev_alloc(&B.ball, cn)) ||
         (rc = dev_alloc(&B.gent, 2 * cn)))
       return rc;
@@ -175,8 +180,101 @@ static int enqueue_forces(gothic_ctx *c, int64_t n, const float4 *xyzm, float ep
   launch_build(c, n, s);
   launch_moments(c, n, s);
   launch_groups(c, n, s);
+  const bool timed = c->prm.timing && c->ev_used < (int)c->ev_start.size();
+  if (timed) (void)hipEventRecord(c->ev_start[c->ev_used], s);
   launch_walk(c, n, eps, theta, out, s);
+  if (timed) (void)hipEventRecord(c->ev_stop[c->ev_used++], s);
   return hip_check(hipGetLastError(), "kernel launch");
+}
+
+static void free_events(gothic_ctx *c) {
+  for (auto e : c->ev_start) (void)hipEventDestroy(e);
+  for (auto e : c->ev_stop) (void)hipEventDestroy(e);
+  c->ev_start.clear();
+  c->ev_stop.clear();
+  c->ev_used = 0;
+}
+
+static int ensure_events(gothic_ctx *c) {
+  constexpr int kPool = 4096;
+  if (!c->prm.timing || !c->ev_start.empty()) return GOTHIC_OK;
+  c->ev_start.resize(kPool);
+  c->ev_stop.resize(kPool);
+  for (int i = 0; i < kPool; ++i) {
+    int rc;
+    if ((rc = hip_check(hipEventCreate(&c->ev_start[i]), "hipEventCreate")) ||
+        (rc = hip_check(hipEventCreate(&c->ev_stop[i]), "hipEventCreate"))) {
+      c->ev_start.resize(i);
+      c->ev_stop.resize(i);
+      return rc;
+    }
+  }
+  return GOTHIC_OK;
+}
+
+static void free_sim(gothic_ctx *c) {
+  SimState &S = c->sim;
+  void *ptrs[] = {S.shadow, S.aold, S.anew, S.si, S.lev, S.act, S.sc};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (S.sc_host) (void)hipHostFree(S.sc_host);
+  S = SimState();
+}
+
+// The force pipeline with argument checks done: capacity, enqueue, and in
+// check mode the synchronous flag check with grow-and-repeat.
+static int run_forces(gothic_ctx *c, int64_t n, const float4 *x4, float eps, float theta,
+                      const uint8_t *active, float4 *o4, hipStream_t s) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(s, &cap);
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  // typical trees hold ~0.25 n nodes at n_leaf = 16 and ~2-3 n at n_leaf = 1
+  const int64_t want_nodes = std::max<int64_t>(
+      c->cap_nodes, c->prm.node_capacity > 0 ? c->prm.node_capacity
+                                              : n + 8 * (n / c->prm.n_leaf) + 1024);
+  const bool must_grow = n > c->cap_n || want_nodes > c->cap_nodes || !c->b.spill ||
+                         walk_slots(c) != c->walk_waves ||
+                         (c->prm.timing && c->ev_start.empty());
+  if (capturing && must_grow)
+    return set_error(GOTHIC_ECAPTURE, "scratch must grow for n = " + std::to_string(n) +
+                                          "; make one uncaptured call of this size first");
+  int rc = ensure(c, n, want_nodes, c->spill_per_wave);
+  if (rc) return rc;
+  if ((rc = ensure_events(c))) return rc;
+  c->last_n = n;
+  c->last_stream = s;
+  c->have_last = true;
+  constexpr int kAttempts = 6;
+  for (int attempt = 0; attempt < kAttempts; ++attempt) {
+    if ((rc = enqueue_forces(c, n, x4, eps, theta, active, o4, s))) return rc;
+    if (!c->prm.check || capturing) return GOTHIC_OK;
+    if ((rc = hip_check(hipMemcpyAsync(c->b.ctl_host, c->b.ctl, sizeof(Ctl),
+                                       hipMemcpyDeviceToHost, s), "hipMemcpyAsync")))
+      return rc;
+    if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
+    const unsigned f = c->b.ctl_host->flags;
+    if (f & kFlagNonFinite) return set_error(GOTHIC_ENONFINITE, "non-finite position or mass");
+    if (f & kFlagBadIndex)
+      return set_error(GOTHIC_EDEVICE, "internal index check failed (flags " + std::to_string(f) + ")");
+    if (!(f & (kFlagNodeOverflow | kFlagSpillOverflow))) return GOTHIC_OK;
+    if (attempt == kAttempts - 1) break;
+    // the abandoned level already knows how many nodes it needed at least
+    int64_t need = 0;
+    for (int l = 0; l < kMaxLevels + 1; ++l)
+      if (c->b.ctl_host->lvl_start[l] != 0xffffffffu)
+        need = std::max<int64_t>(need, c->b.ctl_host->lvl_start[l]);
+    const int64_t nodes =
+        (f & kFlagNodeOverflow) ? std::max<int64_t>(2 * c->cap_nodes, 2 * need) : c->cap_nodes;
+    const int64_t spill = (f & kFlagSpillOverflow) ? 4 * c->spill_per_wave : c->spill_per_wave;
+    if ((rc = ensure(c, n, nodes, spill))) return rc;
+  }
+  const Ctl &h = *c->b.ctl_host;
+  std::string msg = "node or frontier capacity still exceeded after growing (flags " +
+                    std::to_string(h.flags) + ", nodes " + std::to_string(h.n_nodes) + " of " +
+                    std::to_string(c->cap_nodes) + ", groups " + std::to_string(h.n_groups) +
+                    ", spill/wave " + std::to_string(c->spill_per_wave) + ", level starts";
+  for (int l = 0; l < kMaxLevels + 1; ++l) msg += " " + std::to_string(h.lvl_start[l]);
+  return set_error(GOTHIC_EOVERFLOW, msg + ")");
 }
 
 }  // namespace gothic
@@ -191,9 +289,11 @@ void gothic_default_params(gothic_params *p) {
   p->n_leaf = 16;
   p->multipole = 1;
   p->group_size = 32;
-  p->list_depth = 512;
+  p->list_depth = 384;
   p->compensated = 1;
   p->check = 1;
+  p->timing = 0;
+  p->r_crit = -0.0625f;
   p->node_capacity = 0;
 }
 
@@ -228,6 +328,8 @@ int gothic_destroy(gothic_ctx *c) {
   {
     DeviceGuard guard(c->device);
     (void)hipDeviceSynchronize();
+    free_sim(c);
+    free_events(c);
     free_all(c);
   }
   delete c;
@@ -259,57 +361,8 @@ int gothic_tree_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, f
   if ((const void *)xyzm == (const void *)acc_pot)
     return set_error(GOTHIC_EINVAL, "xyzm and acc_pot must not overlap");
   DeviceGuard guard(c->device);
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  (void)hipStreamIsCapturing(s, &cap);
-  const bool capturing = cap != hipStreamCaptureStatusNone;
-  // typical trees hold ~0.25 n nodes at n_leaf = 16 and ~2-3 n at n_leaf = 1
-  const int64_t want_nodes = std::max<int64_t>(
-      c->cap_nodes, c->prm.node_capacity > 0 ? c->prm.node_capacity
-                                              : n + 8 * (n / c->prm.n_leaf) + 1024);
-  const bool must_grow = n > c->cap_n || want_nodes > c->cap_nodes || !c->b.spill ||
-                         walk_slots(c) != c->walk_waves;
-  if (capturing && must_grow)
-    return set_error(GOTHIC_ECAPTURE, "scratch must grow for n = " + std::to_string(n) +
-                                          "; make one uncaptured call of this size first");
-  int rc = ensure(c, n, want_nodes, c->spill_per_wave);
-  if (rc) return rc;
-  c->last_n = n;
-  c->last_stream = s;
-  c->have_last = true;
-  const float4 *x4 = reinterpret_cast<const float4 *>(xyzm);
-  float4 *o4 = reinterpret_cast<float4 *>(acc_pot);
-  constexpr int kAttempts = 6;
-  for (int attempt = 0; attempt < kAttempts; ++attempt) {
-    if ((rc = enqueue_forces(c, n, x4, eps, theta, active, o4, s))) return rc;
-    if (!c->prm.check || capturing) return GOTHIC_OK;
-    if ((rc = hip_check(hipMemcpyAsync(c->b.ctl_host, c->b.ctl, sizeof(Ctl),
-                                       hipMemcpyDeviceToHost, s), "hipMemcpyAsync")))
-      return rc;
-    if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
-    const unsigned f = c->b.ctl_host->flags;
-    if (f & kFlagNonFinite) return set_error(GOTHIC_ENONFINITE, "non-finite position or mass");
-    if (f & kFlagBadIndex)
-      return set_error(GOTHIC_EDEVICE, "internal index check failed (flags " + std::to_string(f) + ")");
-    if (!(f & (kFlagNodeOverflow | kFlagSpillOverflow))) return GOTHIC_OK;
-    if (attempt == kAttempts - 1) break;
-    // the abandoned level already knows how many nodes it needed at least
-    int64_t need = 0;
-    for (int l = 0; l < kMaxLevels + 1; ++l)
-      if (c->b.ctl_host->lvl_start[l] != 0xffffffffu)
-        need = std::max<int64_t>(need, c->b.ctl_host->lvl_start[l]);
-    const int64_t nodes =
-        (f & kFlagNodeOverflow) ? std::max<int64_t>(2 * c->cap_nodes, 2 * need) : c->cap_nodes;
-    const int64_t spill = (f & kFlagSpillOverflow) ? 4 * c->spill_per_wave : c->spill_per_wave;
-    if ((rc = ensure(c, n, nodes, spill))) return rc;
-  }
-  const Ctl &h = *c->b.ctl_host;
-  std::string msg = "node or frontier capacity still exceeded after growing (flags " +
-                    std::to_string(h.flags) + ", nodes " + std::to_string(h.n_nodes) + " of " +
-                    std::to_string(c->cap_nodes) + ", groups " + std::to_string(h.n_groups) +
-                    ", spill/wave " + std::to_string(c->spill_per_wave) + ", level starts";
-  for (int l = 0; l < kMaxLevels + 1; ++l) msg += " " + std::to_string(h.lvl_start[l]);
-  return set_error(GOTHIC_EOVERFLOW, msg + ")");
+  return run_forces(c, n, reinterpret_cast<const float4 *>(xyzm), eps, theta, active,
+                    reinterpret_cast<float4 *>(acc_pot), reinterpret_cast<hipStream_t>(stream));
 }
 
 int gothic_get_stats(gothic_ctx *c, gothic_stats *out) {
@@ -416,10 +469,140 @@ int gothic_get_groups(gothic_ctx *c, uint32_t *alist, uint32_t *gfirst, uint32_t
       (rc = d2d(entries, c->b.gent, (size_t)h.n_groups * 8, s)))
     return rc;
   if (gfirst || gcount) {
-    hipLaunchKernelGGL(extract_groups_k, dim3(256), dim3(256), 0, s, c->b.ctl, c->prm.group_size,
+    hipLaunchKernelGGL(extract_groups_k, dim3(256), dim3(256), 0, s, c->b.ctl, c->b.gfirst,
                        gfirst, gcount);
     if ((rc = hip_check(hipGetLastError(), "extract_groups_k"))) return rc;
   }
+  return hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+int gothic_get_walk_time(gothic_ctx *c, double *ms_total, int64_t *launches) {
+  if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
+  DeviceGuard guard(c->device);
+  double tot = 0.0;
+  for (int i = 0; i < c->ev_used; ++i) {
+    int rc;
+    if ((rc = hip_check(hipEventSynchronize(c->ev_stop[i]), "hipEventSynchronize"))) return rc;
+    float ms = 0.f;
+    if ((rc = hip_check(hipEventElapsedTime(&ms, c->ev_start[i], c->ev_stop[i]),
+                        "hipEventElapsedTime")))
+      return rc;
+    tot += ms;
+  }
+  if (ms_total) *ms_total = tot;
+  if (launches) *launches = c->ev_used;
+  c->ev_used = 0;
+  return GOTHIC_OK;
+}
+
+int gothic_sim_bind(gothic_ctx *c, int64_t n, double *pos, double *vel, const float *mass,
+                    float eps, float theta, double eta, int kmax, int shared_step, void *stream) {
+  if (!c) return set_error(GOTHIC_EINVAL, "context is NULL");
+  if (n <= 0 || n >= (int64_t)1 << 31) return set_error(GOTHIC_EINVAL, "n must be in [1, 2^31)");
+  if (!pos || !vel || !mass) return set_error(GOTHIC_EINVAL, "pos, vel and mass must not be NULL");
+  if (!(eps > 0.f) || !std::isfinite(eps)) return set_error(GOTHIC_EINVAL, "eps must be finite and > 0");
+  if (!(theta >= 0.f && theta < 1.f)) return set_error(GOTHIC_EINVAL, "theta must be in [0, 1)");
+  if (!(eta > 0.0) || !std::isfinite(eta)) return set_error(GOTHIC_EINVAL, "eta must be finite and > 0");
+  if (kmax < 0 || kmax > 30) return set_error(GOTHIC_EINVAL, "kmax must be in 0..30");
+  DeviceGuard guard(c->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  SimState &S = c->sim;
+  int rc;
+  if (n > S.cap || !S.sc) {
+    free_sim(c);
+    if ((rc = dev_alloc(&S.shadow, n)) || (rc = dev_alloc(&S.aold, n)) ||
+        (rc = dev_alloc(&S.anew, n)) || (rc = dev_alloc(&S.si, n)) ||
+        (rc = dev_alloc(&S.lev, n)) || (rc = dev_alloc(&S.act, n)) ||
+        (rc = dev_alloc(&S.sc, 1)))
+      return rc;
+    if ((rc = hip_check(hipHostMalloc(reinterpret_cast<void **>(&S.sc_host), sizeof(SimCtl),
+                                      hipHostMallocDefault), "hipHostMalloc")))
+      return rc;
+    S.cap = n;
+  }
+  S.n = n;
+  S.pos = pos;
+  S.vel = vel;
+  S.mass = mass;
+  S.eps = eps;
+  S.theta = theta;
+  sim_launch_setup(c, s, eps, eta, kmax, shared_step ? 1 : 0);
+  sim_launch_reset(c, s);
+  sim_launch_shadow(c, s);
+  if ((rc = hip_check(hipGetLastError(), "kernel launch"))) return rc;
+  // t = 0 forces on every particle (synchronous, checked)
+  const int saved = c->prm.check;
+  c->prm.check = 1;
+  rc = run_forces(c, n, S.shadow, eps, theta, nullptr, S.anew, s);
+  c->prm.check = saved;
+  if (rc) return rc;
+  sim_launch_init(c, s);
+  sim_launch_reset(c, s);
+  if ((rc = hip_check(hipGetLastError(), "kernel launch"))) return rc;
+  if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
+  S.bound = true;
+  return GOTHIC_OK;
+}
+
+int gothic_sim_step(gothic_ctx *c, void *stream) {
+  if (!c) return set_error(GOTHIC_EINVAL, "context is NULL");
+  SimState &S = c->sim;
+  if (!S.bound) return set_error(GOTHIC_EINVAL, "no system bound (gothic_sim_bind)");
+  DeviceGuard guard(c->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  sim_launch_predict(c, s);
+  int rc = run_forces(c, S.n, S.shadow, S.eps, S.theta, S.act, S.anew, s);
+  if (rc) return rc;
+  sim_launch_correct(c, s);
+  return hip_check(hipGetLastError(), "kernel launch");
+}
+
+int gothic_sim_reset_counters(gothic_ctx *c, void *stream) {
+  if (!c) return set_error(GOTHIC_EINVAL, "context is NULL");
+  if (!c->sim.bound) return set_error(GOTHIC_EINVAL, "no system bound (gothic_sim_bind)");
+  DeviceGuard guard(c->device);
+  sim_launch_reset(c, reinterpret_cast<hipStream_t>(stream));
+  return hip_check(hipGetLastError(), "kernel launch");
+}
+
+int gothic_sim_get_info(gothic_ctx *c, gothic_sim_info *out) {
+  if (!c || !out) return set_error(GOTHIC_EINVAL, "NULL argument");
+  SimState &S = c->sim;
+  if (!S.bound) return set_error(GOTHIC_EINVAL, "no system bound (gothic_sim_bind)");
+  DeviceGuard guard(c->device);
+  hipStream_t s = c->last_stream;
+  sim_launch_hist(c, s);
+  int rc;
+  if ((rc = hip_check(hipMemcpyAsync(S.sc_host, S.sc, sizeof(SimCtl), hipMemcpyDeviceToHost, s),
+                      "hipMemcpyAsync")) ||
+      (rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize")))
+    return rc;
+  const SimCtl &h = *S.sc_host;
+  memset(out, 0, sizeof(*out));
+  out->n = S.n;
+  out->substep = h.s;
+  out->dt_fine = h.dt_fine;
+  out->dt_max = h.dt_max;
+  out->t = (double)h.s * h.dt_fine;
+  out->steps = (int64_t)h.steps;
+  out->last_active = (int64_t)h.last_active;
+  out->active_total = (int64_t)h.active_total;
+  out->interactions_total = (int64_t)h.inter_total;
+  out->node_interactions_total = (int64_t)h.node_inter_total;
+  for (int k = 0; k < 32; ++k) out->level_count[k] = (int64_t)h.level_count[k];
+  return GOTHIC_OK;
+}
+
+int gothic_sim_get_state(gothic_ctx *c, float *acc_pot, uint8_t *levels, int64_t *last) {
+  if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
+  SimState &S = c->sim;
+  if (!S.bound) return set_error(GOTHIC_EINVAL, "no system bound (gothic_sim_bind)");
+  DeviceGuard guard(c->device);
+  hipStream_t s = c->last_stream;
+  int rc;
+  if ((rc = d2d(acc_pot, S.aold, (size_t)S.n * 16, s)) || (rc = d2d(levels, S.lev, (size_t)S.n, s)) ||
+      (rc = d2d(last, S.si, (size_t)S.n * 8, s)))
+    return rc;
   return hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 

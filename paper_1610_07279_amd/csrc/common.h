@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/gothic.h"
 
@@ -28,7 +29,8 @@ struct Ctl {
   unsigned n_active;
   unsigned n_groups;
   unsigned lvl_start[kMaxLevels + 2];  // nodes of level l: [lvl_start[l], lvl_start[l+1])
-  unsigned work;                       // persistent-walk group counter
+  unsigned work;                       // (unused; kept for layout stability)
+  unsigned xwork[8];                   // per-XCD group counters of the persistent walk
   unsigned scan_total;                 // scratch: total of the last scan
   unsigned pad0, pad1;
   double cube[4];                      // x_min, y_min, z_min, L
@@ -48,6 +50,8 @@ struct Buffers {
   uint32_t *flag = nullptr;       // active flag of each key-ordered particle (n)
   uint32_t *flag2 = nullptr;      // scan output scratch (n)
   uint32_t *alist = nullptr;      // key-order indices of active particles
+  uint32_t *gA = nullptr, *gB = nullptr;  // group-formation scratch (n)
+  uint32_t *gfirst = nullptr;     // first active index of each group, [n_groups + 1]
   // nodes (capacity cap_nodes)
   uint32_t *first = nullptr, *count = nullptr, *child_first = nullptr, *parent = nullptr;
   uint8_t *n_child = nullptr, *level = nullptr;
@@ -69,6 +73,29 @@ struct Buffers {
   Ctl *ctl_host = nullptr;        // pinned mirror for read-back
 };
 
+// Block-step driver state on the device (sim.hip)
+struct SimCtl {
+  long long s;                  // current finest sub-step
+  double dt_fine, dt_max, eps, eta;
+  int kmax, shared;
+  unsigned long long min_dt_bits;
+  unsigned long long n_active;  // due particles of the step in progress
+  unsigned long long last_active, steps, inter_total, node_inter_total, active_total;
+  unsigned long long level_count[32];
+};
+
+struct SimState {
+  bool bound = false;
+  int64_t n = 0, cap = 0;
+  double *pos = nullptr, *vel = nullptr;  // caller-owned, float64 [n][3]
+  const float *mass = nullptr;            // caller-owned [n]
+  float eps = 0.f, theta = 0.f;
+  float4 *shadow = nullptr, *aold = nullptr, *anew = nullptr;
+  int64_t *si = nullptr;
+  uint8_t *lev = nullptr, *act = nullptr;
+  SimCtl *sc = nullptr, *sc_host = nullptr;
+};
+
 }  // namespace gothic
 
 struct gothic_ctx {
@@ -83,7 +110,10 @@ struct gothic_ctx {
   int64_t last_n = 0;
   hipStream_t last_stream = nullptr;
   bool have_last = false;
-  bool owns_event = false;
+  // walk-kernel timing (params.timing): event pairs recorded around each walk
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  int ev_used = 0;
+  gothic::SimState sim;
 };
 
 namespace gothic {
@@ -117,5 +147,13 @@ void launch_groups(gothic_ctx *c, int64_t n, hipStream_t s);
 void launch_walk(gothic_ctx *c, int64_t n, float eps, float theta, float4 *acc_pot,
                  hipStream_t s);
 int walk_slots(gothic_ctx *c);
+// sim.hip
+void sim_launch_setup(gothic_ctx *c, hipStream_t s, double eps, double eta, int kmax, int shared);
+void sim_launch_reset(gothic_ctx *c, hipStream_t s);
+void sim_launch_shadow(gothic_ctx *c, hipStream_t s);
+void sim_launch_init(gothic_ctx *c, hipStream_t s);
+void sim_launch_predict(gothic_ctx *c, hipStream_t s);
+void sim_launch_correct(gothic_ctx *c, hipStream_t s);
+void sim_launch_hist(gothic_ctx *c, hipStream_t s);
 
 }  // namespace gothic

@@ -1,10 +1,13 @@
-// Active i-particles and their groups (Section 2.3; block time steps,
-// Section 2.7).  The active particles are compacted in key order, cut into
-// groups of G consecutive ones, and each group gets its pseudo i-particle:
-// the geometric centre r_I of the group's bounding box and the radius b_I of
-// the sphere about r_I that holds every member (the GEO ball of Appendix B).
-// b_I is computed in FP32 and widened by a few ulp so the sphere provably
-// holds the members despite rounding.
+// Active i-particles and their groups (Sections 2.3-2.4; block time steps,
+// Section 2.7).  The active particles are compacted in key order.  Following
+// Section 2.4, consecutive active particles farther apart than the critical
+// separation r_crit start a new group (the squared gap is compared with
+// r_crit^2 in float64 without fused operations, so the bounds are exact and
+// reproducible); every run between such gaps is cut into groups of at most G.
+// Each group gets its pseudo i-particle: the geometric centre r_I of the
+// group's bounding box and the radius b_I of the sphere about r_I that holds
+// every member (the GEO ball of Appendix B).  b_I is computed in FP32 and
+// widened by a few ulp so the sphere provably holds the members.
 #include "common.h"
 #include "primitives.h"
 
@@ -14,10 +17,8 @@ __global__ void __launch_bounds__(256)
 compact_k(int64_t n, int G, const uint32_t *__restrict__ flag, const uint32_t *__restrict__ ofs,
           uint32_t *__restrict__ alist, Ctl *ctl) {
   const unsigned na = ctl->scan_total;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->n_active = na;
-    ctl->n_groups = (na + (unsigned)G - 1) / (unsigned)G;
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->n_active = na;
+  (void)G;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * blockDim.x)
     if (flag[k]) {
@@ -26,19 +27,85 @@ compact_k(int64_t n, int G, const uint32_t *__restrict__ flag, const uint32_t *_
     }
 }
 
+__device__ __forceinline__ double gap2(float4 p, float4 q) {
+  const double dx = __dsub_rn((double)p.x, (double)q.x);
+  const double dy = __dsub_rn((double)p.y, (double)q.y);
+  const double dz = __dsub_rn((double)p.z, (double)q.z);
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+// brk[a] = 1 where a new run starts (first active particle or a gap > r_crit)
+__global__ void __launch_bounds__(256)
+group_breaks_k(int64_t n, float r_crit, const Ctl *__restrict__ ctl,
+               const uint32_t *__restrict__ alist, const float4 *__restrict__ pos,
+               uint32_t *__restrict__ brk) {
+  const unsigned na = ctl->n_active;
+  const double rc = r_crit < 0.f ? (double)(-r_crit) * ctl->cube[3] : (double)r_crit;
+  const double rc2 = __dmul_rn(rc, rc);
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < na;
+       a += (int64_t)gridDim.x * blockDim.x) {
+    unsigned b = (a == 0);
+    if (!b && rc > 0.0) {
+      const uint32_t i = alist[a], j = alist[a - 1];
+      b = (i < n && j < n) ? (gap2(pos[i], pos[j]) > rc2) : 1u;
+    }
+    brk[a] = b;
+  }
+}
+
+// run starts: runpos[run id] = a
+__global__ void __launch_bounds__(256)
+group_runs_k(const Ctl *__restrict__ ctl, const uint32_t *__restrict__ brk,
+             const uint32_t *__restrict__ runx, uint32_t *__restrict__ runpos) {
+  const unsigned na = ctl->n_active;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < na;
+       a += (int64_t)gridDim.x * blockDim.x)
+    if (brk[a]) runpos[runx[a]] = (uint32_t)a;
+}
+
+// gflag[a] = 1 where a group starts: every G-th particle of its run
+__global__ void __launch_bounds__(256)
+group_starts_k(int G, Ctl *__restrict__ ctl, const uint32_t *__restrict__ brk,
+               const uint32_t *__restrict__ runx, const uint32_t *__restrict__ runpos,
+               uint32_t *__restrict__ gflag) {
+  const unsigned na = ctl->n_active;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < na;
+       a += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t run = runx[a] + brk[a] - 1u;  // inclusive count - 1
+    const uint32_t rs = runpos[run];
+    gflag[a] = (rs <= a && ((uint32_t)a - rs) % (uint32_t)G == 0u) ? 1u : 0u;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+group_first_k(Ctl *__restrict__ ctl, const uint32_t *__restrict__ gflag,
+              const uint32_t *__restrict__ gidx, uint32_t *__restrict__ gfirst) {
+  const unsigned na = ctl->n_active, ng = ctl->scan_total;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->n_groups = ng;
+    gfirst[ng] = na;
+  }
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < na;
+       a += (int64_t)gridDim.x * blockDim.x)
+    if (gflag[a]) gfirst[gidx[a]] = (uint32_t)a;
+}
+
 // one wave per group; loop control is wave-uniform and the member load is
 // predicated (lanes past the group's end re-read its first member)
 __global__ void __launch_bounds__(256)
-group_ball_k(int G, int64_t n, const Ctl *__restrict__ ctl, const uint32_t *__restrict__ alist,
-             const float4 *__restrict__ pos, float4 *__restrict__ ball) {
+group_ball_k(int64_t n, const Ctl *__restrict__ ctl, const uint32_t *__restrict__ alist,
+             const uint32_t *__restrict__ gfirst, const float4 *__restrict__ pos,
+             float4 *__restrict__ ball) {
   const unsigned ng = ctl->n_groups, na = ctl->n_active;
   const int lane = lane_id();
   const int64_t wid = __builtin_amdgcn_readfirstlane(
       (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t g = wid; g < ng; g += nw) {
-    const int64_t s = g * G;
-    const int cnt = (int)((int64_t)na - s < G ? (int64_t)na - s : G);
+    const int64_t s = gfirst[g];
+    const int64_t e = gfirst[g + 1];
+    const int cnt = (int)(e - s < 64 ? (e > s ? e - s : 1) : 64);
+    (void)na;
     const uint32_t ai = alist[s + (lane < cnt ? lane : 0)];
     const float4 p = pos[ai < n ? ai : 0];
     const float lx = wave_min(p.x), ly = wave_min(p.y), lz = wave_min(p.z);
@@ -52,16 +119,26 @@ group_ball_k(int G, int64_t n, const Ctl *__restrict__ ctl, const uint32_t *__re
 
 void launch_groups(gothic_ctx *c, int64_t n, hipStream_t s) {
   Buffers &B = c->b;
+  const unsigned *na_dev = &B.ctl->n_active;
   scan_exclusive(B.flag, B.flag2, n, nullptr, nullptr, n, &B.ctl->scan_total, B.part, s);
   int64_t nb = (n + 255) / 256;
   int g = (int)(nb > 8192 ? 8192 : (nb < 1 ? 1 : nb));
   hipLaunchKernelGGL(compact_k, dim3(g), dim3(256), 0, s, n, c->prm.group_size, B.flag, B.flag2,
                      B.alist, B.ctl);
-  int64_t gmax = (n + c->prm.group_size - 1) / c->prm.group_size;
-  int64_t wb = (gmax + 3) / 4;
+  // runs between gaps > r_crit (flag: run breaks, flag2: run index, gA: run starts)
+  hipLaunchKernelGGL(group_breaks_k, dim3(g), dim3(256), 0, s, n, c->prm.r_crit, B.ctl, B.alist,
+                     B.pos, B.flag);
+  scan_exclusive(B.flag, B.flag2, 0, na_dev, nullptr, n, &B.ctl->scan_total, B.part, s);
+  hipLaunchKernelGGL(group_runs_k, dim3(g), dim3(256), 0, s, B.ctl, B.flag, B.flag2, B.gA);
+  // groups: every G-th particle of a run starts one (gB: starts, flag: group index)
+  hipLaunchKernelGGL(group_starts_k, dim3(g), dim3(256), 0, s, c->prm.group_size, B.ctl, B.flag,
+                     B.flag2, B.gA, B.gB);
+  scan_exclusive(B.gB, B.flag, 0, na_dev, nullptr, n, &B.ctl->scan_total, B.part, s);
+  hipLaunchKernelGGL(group_first_k, dim3(g), dim3(256), 0, s, B.ctl, B.gB, B.flag, B.gfirst);
+  int64_t wb = (n + 3) / 4;
   int gb = (int)(wb > 8192 ? 8192 : (wb < 1 ? 1 : wb));
-  hipLaunchKernelGGL(group_ball_k, dim3(gb), dim3(256), 0, s, c->prm.group_size, n, B.ctl, B.alist,
-                     B.pos, B.ball);
+  hipLaunchKernelGGL(group_ball_k, dim3(gb), dim3(256), 0, s, n, B.ctl, B.alist, B.gfirst, B.pos,
+                     B.ball);
 }
 
 }  // namespace gothic

@@ -1,0 +1,251 @@
+// Block (hierarchical) time steps, Section 2.7 of the paper, in float64.
+//
+// All j-particles are predicted to the current time, the due i-particles get
+// tree forces, and they are corrected with the second-order Runge-Kutta
+// scheme of the paper:
+//   predictor  r = r_j + tau v_j + tau^2/2 a_j          (tau = t - t_j)
+//   corrector  r_i += dt v_i + dt^2/2 a_i^old,  v_i += dt/2 (a_i^old + a_i^new)
+// With one shared fixed step this is the leap-frog.  The paper gives neither
+// the time-step criterion nor the level rules; the readings used here:
+//   dt_i = eta sqrt(eps / |a_i|); steps dt_max / 2^k, k = 0..kmax; dt_fine =
+//   largest power of two <= min_i dt_i at t = 0, dt_max = dt_fine 2^kmax; a
+//   particle takes the coarsest level whose step fits its dt_i (exact
+//   comparisons with powers of two); after a correction it may move to any
+//   finer level, and one level coarser only when the current sub-step is a
+//   multiple of that coarser step.  Time is counted in finest sub-steps s
+//   (t = s dt_fine); particle i is due at s when s - s_i = 2^(kmax - k_i).
+// The sub-step counter and every count live on the device, so a step needs
+// no host round-trip.
+#include "common.h"
+#include "primitives.h"
+
+namespace gothic {
+
+__device__ __forceinline__ int level_for(double dt, double dt_max, int kmax) {
+  int k = kmax;
+  for (int kk = kmax; kk >= 0; --kk)
+    if (ldexp(dt_max, -kk) <= dt) k = kk;
+  return k;
+}
+
+__device__ __forceinline__ double step_of(float4 a, double eps, double eta) {
+  const double ax = a.x, ay = a.y, az = a.z;
+  const double am = sqrt(ax * ax + ay * ay + az * az);
+  return am > 0.0 ? eta * sqrt(eps / am) : HUGE_VAL;
+}
+
+__global__ void __launch_bounds__(256)
+sim_shadow_k(int64_t n, const double *__restrict__ pos, const float *__restrict__ mass,
+             float4 *__restrict__ shadow) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    shadow[i] = make_float4((float)pos[3 * i], (float)pos[3 * i + 1], (float)pos[3 * i + 2],
+                            mass[i]);
+}
+
+// t = 0: store a as a_old, find min dt (positive doubles order like their bits)
+__global__ void __launch_bounds__(256)
+sim_init_k(int64_t n, const float4 *__restrict__ acc, float4 *__restrict__ aold,
+           int64_t *__restrict__ si, SimCtl *sc) {
+  const double eps = sc->eps, eta = sc->eta;
+  unsigned long long best = ~0ull;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float4 a = acc[i];
+    aold[i] = a;
+    si[i] = 0;
+    const double dt = step_of(a, eps, eta);
+    const unsigned long long b = __double_as_longlong(dt);
+    best = b < best ? b : best;
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    const unsigned long long o = __shfl_xor(best, d, 64);
+    best = o < best ? o : best;
+  }
+  if (lane_id() == 0) atomicMin(&sc->min_dt_bits, best);
+}
+
+__global__ void sim_anchor_k(SimCtl *sc) {
+  if (threadIdx.x == 0) {
+    const double m = __longlong_as_double((long long)sc->min_dt_bits);
+    int e = 0;
+    if (m > 0.0 && m < HUGE_VAL) {
+      (void)frexp(m, &e);  // m = f 2^e, f in [0.5, 1)
+      sc->dt_fine = ldexp(1.0, e - 1);
+    } else {
+      sc->dt_fine = 1.0;
+    }
+    sc->dt_max = ldexp(sc->dt_fine, sc->kmax);
+    sc->s = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+sim_levels_k(int64_t n, const float4 *__restrict__ aold, uint8_t *__restrict__ lev,
+             const SimCtl *__restrict__ sc) {
+  const double eps = sc->eps, eta = sc->eta, dt_max = sc->dt_max;
+  const int kmax = sc->kmax, shared = sc->shared;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    lev[i] = (uint8_t)(shared ? kmax : level_for(step_of(aold[i], eps, eta), dt_max, kmax));
+}
+
+// sub-step s+1: predict everybody into the float32 shadow, flag the due ones
+__global__ void __launch_bounds__(256)
+sim_predict_k(int64_t n, const double *__restrict__ pos, const double *__restrict__ vel,
+              const float *__restrict__ mass, const float4 *__restrict__ aold,
+              const int64_t *__restrict__ si, const uint8_t *__restrict__ lev,
+              float4 *__restrict__ shadow, uint8_t *__restrict__ act, SimCtl *sc) {
+  const int64_t s = sc->s + 1;
+  const double dtf = sc->dt_fine;
+  const int kmax = sc->kmax;
+  unsigned cnt = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t el = s - si[i];
+    const double tau = (double)el * dtf;
+    const float4 a = aold[i];
+    const double h = 0.5 * tau * tau;
+    const double x = pos[3 * i] + tau * vel[3 * i] + h * (double)a.x;
+    const double y = pos[3 * i + 1] + tau * vel[3 * i + 1] + h * (double)a.y;
+    const double z = pos[3 * i + 2] + tau * vel[3 * i + 2] + h * (double)a.z;
+    shadow[i] = make_float4((float)x, (float)y, (float)z, mass[i]);
+    const bool due = el == ((int64_t)1 << (kmax - lev[i]));
+    act[i] = due ? 1 : 0;
+    cnt += due ? 1u : 0u;
+  }
+  cnt = wave_sum(cnt);
+  if (lane_id() == 0 && cnt) atomicAdd(&sc->n_active, (unsigned long long)cnt);
+}
+
+__global__ void __launch_bounds__(256)
+sim_correct_k(int64_t n, double *__restrict__ pos, double *__restrict__ vel,
+              const float4 *__restrict__ anew, float4 *__restrict__ aold,
+              int64_t *__restrict__ si, uint8_t *__restrict__ lev,
+              const uint8_t *__restrict__ act, const SimCtl *__restrict__ sc) {
+  const int64_t s = sc->s + 1;
+  const double dtf = sc->dt_fine, eps = sc->eps, eta = sc->eta, dt_max = sc->dt_max;
+  const int kmax = sc->kmax, shared = sc->shared;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (!act[i]) continue;
+    const int k = lev[i];
+    const double dt = ldexp(dtf, kmax - k);
+    const float4 ao = aold[i], an = anew[i];
+    const double h = 0.5 * dt * dt;
+    pos[3 * i] += dt * vel[3 * i] + h * (double)ao.x;
+    pos[3 * i + 1] += dt * vel[3 * i + 1] + h * (double)ao.y;
+    pos[3 * i + 2] += dt * vel[3 * i + 2] + h * (double)ao.z;
+    vel[3 * i] += 0.5 * dt * ((double)ao.x + (double)an.x);
+    vel[3 * i + 1] += 0.5 * dt * ((double)ao.y + (double)an.y);
+    vel[3 * i + 2] += 0.5 * dt * ((double)ao.z + (double)an.z);
+    aold[i] = an;
+    si[i] = s;
+    if (!shared) {
+      const int kw = level_for(step_of(an, eps, eta), dt_max, kmax);
+      int kn = k;
+      if (kw > k) {
+        kn = kw;  // finer at once
+      } else if (kw < k && k > 0) {
+        const int64_t coarse = (int64_t)1 << (kmax - k + 1);
+        if (s % coarse == 0) kn = k - 1;  // coarser by one, on that level's grid
+      }
+      lev[i] = (uint8_t)kn;
+    }
+  }
+}
+
+__global__ void sim_advance_k(SimCtl *sc, const Ctl *ctl) {
+  if (threadIdx.x == 0) {
+    sc->s += 1;
+    sc->steps += 1;
+    sc->inter_total += ctl->interactions;
+    sc->node_inter_total += ctl->node_interactions;
+    sc->active_total += sc->n_active;
+    sc->last_active = sc->n_active;
+    sc->n_active = 0;
+  }
+}
+
+__global__ void sim_setup_k(SimCtl *sc, double eps, double eta, int kmax, int shared) {
+  if (threadIdx.x == 0) {
+    sc->eps = eps;
+    sc->eta = eta;
+    sc->kmax = kmax;
+    sc->shared = shared;
+    sc->s = 0;
+  }
+}
+
+__global__ void sim_reset_k(SimCtl *sc) {
+  if (threadIdx.x == 0) {
+    sc->n_active = 0;
+    sc->min_dt_bits = ~0ull;
+    sc->steps = 0;
+    sc->inter_total = 0;
+    sc->node_inter_total = 0;
+    sc->active_total = 0;
+    sc->last_active = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+sim_hist_k(int64_t n, const uint8_t *__restrict__ lev, SimCtl *sc) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&sc->level_count[lev[i] & 31], 1ull);
+}
+
+__global__ void sim_hist_clear_k(SimCtl *sc) {
+  if (threadIdx.x < 32) sc->level_count[threadIdx.x] = 0;
+}
+
+static int grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+void sim_launch_setup(gothic_ctx *c, hipStream_t s, double eps, double eta, int kmax,
+                      int shared) {
+  hipLaunchKernelGGL(sim_setup_k, dim3(1), dim3(64), 0, s, c->sim.sc, eps, eta, kmax, shared);
+}
+
+void sim_launch_reset(gothic_ctx *c, hipStream_t s) {
+  hipLaunchKernelGGL(sim_reset_k, dim3(1), dim3(64), 0, s, c->sim.sc);
+}
+
+void sim_launch_shadow(gothic_ctx *c, hipStream_t s) {
+  SimState &S = c->sim;
+  hipLaunchKernelGGL(sim_shadow_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, S.pos, S.mass,
+                     S.shadow);
+}
+
+void sim_launch_init(gothic_ctx *c, hipStream_t s) {
+  SimState &S = c->sim;
+  hipLaunchKernelGGL(sim_init_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, S.anew, S.aold, S.si,
+                     S.sc);
+  hipLaunchKernelGGL(sim_anchor_k, dim3(1), dim3(64), 0, s, S.sc);
+  hipLaunchKernelGGL(sim_levels_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, S.aold, S.lev,
+                     S.sc);
+}
+
+void sim_launch_predict(gothic_ctx *c, hipStream_t s) {
+  SimState &S = c->sim;
+  hipLaunchKernelGGL(sim_predict_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, S.pos, S.vel,
+                     S.mass, S.aold, S.si, S.lev, S.shadow, S.act, S.sc);
+}
+
+void sim_launch_correct(gothic_ctx *c, hipStream_t s) {
+  SimState &S = c->sim;
+  hipLaunchKernelGGL(sim_correct_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, S.pos, S.vel,
+                     S.anew, S.aold, S.si, S.lev, S.act, S.sc);
+  hipLaunchKernelGGL(sim_advance_k, dim3(1), dim3(64), 0, s, S.sc, c->b.ctl);
+}
+
+void sim_launch_hist(gothic_ctx *c, hipStream_t s) {
+  SimState &S = c->sim;
+  hipLaunchKernelGGL(sim_hist_clear_k, dim3(1), dim3(64), 0, s, S.sc);
+  hipLaunchKernelGGL(sim_hist_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, S.lev, S.sc);
+}
+
+}  // namespace gothic

@@ -5,13 +5,18 @@
 // represented by its pseudo i-particle (r_I, b_I); a candidate pseudo
 // j-particle J is at distance d = lambda r_JI with lambda = 1 - b_I / r_JI
 // (0 when b_I >= r_JI), and is accepted when b_J <= theta d (the opening-angle
-// MAC of Barnes & Hut written without the division).  The walk is breadth
-// first: up to 64 queued nodes are tested at once, one per lane, and
-// ballot/prefix-sum compaction routes
+// MAC of Barnes & Hut written without the division).  Up to 64 pending
+// nodes are tested at once, one per lane, and ballot/prefix-sum compaction
+// routes
 //   accepted nodes        -> the LDS interaction list (pseudo particles),
-//   rejected internal     -> their children to the LDS queue (global spill
-//                            when the queue is full),
+//   rejected internal     -> their children onto the pending stack,
 //   rejected leaves       -> their member particles to the LDS list.
+// The pending nodes form a last-in-first-out stack whose top lives in an LDS
+// ring and whose older part spills to a per-wave global stack.  Taking the
+// newest 64 nodes first keeps the stack near depth x 512 entries, where a
+// first-in-first-out frontier would grow to a whole tree level for groups
+// spread over the system (sparse block-step groups).  The set of interactions
+// does not depend on the order in which pending nodes are tested.
 // When the list is full it is flushed: every lane accumulates the softened
 // force and potential of its i-particle from the list entries (broadcast LDS
 // reads, FP32 with the hardware reciprocal square root).  With G < 64 the
@@ -30,8 +35,10 @@
 
 namespace gothic {
 
-constexpr int kQueueCap = 1024;  // LDS frontier ring per wave (power of two)
+constexpr int kQueueCap = 512;   // LDS part of the pending stack per wave (power of two)
+constexpr int kXcds = 8;         // MI355X: 8 XCDs, workgroups dispatched round-robin
 constexpr int kQueueMask = kQueueCap - 1;
+constexpr int kSpillChunk = 256;  // entries moved to the global stack at a time
 
 struct WalkArgs {
   Ctl *ctl;
@@ -40,6 +47,7 @@ struct WalkArgs {
   const float4 *quad;
   const float4 *pos;
   const uint32_t *alist;
+  const uint32_t *gfirst;
   const float4 *ball;
   const uint32_t *perm;
   float4 *out;
@@ -151,12 +159,31 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   const int D = a.D, DQ = a.DQ;
 
   unsigned long long t_node = 0, t_part = 0, t_int = 0, t_nint = 0, t_mac = 0;
+  // XCD-aware work distribution: the groups (key order, hence spatially
+  // ordered) are cut into kXcds contiguous ranges; the waves of a workgroup
+  // on XCD x (blockIdx % kXcds under round-robin dispatch) drain range x
+  // first, so neighbouring groups share that XCD's L2, then help elsewhere.
+  unsigned xr = blockIdx.x % kXcds;
+  int tried = 0;
   for (;;) {
-    const unsigned g =
-        __builtin_amdgcn_readfirstlane(atomicAdd(&ctl->work, lane == 0 ? 1u : 0u));
+    unsigned g = ng;
+    while (tried < kXcds) {
+      const unsigned lo = (unsigned)(((unsigned long long)xr * ng) / kXcds);
+      const unsigned hi = (unsigned)(((unsigned long long)(xr + 1) * ng) / kXcds);
+      const unsigned cl =
+          __builtin_amdgcn_readfirstlane(atomicAdd(&ctl->xwork[xr], lane == 0 ? 1u : 0u));
+      if (lo + cl < hi) {
+        g = lo + cl;
+        break;
+      }
+      ++tried;
+      xr = (xr + 1) % kXcds;
+    }
     if (g >= ng) break;
-    const unsigned gs = g * (unsigned)G;
-    const int gc = (int)((na - gs) < (unsigned)G ? (na - gs) : (unsigned)G);
+    const unsigned gs = a.gfirst[g];
+    const unsigned ge = a.gfirst[g + 1];
+    const int gc0 = (int)(ge > gs ? ge - gs : 0u);
+    const int gc = gc0 < G ? gc0 : G;
     const float4 bl = a.ball[g];
     const bool vi = il < gc;
     const uint32_t ki0 = a.alist[gs + (vi ? il : 0)];
@@ -164,7 +191,9 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     const float4 pi = a.pos[ki];
     Acc acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int np = 0, nq = 0;
-    unsigned qh = 0, qt = 1;
+    // LDS ring holds stack entries [qb, qt) (ring positions mod kQueueCap);
+    // the global stack holds the older entries [0, stop)
+    unsigned qb = 0, qt = 1;
     int64_t stop = 0;
     unsigned long long e_node = 0, e_part = 0, n_mac = 0;
     if (lane == 0) queue[0] = 0;
@@ -173,24 +202,23 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     // a valid walk pops every node at most once; the bound only guards
     // against a corrupted tree
     unsigned long long pops = 0;
-    while ((qt > qh || stop > 0) && pops <= (unsigned long long)nn) {
-      if (qt == qh) {  // refill the ring from the spill stack
+    while ((qt > qb || stop > 0) && pops <= (unsigned long long)nn) {
+      if (qt == qb) {  // LDS part empty: bring back the newest spilled entries
         // the spill entries were written by other lanes of this wave
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-        const int64_t m = stop < kQueueCap ? stop : kQueueCap;
-        for (int64_t t = lane; t < m; t += 64) queue[t] = spill[stop - m + t];
+        const int64_t m = stop < kQueueCap / 2 ? stop : kQueueCap / 2;
+        for (int64_t t = lane; t < m; t += 64) queue[(qb + t) & kQueueMask] = spill[stop - m + t];
         stop -= m;
-        qh = 0;
-        qt = (unsigned)m;
+        qt = qb + (unsigned)m;
         wave_sync();
       }
-      const unsigned nb = (qt - qh) < 64u ? (qt - qh) : 64u;
+      const unsigned nb = (qt - qb) < 64u ? (qt - qb) : 64u;
       const bool has = (unsigned)lane < nb;
-      const unsigned qv = queue[(qh + lane) & kQueueMask];
+      const unsigned qv = queue[(qt - nb + lane) & kQueueMask];
       // lanes without a node read the root; an entry past the node count
       // (never produced by a valid tree) is dropped the same way
       const unsigned node = (has && qv < nn) ? qv : 0u;
-      qh += nb;
+      qt -= nb;  // pop the newest nb entries
       n_mac += nb;
       pops += nb;
       const float4 r0 = a.nrec[2 * (size_t)node];
@@ -230,21 +258,30 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
         e_node += (unsigned)nacc;
       }
 
-      // (2) children of rejected internal nodes -> queue
+      // (2) children of rejected internal nodes -> pending stack
       const unsigned nc = open_int ? __float_as_uint(r1.z) : 0u;
       const unsigned cf = __float_as_uint(r1.y);
       const unsigned cinc = wave_incl_sum(nc);
       const unsigned C = __builtin_amdgcn_readfirstlane(__shfl(cinc, 63, 64));
       if (C) {
         const unsigned pre = cinc - nc;
-        if ((qt - qh) + C <= (unsigned)kQueueCap) {
+        if ((qt - qb) + C > (unsigned)kQueueCap) {
+          // move the oldest LDS entries to the global stack to make room
+          unsigned k = (qt - qb) + C - (unsigned)kQueueCap;
+          k = (k + kSpillChunk - 1) / kSpillChunk * kSpillChunk;
+          if (k > qt - qb) k = qt - qb;
+          if (stop + k <= a.spill_cap) {
+            for (unsigned t = lane; t < k; t += 64) spill[stop + t] = queue[(qb + t) & kQueueMask];
+            stop += k;
+            qb += k;
+          } else {
+            atomicOr(&ctl->flags, kFlagSpillOverflow);  // all lanes, same bit
+          }
+          wave_sync();
+        }
+        if ((qt - qb) + C <= (unsigned)kQueueCap) {
           for (unsigned q = 0; q < nc; ++q) queue[(qt + pre + q) & kQueueMask] = cf + q;
           qt += C;
-        } else if (stop + C <= a.spill_cap) {
-          for (unsigned q = 0; q < nc; ++q) spill[stop + pre + q] = cf + q;
-          stop += C;
-        } else {
-          atomicOr(&ctl->flags, kFlagSpillOverflow);  // all lanes, same bit
         }
         wave_sync();
       }
@@ -313,12 +350,14 @@ static int wave_bytes_for(int multi, int D, int DQ) {
   return D * 16 + (multi == 2 ? 3 * DQ * 16 : 0) + kQueueCap * 4 + 2 * 64 * 4;
 }
 
-// LDS list sizes: monopole entries take one float4; with quadrupole nodes the
-// list budget is split between particle entries and three-float4 node entries.
+// LDS list sizes (in float4 slots, list_depth in total): monopole entries take
+// one slot; with quadrupole nodes half the budget holds particle entries and
+// half holds node entries of three slots each.  Small lists keep the LDS per
+// wave near 8 KB so 16 waves fit on a CU and hide the walk's memory latency.
 static void list_dims(int multi, int depth, int *D, int *DQ) {
   if (multi == 2) {
     *D = depth / 2 < 64 ? 64 : depth / 2;
-    *DQ = *D;
+    *DQ = depth / 6 < 64 ? 64 : depth / 6;
   } else {
     *D = depth;
     *DQ = 0;
@@ -357,6 +396,7 @@ void launch_walk(gothic_ctx *c, int64_t n, float eps, float theta, float4 *acc_p
   a.quad = B.quad;
   a.pos = B.pos;
   a.alist = B.alist;
+  a.gfirst = B.gfirst;
   a.ball = B.ball;
   a.perm = B.idxA;
   a.out = acc_pot;

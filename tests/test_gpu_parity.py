@@ -87,15 +87,17 @@ def test_moments_match(name, multipole):
         assert np.all(q == 0)
 
 
+@pytest.mark.parametrize("r_crit", [0.0, -0.0625, 0.05])
 @pytest.mark.parametrize("G", [64, 32, 16, 1])
-def test_groups_match(G):
+def test_groups_match(G, r_crit):
     x = ics.nfw(5000, seed=9)
     act = ics.random_active(5000, 0.3, seed=10)
-    ctx, _ = run_gpu(x, 1 / 128, 0.5, active=act, group_size=G)
+    ctx, _ = run_gpu(x, 1 / 128, 0.5, active=act, group_size=G, r_crit=r_crit)
     gg = ctx.groups()
-    ks, perm, _ = ctx.keys()
+    ks, perm, cube = ctx.keys()
     ps = x[perm].astype(np.float64)
-    go = oracle.groups(act[perm], ps, G)
+    rc = float(np.float32(r_crit))
+    go = oracle.groups(act[perm], ps, G, -rc * cube[3] if rc < 0 else rc)
     assert np.array_equal(gg["alist"], go["alist"])
     assert np.array_equal(gg["first"], go["first"])
     assert np.array_equal(gg["count"], go["count"])
@@ -112,19 +114,30 @@ def _check_forces(x, eps, theta, active=None, tol=1e-5, **params):
     ref = oracle.tree_forces(x, eps, theta, active=active, n_leaf=params.get("n_leaf", 16),
                              group_size=params.get("group_size", 32),
                              multipole=params.get("multipole", 1),
-                             key_kind=params.get("key_kind", 0), **tie_params())
+                             key_kind=params.get("key_kind", 0),
+                             r_crit=params.get("r_crit", -0.0625), **tie_params())
     act = np.ones(x.shape[0], bool) if active is None else active.astype(bool)
     assert np.all(np.isnan(out[~act])), "inactive rows must stay untouched"
-    a, r = out[act], ref["acc_pot"][act]
-    assert np.all(np.isfinite(a))
-    e_acc = rel_rms(a, r)
-    e_pot = rel_rms(a, r, cols=slice(3, 4))
+    assert np.all(np.isfinite(out[act]))
     cnt = ref["counts"]
     clean = cnt[:, 2] == 0
+    # particles of groups with a MAC near-tie may legitimately use a different
+    # (equally valid) decomposition: the 1e-5 bar applies to identical lists
+    og = ref["groups"]
+    tie_rows = np.zeros(x.shape[0], bool)
+    for q in np.flatnonzero(~clean):
+        tie_rows[ref["perm"][og["alist"][og["first"][q]:og["first"][q] + og["count"][q]]]] = True
+    ok = act & ~tie_rows
+    a, r = out[ok], ref["acc_pot"][ok]
+    e_acc = rel_rms(a, r) if ok.any() else 0.0
+    e_pot = rel_rms(a, r, cols=slice(3, 4)) if ok.any() else 0.0
+    e_tie = rel_rms(out[act & tie_rows], ref["acc_pot"][act & tie_rows]) if tie_rows.any() else 0.0
     ent = gg["entries"].astype(np.int64)
-    say(f"  rms acc {e_acc:.2e} pot {e_pot:.2e}; groups {cnt.shape[0]} clean {clean.sum()}; "
-        f"interactions {st['interactions']}")
+    say(f"  rms acc {e_acc:.2e} pot {e_pot:.2e} (tie groups {e_tie:.2e}); groups {cnt.shape[0]} "
+        f"clean {clean.sum()}; interactions {st['interactions']}")
     assert e_acc <= tol and e_pot <= tol
+    assert e_tie <= 1e-2  # bounded by the truncation error of one node
+    assert clean.mean() >= 0.9
     assert np.array_equal(ent[clean, 0], cnt[clean, 0])
     assert np.array_equal(ent[clean, 1], cnt[clean, 1])
     if clean.all():
@@ -134,6 +147,11 @@ def _check_forces(x, eps, theta, active=None, tol=1e-5, **params):
 
 def test_plummer8k_config():
     _check_forces(ics.plummer(8192, seed=101), 1 / 64, 0.5)
+
+
+@pytest.mark.parametrize("r_crit", [0.0, 0.3, -0.03125])
+def test_critical_separation(r_crit):
+    _check_forces(ics.nfw(20000, seed=23), 1 / 128, 0.5, multipole=2, r_crit=r_crit)
 
 
 @pytest.mark.parametrize("G", [64, 16, 8, 1])
@@ -173,7 +191,7 @@ def test_node_capacity_overflow_grows_and_repeats():
     # and repeats until the tree fits
     x = ics.nfw(3000, seed=22)
     ctx, out = run_gpu(x, 1 / 128, 0.5, n_leaf=4, node_capacity=256)
-    ref = oracle.tree_forces(x, 1 / 128, 0.5, n_leaf=4)
+    ref = oracle.tree_forces(x, 1 / 128, 0.5, n_leaf=4)  # same default r_crit (L/16)
     assert rel_rms(out, ref["acc_pot"]) <= 1e-5
     assert ctx.stats()["n_nodes"] == ref["tree"]["first"].size
 

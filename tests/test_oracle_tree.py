@@ -144,6 +144,30 @@ def test_moments_parallel_axis_and_ball():
             assert np.abs(Sp - S[k]).max() <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("r_crit", [0.05, 0.3])
+def test_groups_split_at_critical_separation(r_crit):
+    xyzm = ics.nfw(3000, seed=6)
+    act = ics.random_active(3000, 0.5, seed=7)
+    k, _ = oracle.keys(xyzm, 0)
+    ks, perm = oracle.sort(k)
+    ps = xyzm[perm].astype(np.float64)
+    g = oracle.groups(act[perm], ps, 16, r_crit)
+    al = g["alist"]
+    gap = np.r_[np.inf, np.sqrt((np.diff(ps[al, :3], axis=0) ** 2).sum(1))]
+    starts = np.zeros(al.size, bool)
+    starts[g["first"]] = True
+    # a group never spans a gap above r_crit ...
+    assert np.all(starts[gap > r_crit])
+    # ... and inside a run of small gaps groups are cut exactly every G
+    run = np.maximum.accumulate(np.where(gap > r_crit, np.arange(al.size), 0))
+    assert np.array_equal(starts, (np.arange(al.size) - run) % 16 == 0)
+    assert g["count"].sum() == al.size and g["count"].max() <= 16
+    assert np.array_equal(g["first"][1:], (g["first"] + g["count"])[:-1])
+    # no split at all without r_crit
+    g0 = oracle.groups(act[perm], ps, 16, 0.0)
+    assert g0["first"].size == (al.size + 15) // 16
+
+
 def test_groups_chunks_and_geo_ball():
     xyzm = ics.plummer(1000, seed=4)
     act = ics.random_active(1000, 0.3, seed=8)

@@ -68,7 +68,7 @@ def run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, shared, steps, warmup)
     return dict(seconds=t1 - t0, info=info, walk_ms=walk_ms, walk_launches=launches)
 
 
-def cpu_baseline(x, eps, theta, multipole, group_size, n_leaf, target_s=15.0):
+def cpu_baseline(x, eps, theta, multipole, group_size, n_leaf, r_crit, target_s=15.0):
     """The float64 oracle walk on a random sample of the groups of the same
     all-active system (its tree preparation is not timed)."""
     import oracle
@@ -78,7 +78,7 @@ def cpu_baseline(x, eps, theta, multipole, group_size, n_leaf, target_s=15.0):
     tree = oracle.build(ks, n_leaf)
     ps = x[perm].astype(np.float64)
     mom = oracle.moments(tree, ps)
-    grp = oracle.groups(np.ones(x.shape[0], np.uint8), ps, group_size)
+    grp = oracle.groups(np.ones(x.shape[0], np.uint8), ps, group_size, float(np.float32(r_crit)))
     prep = time.perf_counter() - t0
     ng = grp["first"].size
     rng = np.random.default_rng(7)
@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 24)
     ap.add_argument("--group-size", type=int, default=32)
     ap.add_argument("--list-depth", type=int, default=384)
+    ap.add_argument("--r-crit", type=float, default=0.5,
+                    help="critical separation splitting groups (Section 2.4)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-shared", action="store_true", help="skip the shared-step run")
     args = ap.parse_args()
@@ -127,7 +129,7 @@ def main():
     vel0 = torch.from_numpy(v).to(dev)
     mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).to(dev)
     ctx = g.Context(device=0, multipole=multipole, group_size=args.group_size,
-                    list_depth=args.list_depth, timing=1)
+                    list_depth=args.list_depth, r_crit=args.r_crit, timing=1)
 
     log(f"bench: block steps (warmup {args.warmup}, timed {args.steps})")
     blk = run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, False, args.steps, args.warmup)
@@ -162,6 +164,7 @@ def main():
         "config": {"workload": f"NFW sphere N={n}, c=10, eps=1/512, theta=0.5 quadrupole, "
                                f"block steps kmax=8 (eta=0.1), finest sub-steps",
                    "n": n, "group_size": args.group_size, "list_depth": args.list_depth,
+                   "r_crit": args.r_crit,
                    "parallelism": "single GPU"},
         "block": {"s_per_step": blk["seconds"] / args.steps,
                   "interactions_per_s": inter / blk["seconds"],
@@ -181,7 +184,8 @@ def main():
         out["speedup_block_vs_shared"] = shd["seconds"] / blk["seconds"]
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(x, eps, theta, multipole, args.group_size, 16)
+        out["cpu_baseline"] = cpu_baseline(x, eps, theta, multipole, args.group_size, 16,
+                                           args.r_crit)
     print(json.dumps(out), flush=True)
 
 

@@ -121,20 +121,44 @@ internal_moments_k(int l, Ctl *__restrict__ ctl, const uint32_t *__restrict__ ch
   }
 }
 
+// Each wave takes a contiguous chunk of key-ordered particles, in tiles of
+// 64.  A node's particles are contiguous, so at every level the ancestors of
+// a tile form runs; runs that end inside the tile are complete and issue one
+// atomic max each, the last run of a tile is carried to the next tile as a
+// per-level running (node, max) in LDS.  Upper-level nodes thus receive one
+// atomic per wave chunk instead of one per 64 particles.
+constexpr int kRadiusWaves = 4;  // waves per workgroup
+
+__device__ __forceinline__ void flush_b(float4 *nrec, unsigned node, float v) {
+  // every lane passes the same (node, v): the atomic is combined per wave
+  atomicMax(reinterpret_cast<unsigned *>(&nrec[2 * (size_t)node + 1].x), __float_as_uint(v));
+}
+
 __global__ void __launch_bounds__(256)
 radius_k(Ctl *__restrict__ ctl, int64_t n, const float4 *__restrict__ pos,
          const uint32_t *__restrict__ leaf_of, const uint32_t *__restrict__ parent,
          const uint8_t *__restrict__ level, float4 *__restrict__ nrec) {
   if (ctl->flags & kFlagNodeOverflow) return;
   const unsigned nn = ctl->n_nodes;
-  // Loop control is wave-uniform (readfirstlane) and the per-lane steps are
-  // predicated rather than branched, so every lane takes part in each shuffle.
+  __shared__ unsigned s_node[kRadiusWaves][kMaxLevels];
+  __shared__ float s_max[kRadiusWaves][kMaxLevels];
+  const int w = threadIdx.x >> 6;
   const int lane = lane_id();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-    const int64_t i = base + threadIdx.x;
-    const bool inr = i < n;
-    const int64_t ic = inr ? i : n - 1;
+  if (lane < kMaxLevels) {
+    s_node[w][lane] = kNone;
+    s_max[w][lane] = 0.f;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int64_t nw = (int64_t)gridDim.x * kRadiusWaves;
+  const int64_t wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kRadiusWaves + w));
+  const int64_t chunk = ((n + nw - 1) / nw + 63) / 64 * 64;
+  const int64_t c0 = wid * chunk;
+  const int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
+  for (int64_t base = c0; base < c1; base += 64) {
+    const int64_t i = base + lane;
+    const bool inr = i < c1;
+    const int64_t ic = inr ? i : c1 - 1;
     const float4 p = pos[ic];
     const unsigned lf = leaf_of[ic];
     const unsigned par = lf < nn ? parent[lf] : kNone;
@@ -151,7 +175,8 @@ radius_k(Ctl *__restrict__ ctl, int64_t n, const float4 *__restrict__ pos,
       const float4 r = nrec[2 * (size_t)ns];
       const float dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z;
       float dist = (part && r.w > 0.f) ? sqrtf(dx * dx + dy * dy + dz * dz) : 0.f;
-      // segmented max over contiguous runs of equal key
+      // segmented max over contiguous runs of equal key: the first lane of
+      // each run ends up with the run's maximum
 #pragma unroll
       for (int d = 1; d < 64; d <<= 1) {
         const float od = __shfl_down(dist, d, 64);
@@ -159,15 +184,53 @@ radius_k(Ctl *__restrict__ ctl, int64_t n, const float4 *__restrict__ pos,
         dist = (lane + d < 64 && ok == key) ? fmaxf(dist, od) : dist;
       }
       const unsigned prev = __shfl_up(key, 1, 64);
-      if (part && (lane == 0 || prev != key))
-        atomicMax(reinterpret_cast<unsigned *>(&nrec[2 * (size_t)node + 1].x),
-                  __float_as_uint(dist));
+      const bool lead = part && (lane == 0 || prev != key);
+      const unsigned long long lm = __ballot(lead);
+      if (lm) {
+        const int fl = __builtin_amdgcn_readfirstlane(__ffsll((long long)lm) - 1);
+        const int ll = __builtin_amdgcn_readfirstlane(63 - __clzll((long long)lm));
+        const unsigned fnode = __builtin_amdgcn_readfirstlane(__shfl(key, fl, 64));
+        const unsigned lnode = __builtin_amdgcn_readfirstlane(__shfl(key, ll, 64));
+        const float fmx = __shfl(dist, fl, 64);
+        const float lmx = __shfl(dist, ll, 64);
+        unsigned rn = __builtin_amdgcn_readfirstlane(s_node[w][l]);
+        float rm = s_max[w][l];
+        // runs strictly inside the tile are complete
+        if (lead && lane != fl && lane != ll) flush_b(nrec, node, dist);
+        if (fl == ll) {
+          if (fnode == rn) {
+            rm = fmaxf(rm, fmx);
+          } else {
+            if (rn != kNone) flush_b(nrec, rn, rm);
+            rn = fnode;
+            rm = fmx;
+          }
+        } else {
+          if (fnode == rn) {
+            flush_b(nrec, rn, fmaxf(rm, fmx));
+          } else {
+            if (rn != kNone) flush_b(nrec, rn, rm);
+            flush_b(nrec, fnode, fmx);
+          }
+          rn = lnode;
+          rm = lmx;
+        }
+        s_node[w][l] = rn;  // same value from every lane
+        s_max[w][l] = rm;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
       const unsigned up0 = parent[ns];
       const unsigned up = up0 < nn ? up0 : kNone;  // the root's parent is kNone
       const int uplv = (up != kNone) ? (int)level[up != kNone ? up : 0] : -1;
       node = part ? up : node;
       lv = part ? uplv : lv;
     }
+  }
+  // carried runs of the last tile
+  for (int l = 0; l < kMaxLevels; ++l) {
+    const unsigned rn = __builtin_amdgcn_readfirstlane(s_node[w][l]);
+    if (rn != kNone) flush_b(nrec, rn, s_max[w][l]);
   }
 }
 
@@ -187,8 +250,9 @@ void launch_moments(gothic_ctx *c, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(internal_moments_k, dim3(gl), dim3(256), 0, s, l, B.ctl, B.child_first,
                        B.n_child, B.nrec, B.quad, wq);
   }
-  int64_t pb = (n + 255) / 256;
-  int gp = (int)(pb > 8192 ? 8192 : (pb < 1 ? 1 : pb));
+  // about 1024 particles per wave chunk (more waves only for small n)
+  int64_t pb = (n + 4095) / 4096;
+  int gp = (int)(pb > 16384 ? 16384 : (pb < 1 ? 1 : pb));
   hipLaunchKernelGGL(radius_k, dim3(gp), dim3(256), 0, s, B.ctl, n, B.pos, B.leaf_of, B.parent,
                      B.level, B.nrec);
 }

@@ -191,9 +191,15 @@ __global__ void sim_reset_k(SimCtl *sc) {
 
 __global__ void __launch_bounds__(256)
 sim_hist_k(int64_t n, const uint8_t *__restrict__ lev, SimCtl *sc) {
+  __shared__ unsigned h[32];
+  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __syncthreads();
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&sc->level_count[lev[i] & 31], 1ull);
+    atomicAdd(&h[lev[i] & 31], 1u);
+  __syncthreads();
+  if (threadIdx.x < 32 && h[threadIdx.x])
+    atomicAdd(&sc->level_count[threadIdx.x], (unsigned long long)h[threadIdx.x]);
 }
 
 __global__ void sim_hist_clear_k(SimCtl *sc) {

@@ -1,0 +1,155 @@
+"""Parity at the workloads' full sizes, on outputs the oracle can afford.
+
+* NFW 2^24, eps 1/512, theta 0.5, quadrupole, in the launch configuration the
+  benchmark times (G = 32, r_crit = 0.5, list depth 384): bit-exact keys,
+  permutation and octree; forces of 48 sampled groups against the float64
+  tree.
+* Galaxy-like model 2^22 (NFW halo + Hernquist bulge + exponential disk),
+  eps 1/256, theta 0.5, monopole: plain FP32 and compensated accumulation
+  against the float64 tree and the float64 direct sum on 4096 random
+  particles (seed 304).
+* NFW 2^20, eps 1/128, quadrupole, block levels (kmax = 8): t = 0 forces on
+  sampled groups, anchored steps exact, levels exact away from boundaries.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import ics
+import oracle
+from gpu_util import rel_rms, say, tie_params
+from oracle import integrate as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1610_07279_amd as g  # noqa: E402
+
+
+def _oracle_prep(x, n_leaf, G, r_crit, key_kind=0):
+    k, cb = oracle.keys(x, key_kind)
+    ks, perm = oracle.sort(k)
+    tree = oracle.build(ks, n_leaf)
+    ps = x[perm].astype(np.float64)
+    mom = oracle.moments(tree, ps)
+    rc = float(np.float32(r_crit))
+    rc = -rc * cb[3] if rc < 0 else rc
+    return ks, perm, tree, ps, mom, rc
+
+
+def _sampled_groups_parity(out, x, perm, tree, ps, mom, grp, eps, theta, multipole, sel):
+    ref_sorted, cnt, _ = oracle.walk(tree, mom, ps, grp, eps, theta, multipole, gsel=sel,
+                                     **tie_params())
+    clean = cnt[sel, 2] == 0
+    rows_sorted = np.concatenate([grp["alist"][grp["first"][q]:grp["first"][q] + grp["count"][q]]
+                                  for q in sel[clean]])
+    orig = perm[rows_sorted]
+    e_acc = rel_rms(out[orig], ref_sorted[rows_sorted])
+    e_pot = rel_rms(out[orig], ref_sorted[rows_sorted], cols=slice(3, 4))
+    return e_acc, e_pot, cnt, clean
+
+
+def test_nfw16m_bench_configuration():
+    n, eps, theta = 1 << 24, 1 / 512, 0.5
+    say("[gpu] NFW 2^24 quadrupole, G=32, r_crit=0.5")
+    x = ics.nfw(n, seed=501)
+    ctx = g.Context(device=0, multipole=2, group_size=32, r_crit=0.5, list_depth=384)
+    out = ctx.tree_forces(torch.from_numpy(x).cuda(), eps, theta).cpu().numpy()
+    ks, perm, cube = ctx.keys()
+    t = ctx.tree()
+    gg = ctx.groups()
+    say("  oracle tree at 2^24")
+    ks_o, perm_o, tree, ps, mom, rc = _oracle_prep(x, 16, 32, 0.5)
+    assert np.array_equal(ks, ks_o) and np.array_equal(perm, perm_o)
+    for f in ("first", "count", "child_first", "n_child", "level"):
+        assert np.array_equal(t[f], tree[f]), f
+    grp = oracle.groups(np.ones(n, np.uint8), ps, 32, rc)
+    assert np.array_equal(gg["first"], grp["first"]) and np.array_equal(gg["count"], grp["count"])
+    rng = np.random.default_rng(5)
+    ng = grp["first"].size
+    sel = np.unique(np.r_[rng.choice(ng, 40, replace=False), np.argsort(-grp["ball"][:, 3])[:8]])
+    e_acc, e_pot, cnt, clean = _sampled_groups_parity(out, x, perm, tree, ps, mom, grp, eps,
+                                                      theta, 2, sel)
+    ent = gg["entries"].astype(np.int64)
+    say(f"  sampled {sel.size} groups ({clean.sum()} tie-free): rms acc {e_acc:.2e} pot {e_pot:.2e}")
+    assert e_acc <= 1e-5 and e_pot <= 1e-5
+    assert np.array_equal(ent[sel[clean], 0], cnt[sel[clean], 0])
+    assert np.array_equal(ent[sel[clean], 1], cnt[sel[clean], 1])
+
+
+@functools.lru_cache(maxsize=1)
+def _galaxy_reference():
+    n, eps = 1 << 22, 1 / 256
+    x = ics.galaxy(n)
+    rng = np.random.default_rng(304)
+    sub = rng.choice(n, 4096, replace=False)
+    say("  oracle direct sum on 4096 particles")
+    d = oracle.direct(x, eps, idx=sub)
+    say("  oracle tree on the groups of the sample")
+    ks_o, perm_o, tree, ps, mom, rc = _oracle_prep(x, 16, 32, -0.0625)
+    grp = oracle.groups(np.ones(n, np.uint8), ps, 32, rc)
+    inv = np.empty(n, np.int64)
+    inv[perm_o] = np.arange(n)
+    sel = np.unique(np.searchsorted(grp["first"], inv[sub], side="right") - 1)
+    ref_sorted, cnt, _ = oracle.walk(tree, mom, ps, grp, eps, 0.5, 1, gsel=sel, **tie_params())
+    clean = cnt[sel, 2] == 0
+    rows = np.concatenate([grp["alist"][grp["first"][q]:grp["first"][q] + grp["count"][q]]
+                           for q in sel[clean]])
+    return x, sub, d, perm_o[rows], ref_sorted[rows], sel.size
+
+
+@pytest.mark.parametrize("compensated", [0, 1])
+def test_galaxy4m_fp32_and_compensated(compensated):
+    eps, theta = 1 / 256, 0.5
+    say(f"[gpu] galaxy 2^22 monopole compensated={compensated}")
+    x, sub, d, rows, ref, nsel = _galaxy_reference()
+    ctx = g.Context(device=0, multipole=1, compensated=compensated)
+    out = ctx.tree_forces(torch.from_numpy(x).cuda(), eps, theta).cpu().numpy()
+    err_direct = np.linalg.norm(out[sub, :3] - d[:, :3], axis=1) / np.linalg.norm(d[:, :3], axis=1)
+    e_acc = rel_rms(out[rows], ref)
+    e_pot = rel_rms(out[rows], ref, cols=slice(3, 4))
+    say(f"  vs float64 tree ({nsel} groups): rms acc {e_acc:.2e} pot {e_pot:.2e}; vs direct: "
+        f"p50 {np.median(err_direct):.2e} p99 {np.percentile(err_direct, 99):.2e} "
+        f"rms {rel_rms(out[sub], d):.2e}")
+    assert e_acc <= 1e-5 and e_pot <= 1e-5
+    # truncation error of theta = 0.5 monopoles (about 1e-3 typical)
+    assert np.median(err_direct) < 3e-3 and rel_rms(out[sub], d) < 1e-2
+
+
+def test_nfw1m_block_levels():
+    n, eps, theta, eta, kmax = 1 << 20, 1 / 128, 0.5, 0.1, 8
+    say("[gpu] NFW 2^20 quadrupole block levels")
+    x, v = ics.nfw(n, seed=201, with_vel=True)
+    ctx = g.Context(device=0, multipole=2, r_crit=0.5)
+    pos = torch.from_numpy(x[:, :3].astype(np.float64)).cuda()
+    vel = torch.from_numpy(v).cuda()
+    mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).cuda()
+    ctx.sim_bind(pos, vel, mass, eps, theta, eta=eta, kmax=kmax)
+    info = ctx.sim_info()
+    acc, lev, _ = ctx.sim_state()
+    ks_o, perm_o, tree, ps, mom, rc = _oracle_prep(x, 16, 32, 0.5)
+    grp = oracle.groups(np.ones(n, np.uint8), ps, 32, rc)
+    rng = np.random.default_rng(6)
+    sel = rng.choice(grp["first"].size, 64, replace=False)
+    ref_sorted, cnt, _ = oracle.walk(tree, mom, ps, grp, eps, theta, 2, gsel=sel, **tie_params())
+    clean = cnt[sel, 2] == 0
+    rows = np.concatenate([grp["alist"][grp["first"][q]:grp["first"][q] + grp["count"][q]]
+                           for q in sel[clean]])
+    e_acc = rel_rms(acc[perm_o[rows]], ref_sorted[rows])
+    # levels from the oracle's accelerations on the sampled rows
+    dt_o = I.timestep(ref_sorted[rows, :3], eps, eta)
+    dt_all_gpu = I.timestep(acc[:, :3].astype(np.float64), eps, eta)
+    assert info["dt_fine"] == I.anchor(dt_all_gpu)
+    k_o = I.level_for(dt_o, info["dt_max"], kmax)
+    r = np.log2(info["dt_max"] / dt_o)
+    away = np.abs(r - np.round(r)) > 1e-4
+    lv = lev[perm_o[rows]]
+    say(f"  rms acc {e_acc:.2e}; levels agree {np.mean(lv[away] == k_o[away]):.5f}; histogram "
+        f"{[c for c in info['level_count'] if c]}")
+    assert e_acc <= 1e-5
+    assert np.array_equal(lv[away], k_o[away])
+    assert sum(info["level_count"]) == n

@@ -68,6 +68,101 @@ def run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, shared, steps, warmup)
     return dict(seconds=t1 - t0, info=info, walk_ms=walk_ms, walk_launches=launches)
 
 
+def batched_bench(cycles=1, kmax=6):
+    """64 independent systems (N_s log-uniform in [2^12, 2^18], Plummer / NFW,
+    seed 401), monopole, theta 0.5, block steps on 6 levels below the finest:
+    one full cycle of 2^kmax sub-steps with every system advanced by ONE
+    captured batched sub-step (graph), against the same systems advanced by 64
+    separate contexts, one sub-step each, launched in turn on the same stream.
+    Also one all-active force evaluation: batched vs 64 serial calls."""
+    import torch
+
+    import ics
+    import paper_1610_07279_amd as g
+    x, offs, eps, v = ics.batched_systems(64, seed=401, with_vel=True)
+    nsys, n = 64, x.shape[0]
+    dev = torch.device("cuda", 0)
+    pos0 = torch.from_numpy(x[:, :3].astype(np.float64)).to(dev)
+    vel0 = torch.from_numpy(v).to(dev)
+    mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).to(dev)
+    xt = torch.from_numpy(x).to(dev)
+    steps = cycles << kmax
+
+    # both sides take one untimed sub-step (the capture, the first launches),
+    # then a full cycle of 2^kmax sub-steps is timed
+    ctx = g.Context(device=0, graph=1)
+    pos, vel = pos0.clone(), vel0.clone()
+    ctx.sim_bind_batched(pos, vel, mass, offs, eps, 0.5, eta=0.1, kmax=kmax)
+    ctx.set_params(check=0)
+    ctx.sim_step(1)
+    ctx.sim_reset_counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.sim_step(steps)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    info = ctx.sim_info()
+    if ctx.stats()["flags"]:
+        raise RuntimeError("device flags set in the batched steps")
+
+    ctxs, keep = [], []
+    for s in range(nsys):
+        lo, hi = int(offs[s]), int(offs[s + 1])
+        c = g.Context(device=0)
+        p, q = pos0[lo:hi].clone(), vel0[lo:hi].clone()
+        m = mass[lo:hi].contiguous()
+        c.sim_bind(p, q, m, float(eps[s]), 0.5, eta=0.1, kmax=kmax)
+        c.set_params(check=0)
+        ctxs.append(c)
+        keep.append((p, q, m))
+    for c in ctxs:
+        c.sim_step(1)
+        c.sim_reset_counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for c in ctxs:
+            c.sim_step(1)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    active_serial = sum(c.sim_info()["active_total"] for c in ctxs)
+
+    # one all-active evaluation
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    fctx = g.Context(device=0, check=0)
+    fctx.tree_forces_batched(xt, offs, eps, 0.5, out=out)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fctx.tree_forces_batched(xt, offs, eps, 0.5, out=out)
+    torch.cuda.synchronize()
+    f_b = (time.perf_counter() - t0) / reps
+    sctx = g.Context(device=0, check=0)
+    views = [(xt[int(offs[s]):int(offs[s + 1])], out[int(offs[s]):int(offs[s + 1])])
+             for s in range(nsys)]
+    for s, (xs, os_) in enumerate(views):
+        sctx.tree_forces(xs, float(eps[s]), 0.5, out=os_)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for s, (xs, os_) in enumerate(views):
+            sctx.tree_forces(xs, float(eps[s]), 0.5, out=os_)
+    torch.cuda.synchronize()
+    f_s = (time.perf_counter() - t0) / reps
+    return {"workload": f"64 systems, N={n} in all (N_s log-uniform in [2^12, 2^18], Plummer "
+                        f"eps 1/64 / NFW eps 1/128), monopole, theta 0.5, kmax {kmax}",
+            "substeps": steps,
+            "batched_graph_ms_per_substep": t_b / steps * 1e3,
+            "serial_64_contexts_ms_per_substep": t_s / steps * 1e3,
+            "speedup": t_s / t_b,
+            "active_per_substep": info["active_total"] / steps,
+            "active_per_substep_serial": active_serial / steps,
+            "interactions_per_s": info["interactions_total"] / t_b,
+            "forces_all_active_ms": {"batched": f_b * 1e3, "serial_64_calls": f_s * 1e3,
+                                     "speedup": f_s / f_b}}
+
+
 def cpu_baseline(x, eps, theta, multipole, group_size, n_leaf, r_crit, target_s=15.0):
     """The float64 oracle walk on a random sample of the groups of the same
     all-active system (its tree preparation is not timed)."""
@@ -110,6 +205,8 @@ def main():
                     help="critical separation splitting groups (Section 2.4)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-shared", action="store_true", help="skip the shared-step run")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-system batched / captured sub-step comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profile to bytes) and exit")
@@ -196,6 +293,11 @@ def main():
                          "interactions_per_s": inter_s / shd["seconds"],
                          "walk_ms_per_step": shd["walk_ms"] / max(shd["walk_launches"], 1)}
         out["speedup_block_vs_shared"] = shd["seconds"] / blk["seconds"]
+    if not args.no_batched:
+        log("bench: 64 systems, batched captured sub-steps vs 64 contexts")
+        out["batched"] = batched_bench()
+        log(f"bench: batched {out['batched']['batched_graph_ms_per_substep']:.2f} ms/sub-step, "
+            f"serial {out['batched']['serial_64_contexts_ms_per_substep']:.2f}")
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(x, eps, theta, multipole, args.group_size, 16,

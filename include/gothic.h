@@ -81,8 +81,14 @@ typedef struct {
   float r_crit;       /* critical separation of Section 2.4: two consecutive
                          active particles (key order) farther apart than r_crit
                          never share a group; > 0 absolute length, 0 = no split,
-                         < 0 a fraction of the key-cube side L (default -1/16,
-                         i.e. L/16) */
+                         < 0 a fraction of the key-cube side L of the
+                         particle's system (default -1/16, i.e. L/16) */
+  int graph;          /* 1: with check = 0, gothic_sim_step replays one captured
+                         HIP graph of the whole sub-step (predict, keys, sort,
+                         tree, moments, groups, walk, correct) instead of
+                         launching some two hundred kernels; it is captured on
+                         first use and again after any buffer or parameter
+                         change (default 0) */
   int64_t node_capacity; /* initial size of the node arrays in nodes; 0 = from
                          n and n_leaf (about n + 8 n / n_leaf).  Trees that do
                          not fit are abandoned on the device, the arrays grow
@@ -105,7 +111,8 @@ typedef struct {
   int32_t flags;          /* device error flags (bit 0 non-finite input, bit 1
                              node overflow, bit 2 frontier overflow, bit 3 an
                              internal index check failed) */
-  int32_t pad;
+  int32_t n_systems;      /* non-empty systems of the evaluation (1 unless
+                             batched) */
 } gothic_stats;
 
 /* Default tunables (see gothic_params). */
@@ -143,11 +150,18 @@ int gothic_tree_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, f
                        const uint8_t *active, float *acc_pot, void *stream);
 
 /*
- * Many independent systems in one call (one walk launch over the groups of
- * every system).  System s owns particles [offsets[s], offsets[s+1]) of xyzm,
+ * Many independent systems in one evaluation: every kernel of the pipeline is
+ * launched once for all systems (one walk launch over the groups of every
+ * system).  System s owns particles [offsets[s], offsets[s+1]) of xyzm,
  * active and acc_pot, with its own softening eps[s] and angle theta[s]; each
- * system gets its own keys, tree and groups.  offsets/eps/theta are HOST
- * arrays of nsys+1 / nsys / nsys entries.  Same rules as gothic_tree_forces.
+ * system gets its own key cube, keys, tree (root = node s of the combined
+ * breadth-first numbering, counting non-empty systems only) and groups, and
+ * its forces are those of gothic_tree_forces on that system alone.
+ *   nsys     1 <= nsys <= 65535
+ *   offsets  HOST int64 [nsys + 1]: offsets[0] = 0, non-decreasing, total
+ *            below 2^31 (empty systems are allowed and skipped)
+ *   eps, theta  HOST float [nsys], each as in gothic_tree_forces
+ * Same pointer and error rules as gothic_tree_forces.
  */
 int gothic_tree_forces_batched(gothic_ctx *c, int nsys, const int64_t *offsets,
                                const float *xyzm, const float *eps, const float *theta,
@@ -191,23 +205,37 @@ typedef struct {
 
 int gothic_sim_bind(gothic_ctx *c, int64_t n, double *pos, double *vel, const float *mass,
                     float eps, float theta, double eta, int kmax, int shared_step, void *stream);
+/* nsys independent systems stepped together (arguments as in
+ * gothic_tree_forces_batched, no empty systems): each has its own dt_fine and
+ * dt_max (from its own minimum step) and advances one of its own finest
+ * sub-steps per gothic_sim_step; the forces of a sub-step are one batched
+ * evaluation. */
+int gothic_sim_bind_batched(gothic_ctx *c, int nsys, const int64_t *offsets, double *pos,
+                            double *vel, const float *mass, const float *eps,
+                            const float *theta, double eta, int kmax, int shared_step,
+                            void *stream);
 int gothic_sim_step(gothic_ctx *c, void *stream);
 int gothic_sim_reset_counters(gothic_ctx *c, void *stream);
 int gothic_sim_get_info(gothic_ctx *c, gothic_sim_info *out);
 /* acc_pot [n][4] float (last forces), levels [n] uint8, last [n] int64 (sub-step
  * of each particle's last update): caller DEVICE buffers, NULL skips. */
 int gothic_sim_get_state(gothic_ctx *c, float *acc_pot, uint8_t *levels, int64_t *last);
+/* dt_fine and dt_max of every bound system: HOST double arrays of nsys
+ * entries (gothic_sim_info reports system 0).  Synchronises. */
+int gothic_sim_get_steps(gothic_ctx *c, int nsys, double *dt_fine, double *dt_max);
 
 /* Counts of the last evaluation; synchronises the stream of that call. */
 int gothic_get_stats(gothic_ctx *c, gothic_stats *out);
 
 /*
- * Introspection of the last single-system evaluation, for bit-exact tests.
- * All outputs are caller-owned DEVICE buffers sized from gothic_get_stats;
- * any pointer may be NULL to skip it.  Each call synchronises.
+ * Introspection of the last evaluation, for bit-exact tests.  All outputs are
+ * caller-owned DEVICE buffers sized from gothic_get_stats; any pointer may be
+ * NULL to skip it.  Each call synchronises.
  *   keys_sorted [n] uint64 and perm [n] uint32: the stable key sort
- *     (perm[k] = caller index of the k-th particle in key order)
- *   cube [4] double: x_min, y_min, z_min, side L of the key cube
+ *     (perm[k] = caller index of the k-th particle in key order; with several
+ *     systems the order is by system first, each within its own range)
+ *   cube [n_systems][4] double: x_min, y_min, z_min, side L of the key cube
+ *     of each non-empty system
  *   tree [n_nodes] arrays in breadth-first order: first particle (in key
  *     order), particle count, first child, number of children, level
  *   nodes: com_m [n_nodes][4] float (centre of mass, mass), b [n_nodes] float

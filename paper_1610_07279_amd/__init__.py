@@ -33,7 +33,7 @@ class Params(C.Structure):
     _fields_ = [("key_kind", C.c_int), ("n_leaf", C.c_int), ("multipole", C.c_int),
                 ("group_size", C.c_int), ("list_depth", C.c_int), ("compensated", C.c_int),
                 ("check", C.c_int), ("timing", C.c_int), ("r_crit", C.c_float),
-                ("node_capacity", C.c_int64)]
+                ("graph", C.c_int), ("node_capacity", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -41,10 +41,10 @@ class Stats(C.Structure):
                 ("n_groups", C.c_int64), ("n_levels", C.c_int64), ("node_entries", C.c_int64),
                 ("part_entries", C.c_int64), ("interactions", C.c_int64),
                 ("node_interactions", C.c_int64), ("mac_tests", C.c_int64),
-                ("flags", C.c_int32), ("pad", C.c_int32)]
+                ("flags", C.c_int32), ("n_systems", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class SimInfo(C.Structure):
@@ -82,6 +82,8 @@ def _load():
     lib.gothic_get_groups.argtypes = [P, P, P, P, P, P]
     lib.gothic_get_walk_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64)]
     lib.gothic_sim_bind.argtypes = [P, i64, P, P, P, f32, f32, C.c_double, i32, i32, P]
+    lib.gothic_sim_bind_batched.argtypes = [P, i32, P, P, P, P, P, P, C.c_double, i32, i32, P]
+    lib.gothic_sim_get_steps.argtypes = [P, i32, P, P]
     lib.gothic_sim_step.argtypes = [P, P]
     lib.gothic_sim_reset_counters.argtypes = [P, P]
     lib.gothic_sim_get_info.argtypes = [P, C.POINTER(SimInfo)]
@@ -89,8 +91,9 @@ def _load():
     for name in ("gothic_create", "gothic_destroy", "gothic_set_params", "gothic_get_params",
                  "gothic_tree_forces", "gothic_tree_forces_batched", "gothic_get_stats",
                  "gothic_get_keys", "gothic_get_tree", "gothic_get_nodes", "gothic_get_groups",
-                 "gothic_get_walk_time", "gothic_sim_bind", "gothic_sim_step",
-                 "gothic_sim_reset_counters", "gothic_sim_get_info", "gothic_sim_get_state"):
+                 "gothic_get_walk_time", "gothic_sim_bind", "gothic_sim_bind_batched",
+                 "gothic_sim_step", "gothic_sim_reset_counters", "gothic_sim_get_info",
+                 "gothic_sim_get_state", "gothic_sim_get_steps"):
         getattr(lib, name).restype = i32
     return lib
 
@@ -192,17 +195,39 @@ class Context:
                                       _ptr(active), _ptr(out), s))
         return out
 
-    def tree_forces_batched(self, xyzm, offsets, eps, theta, active=None, out=None, stream=None):
+    @staticmethod
+    def _systems(offsets, eps, theta):
         import numpy as np
-        import torch
         offs = np.ascontiguousarray(offsets, dtype=np.int64)
         nsys = offs.size - 1
+        if nsys < 1:
+            raise ValueError("offsets needs at least two entries")
         e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float32), (nsys,)))
         t = np.ascontiguousarray(np.broadcast_to(np.asarray(theta, np.float32), (nsys,)))
+        return offs, nsys, e, t
+
+    def tree_forces_batched(self, xyzm, offsets, eps, theta, active=None, out=None, stream=None):
+        """Forces of nsys independent systems in one evaluation: system s owns rows
+        offsets[s]:offsets[s+1] of xyzm (eps, theta: scalars or one per system)."""
+        import torch
+        offs, nsys, e, t = self._systems(offsets, eps, theta)
+        if xyzm.dtype != torch.float32 or xyzm.dim() != 2 or xyzm.shape[1] != 4:
+            raise ValueError("xyzm must be a float32 [n,4] tensor")
+        if not xyzm.is_cuda or not xyzm.is_contiguous():
+            raise ValueError("xyzm must be a contiguous GPU tensor")
         n = xyzm.shape[0]
+        if offs[-1] != n:
+            raise ValueError("offsets[-1] must equal the number of rows of xyzm")
+        if active is not None:
+            if active.dtype != torch.uint8 or active.shape != (n,) or not active.is_cuda \
+                    or not active.is_contiguous():
+                raise ValueError("active must be a contiguous uint8 [n] GPU tensor")
         if out is None:
             out = torch.zeros((n, 4), dtype=torch.float32, device=xyzm.device)
+        elif out.dtype != torch.float32 or out.shape != (n, 4) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 [n,4] tensor")
         s = _stream_of(xyzm, stream)
+        self._last_stream = s
         _check(lib.gothic_tree_forces_batched(
             self._h, nsys, offs.ctypes.data_as(C.c_void_p), _ptr(xyzm),
             e.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p), _ptr(active), _ptr(out),
@@ -220,10 +245,44 @@ class Context:
             if t.dtype != dt or tuple(t.shape) != shp or not t.is_cuda or not t.is_contiguous():
                 raise ValueError("pos/vel must be float64 [n,3], mass float32 [n], contiguous GPU")
         self._sim_keep = (pos, vel, mass)
+        self._sim_nsys = 1
         s = _stream_of(pos, stream)
         self._last_stream = s
         _check(lib.gothic_sim_bind(self._h, n, _ptr(pos), _ptr(vel), _ptr(mass), float(eps),
                                    float(theta), float(eta), int(kmax), int(bool(shared)), s))
+
+    def sim_bind_batched(self, pos, vel, mass, offsets, eps, theta, eta=0.1, kmax=8, shared=False,
+                         stream=None):
+        """sim_bind for nsys independent systems (rows offsets[s]:offsets[s+1]), each
+        with its own softening, opening angle and time-step hierarchy."""
+        import torch
+        offs, nsys, e, t = self._systems(offsets, eps, theta)
+        n = pos.shape[0]
+        for a, dt, shp in ((pos, torch.float64, (n, 3)), (vel, torch.float64, (n, 3)),
+                           (mass, torch.float32, (n,))):
+            if a.dtype != dt or tuple(a.shape) != shp or not a.is_cuda or not a.is_contiguous():
+                raise ValueError("pos/vel must be float64 [n,3], mass float32 [n], contiguous GPU")
+        if offs[-1] != n:
+            raise ValueError("offsets[-1] must equal the number of rows of pos")
+        self._sim_keep = (pos, vel, mass)
+        self._sim_nsys = nsys
+        s = _stream_of(pos, stream)
+        self._last_stream = s
+        _check(lib.gothic_sim_bind_batched(self._h, nsys, offs.ctypes.data_as(C.c_void_p),
+                                           _ptr(pos), _ptr(vel), _ptr(mass),
+                                           e.ctypes.data_as(C.c_void_p),
+                                           t.ctypes.data_as(C.c_void_p), float(eta), int(kmax),
+                                           int(bool(shared)), s))
+
+    def sim_steps(self):
+        """(dt_fine [nsys], dt_max [nsys]) float64 numpy arrays of the bound systems."""
+        import numpy as np
+        ns = getattr(self, "_sim_nsys", 1)
+        f = np.zeros(ns, np.float64)
+        m = np.zeros(ns, np.float64)
+        _check(lib.gothic_sim_get_steps(self._h, ns, f.ctypes.data_as(C.c_void_p),
+                                        m.ctypes.data_as(C.c_void_p)))
+        return f, m
 
     def sim_step(self, nsteps: int = 1, stream=None):
         s = _stream_of(self._sim_keep[0], stream)
@@ -267,17 +326,19 @@ class Context:
         return st.as_dict()
 
     def keys(self):
-        """(keys_sorted uint64 numpy, perm uint32 numpy, cube float64 numpy)"""
+        """(keys_sorted uint64 numpy, perm uint32 numpy, cube float64 numpy): cube is
+        [4] for one system, [n_systems, 4] for a batched evaluation."""
         import torch
         st = self._stats_raw()
-        n = st["n"]
+        n, ns = st["n"], max(st["n_systems"], 1)
         dev = torch.device("cuda", self.device)
         k = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
         p = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
-        cb = torch.empty(4, dtype=torch.float64, device=dev)
+        cb = torch.empty((ns, 4), dtype=torch.float64, device=dev)
         _check(lib.gothic_get_keys(self._h, _ptr(k), _ptr(p), _ptr(cb)))
+        cube = cb.cpu().numpy()
         return (k[:n].cpu().numpy().view("uint64"), p[:n].cpu().numpy().view("uint32"),
-                cb.cpu().numpy())
+                cube[0] if ns == 1 else cube)
 
     def tree(self) -> dict:
         import torch

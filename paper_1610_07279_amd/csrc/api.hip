@@ -37,6 +37,33 @@ __global__ void ctl_reset_k(Ctl *ctl) {
   for (unsigned i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) w[i] = 0u;
 }
 
+// The system table travels in kernel arguments (captured by value in a
+// graph), kSysChunk systems per launch: no host staging buffer that a later
+// call could overwrite before the copy runs.
+constexpr int kSysChunk = 32;
+constexpr int kMaxSys = 65535;  // grid y limit of the per-system kernels
+struct SysChunk {
+  int first, count;
+  uint32_t off[kSysChunk + 1];
+  float eps2[kSysChunk], theta[kSysChunk], inv_eps[kSysChunk];
+};
+
+__global__ void sys_upload_k(SysChunk ch, SysRec *sys, uint32_t *soff) {
+  const int t = threadIdx.x;
+  if (t < ch.count) {
+    SysRec &r = sys[ch.first + t];
+    r.eps2 = ch.eps2[t];
+    r.theta = ch.theta[t];
+    r.inv_eps = ch.inv_eps[t];
+  }
+  if (t <= ch.count) soff[ch.first + t] = ch.off[t];
+}
+
+__global__ void extract_cubes_k(int nsys, const SysRec *sys, double *cube) {
+  for (int s = threadIdx.x; s < nsys; s += blockDim.x)
+    for (int a = 0; a < 4; ++a) cube[4 * s + a] = sys[s].cube[a];
+}
+
 __global__ void extract_nodes_k(const Ctl *ctl, const float4 *nrec, const float4 *quad,
                                 float4 *com_m, float *b, float *q6) {
   const int64_t nn = ctl->n_nodes;
@@ -81,12 +108,14 @@ static void free_all(gothic_ctx *c) {
   void *ptrs[] = {B.keyA, B.keyB, B.idxA, B.idxB, B.pos, B.leaf_of, B.flag, B.flag2, B.alist,
                   B.gA, B.gB, B.gfirst,
                   B.first, B.count, B.child_first, B.parent, B.n_child, B.level, B.nch, B.bnd,
-                  B.nrec, B.quad, B.ball, B.gent, B.hist, B.part, B.bbox_part, B.spill, B.ctl};
+                  B.nrec, B.quad, B.ball, B.gent, B.hist, B.part, B.bbox_part, B.spill, B.sys,
+                  B.soff, B.ctl};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (B.ctl_host) (void)hipHostFree(B.ctl_host);
   B = Buffers();
-  c->cap_n = c->cap_nodes = c->cap_groups = c->cap_hist = 0;
+  c->cap_n = c->cap_nodes = c->cap_groups = c->cap_hist = c->cap_sys = 0;
+  ++c->generation;
 }
 
 static int validate_params(const gothic_params *p) {
@@ -106,21 +135,31 @@ static int validate_params(const gothic_params *p) {
   if (p->node_capacity < 0) return set_error(GOTHIC_EINVAL, "node_capacity must be >= 0");
   if (p->timing != 0 && p->timing != 1) return set_error(GOTHIC_EINVAL, "timing must be 0 or 1");
   if (!std::isfinite(p->r_crit)) return set_error(GOTHIC_EINVAL, "r_crit must be finite");
+  if (p->graph != 0 && p->graph != 1) return set_error(GOTHIC_EINVAL, "graph must be 0 or 1");
   return GOTHIC_OK;
 }
 
 // Make sure every buffer can hold n particles (and the current node / spill
 // capacities).  Never called while the stream is being captured.
-static int ensure(gothic_ctx *c, int64_t n, int64_t want_nodes, int64_t want_spill) {
+static int ensure(gothic_ctx *c, int64_t n, int nsys, int64_t want_nodes, int64_t want_spill) {
   Buffers &B = c->b;
   if (!B.ctl) {
     GCHECK(hipMalloc(reinterpret_cast<void **>(&B.ctl), sizeof(Ctl)));
     GCHECK(hipHostMalloc(reinterpret_cast<void **>(&B.ctl_host), sizeof(Ctl), hipHostMallocDefault));
     int rc;
     if ((rc = dev_alloc(&B.part, scan_blocks() + 64)) != GOTHIC_OK) return rc;
-    if ((rc = dev_alloc(&B.bbox_part, 1024 * 6)) != GOTHIC_OK) return rc;
+    ++c->generation;
   }
   int rc;
+  if (nsys > c->cap_sys) {
+    const int64_t cs = std::max<int64_t>(nsys, 64);
+    // bbox partials: nsys x bbox_partials(nsys, .) <= max(1024, nsys) workgroups
+    if ((rc = dev_alloc(&B.sys, cs)) || (rc = dev_alloc(&B.soff, cs + 1)) ||
+        (rc = dev_alloc(&B.bbox_part, 6 * std::max<int64_t>(1024, cs))))
+      return rc;
+    c->cap_sys = cs;
+    ++c->generation;
+  }
   if (n > c->cap_n) {
     const int64_t cn = std::max<int64_t>(n, 1024);
     if ((rc = dev_alloc(&B.keyA, cn)) || (rc = dev_alloc(&B.keyB, cn)) ||
@@ -138,6 +177,7 @@ static int ensure(gothic_ctx *c, int64_t n, int64_t want_nodes, int64_t want_spi
     c->cap_n = cn;
     c->cap_groups = cn;
     c->cap_hist = hist;
+    ++c->generation;
   }
   const int64_t nodes = std::max<int64_t>(want_nodes, 64);
   if (nodes > c->cap_nodes) {
@@ -147,6 +187,7 @@ static int ensure(gothic_ctx *c, int64_t n, int64_t want_nodes, int64_t want_spi
         (rc = dev_alloc(&B.nrec, 2 * nodes)) || (rc = dev_alloc(&B.quad, 2 * nodes)))
       return rc;
     c->cap_nodes = nodes;
+    ++c->generation;
   }
   const int slots = walk_slots(c);
   const int64_t spill = std::max<int64_t>(want_spill, 16384);
@@ -154,6 +195,7 @@ static int ensure(gothic_ctx *c, int64_t n, int64_t want_nodes, int64_t want_spi
     if ((rc = dev_alloc(&B.spill, (int64_t)slots * spill))) return rc;
     c->walk_waves = slots;
     c->spill_per_wave = spill;
+    ++c->generation;
   }
   return GOTHIC_OK;
 }
@@ -170,21 +212,86 @@ struct DeviceGuard {
   }
 };
 
-static int enqueue_forces(gothic_ctx *c, int64_t n, const float4 *xyzm, float eps, float theta,
-                          const uint8_t *active, float4 *out, hipStream_t s) {
+// The systems of one evaluation, non-empty ones only (host side).
+struct Systems {
+  int nsys = 0;
+  int64_t n = 0, max_n = 0;
+  std::vector<int64_t> off;  // nsys + 1
+  std::vector<float> eps, theta;
+};
+
+// Everything before the walk: system table, keys, sort, tree, moments, groups.
+static void enqueue_pre_walk(gothic_ctx *c, const Systems &sy, const float4 *xyzm,
+                             const uint8_t *active, hipStream_t s) {
   Buffers &B = c->b;
   hipLaunchKernelGGL(ctl_reset_k, dim3(1), dim3(64), 0, s, B.ctl);
-  launch_bbox_keys(c, xyzm, n, s);
-  launch_radix_sort(c, n, s);
+  for (int f = 0; f < sy.nsys; f += kSysChunk) {
+    SysChunk ch;
+    memset(&ch, 0, sizeof(ch));
+    ch.first = f;
+    ch.count = std::min(kSysChunk, sy.nsys - f);
+    for (int t = 0; t <= ch.count; ++t) ch.off[t] = (uint32_t)sy.off[f + t];
+    for (int t = 0; t < ch.count; ++t) {
+      const float e = sy.eps[f + t];
+      ch.eps2[t] = e * e;
+      ch.theta[t] = sy.theta[f + t];
+      ch.inv_eps[t] = 1.0f / e;
+    }
+    hipLaunchKernelGGL(sys_upload_k, dim3(1), dim3(64), 0, s, ch, B.sys, B.soff);
+  }
+  const int64_t n = sy.n;
+  launch_bbox_keys(c, xyzm, n, sy.nsys, sy.max_n, s);
+  launch_radix_sort(c, n, sy.nsys, s);
   launch_permute(c, xyzm, active, n, s);
-  launch_build(c, n, s);
-  launch_moments(c, n, s);
+  launch_build(c, n, sy.nsys, s);
+  launch_moments(c, n, sy.nsys, s);
   launch_groups(c, n, s);
-  const bool timed = c->prm.timing && c->ev_used < (int)c->ev_start.size();
+}
+
+static void enqueue_walk(gothic_ctx *c, int64_t n, float4 *out, hipStream_t s, bool timed) {
+  timed = timed && c->prm.timing && c->ev_used < (int)c->ev_start.size();
   if (timed) (void)hipEventRecord(c->ev_start[c->ev_used], s);
-  launch_walk(c, n, eps, theta, out, s);
+  launch_walk(c, n, out, s);
   if (timed) (void)hipEventRecord(c->ev_stop[c->ev_used++], s);
+}
+
+static int enqueue_forces(gothic_ctx *c, const Systems &sy, const float4 *xyzm,
+                          const uint8_t *active, float4 *out, hipStream_t s) {
+  enqueue_pre_walk(c, sy, xyzm, active, s);
+  enqueue_walk(c, sy.n, out, s, true);
   return hip_check(hipGetLastError(), "kernel launch");
+}
+
+// Checks a batched description and drops empty systems.
+static int make_systems(int nsys, const int64_t *offsets, const float *eps, const float *theta,
+                        bool allow_empty, Systems *out) {
+  if (nsys < 1 || nsys > kMaxSys) return set_error(GOTHIC_EINVAL, "nsys must be in 1..65535");
+  if (!offsets || !eps || !theta)
+    return set_error(GOTHIC_EINVAL, "offsets, eps and theta must not be NULL");
+  if (offsets[0] != 0) return set_error(GOTHIC_EINVAL, "offsets[0] must be 0");
+  Systems sy;
+  sy.off.push_back(0);
+  for (int k = 0; k < nsys; ++k) {
+    const int64_t a = offsets[k], b = offsets[k + 1];
+    if (b < a) return set_error(GOTHIC_EINVAL, "offsets must be non-decreasing");
+    if (b >= (int64_t)1 << 31) return set_error(GOTHIC_EINVAL, "total particles must be < 2^31");
+    if (!(eps[k] > 0.f) || !std::isfinite(eps[k]))
+      return set_error(GOTHIC_EINVAL, "eps must be finite and > 0");
+    if (!(theta[k] >= 0.f && theta[k] < 1.f))
+      return set_error(GOTHIC_EINVAL, "theta must be in [0, 1)");
+    if (b == a) {
+      if (!allow_empty) return set_error(GOTHIC_EINVAL, "empty system");
+      continue;
+    }
+    sy.off.push_back(b);
+    sy.eps.push_back(eps[k]);
+    sy.theta.push_back(theta[k]);
+    sy.max_n = std::max(sy.max_n, b - a);
+  }
+  sy.nsys = (int)sy.eps.size();
+  sy.n = offsets[nsys];
+  *out = std::move(sy);
+  return GOTHIC_OK;
 }
 
 static void free_events(gothic_ctx *c) {
@@ -212,41 +319,59 @@ static int ensure_events(gothic_ctx *c) {
   return GOTHIC_OK;
 }
 
+static void free_graphs(gothic_ctx *c) {
+  SimGraphs &G = c->graphs;
+  for (auto &e : G.exec)
+    if (e) {
+      (void)hipGraphExecDestroy(e);
+      e = nullptr;
+    }
+  G.valid = false;
+}
+
 static void free_sim(gothic_ctx *c) {
   SimState &S = c->sim;
-  void *ptrs[] = {S.shadow, S.aold, S.anew, S.si, S.lev, S.act, S.sc};
+  void *ptrs[] = {S.shadow, S.aold, S.anew, S.si, S.lev, S.act, S.soff, S.ss, S.sc};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (S.sc_host) (void)hipHostFree(S.sc_host);
+  if (S.ss_host) (void)hipHostFree(S.ss_host);
   S = SimState();
+  ++c->generation;
 }
 
 // The force pipeline with argument checks done: capacity, enqueue, and in
 // check mode the synchronous flag check with grow-and-repeat.
-static int run_forces(gothic_ctx *c, int64_t n, const float4 *x4, float eps, float theta,
-                      const uint8_t *active, float4 *o4, hipStream_t s) {
+static int64_t nodes_wanted(gothic_ctx *c, int64_t n, int nsys) {
+  // typical trees hold ~0.25 n nodes at n_leaf = 16 and ~2-3 n at n_leaf = 1
+  return std::max<int64_t>(c->cap_nodes, c->prm.node_capacity > 0
+                                             ? c->prm.node_capacity
+                                             : n + 8 * (n / c->prm.n_leaf) + 1024 + nsys);
+}
+
+static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const uint8_t *active,
+                      float4 *o4, hipStream_t s) {
+  const int64_t n = sy.n;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(s, &cap);
   const bool capturing = cap != hipStreamCaptureStatusNone;
-  // typical trees hold ~0.25 n nodes at n_leaf = 16 and ~2-3 n at n_leaf = 1
-  const int64_t want_nodes = std::max<int64_t>(
-      c->cap_nodes, c->prm.node_capacity > 0 ? c->prm.node_capacity
-                                              : n + 8 * (n / c->prm.n_leaf) + 1024);
-  const bool must_grow = n > c->cap_n || want_nodes > c->cap_nodes || !c->b.spill ||
-                         walk_slots(c) != c->walk_waves ||
+  const int64_t want_nodes = nodes_wanted(c, n, sy.nsys);
+  const bool must_grow = n > c->cap_n || sy.nsys > c->cap_sys || want_nodes > c->cap_nodes ||
+                         !c->b.spill || walk_slots(c) != c->walk_waves ||
                          (c->prm.timing && c->ev_start.empty());
   if (capturing && must_grow)
     return set_error(GOTHIC_ECAPTURE, "scratch must grow for n = " + std::to_string(n) +
                                           "; make one uncaptured call of this size first");
-  int rc = ensure(c, n, want_nodes, c->spill_per_wave);
+  int rc = ensure(c, n, sy.nsys, want_nodes, c->spill_per_wave);
   if (rc) return rc;
   if ((rc = ensure_events(c))) return rc;
   c->last_n = n;
+  c->last_nsys = sy.nsys;
   c->last_stream = s;
   c->have_last = true;
   constexpr int kAttempts = 6;
   for (int attempt = 0; attempt < kAttempts; ++attempt) {
-    if ((rc = enqueue_forces(c, n, x4, eps, theta, active, o4, s))) return rc;
+    if ((rc = enqueue_forces(c, sy, x4, active, o4, s))) return rc;
     if (!c->prm.check || capturing) return GOTHIC_OK;
     if ((rc = hip_check(hipMemcpyAsync(c->b.ctl_host, c->b.ctl, sizeof(Ctl),
                                        hipMemcpyDeviceToHost, s), "hipMemcpyAsync")))
@@ -266,7 +391,7 @@ static int run_forces(gothic_ctx *c, int64_t n, const float4 *x4, float eps, flo
     const int64_t nodes =
         (f & kFlagNodeOverflow) ? std::max<int64_t>(2 * c->cap_nodes, 2 * need) : c->cap_nodes;
     const int64_t spill = (f & kFlagSpillOverflow) ? 4 * c->spill_per_wave : c->spill_per_wave;
-    if ((rc = ensure(c, n, nodes, spill))) return rc;
+    if ((rc = ensure(c, n, sy.nsys, nodes, spill))) return rc;
   }
   const Ctl &h = *c->b.ctl_host;
   std::string msg = "node or frontier capacity still exceeded after growing (flags " +
@@ -294,6 +419,7 @@ void gothic_default_params(gothic_params *p) {
   p->check = 1;
   p->timing = 0;
   p->r_crit = -0.0625f;
+  p->graph = 0;
   p->node_capacity = 0;
 }
 
@@ -328,6 +454,8 @@ int gothic_destroy(gothic_ctx *c) {
   {
     DeviceGuard guard(c->device);
     (void)hipDeviceSynchronize();
+    free_graphs(c);
+    if (c->graphs.cap_stream) (void)hipStreamDestroy(c->graphs.cap_stream);
     free_sim(c);
     free_events(c);
     free_all(c);
@@ -341,6 +469,7 @@ int gothic_set_params(gothic_ctx *c, const gothic_params *p) {
   int rc = validate_params(p);
   if (rc) return rc;
   c->prm = *p;
+  ++c->generation;
   return GOTHIC_OK;
 }
 
@@ -361,7 +490,27 @@ int gothic_tree_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, f
   if ((const void *)xyzm == (const void *)acc_pot)
     return set_error(GOTHIC_EINVAL, "xyzm and acc_pot must not overlap");
   DeviceGuard guard(c->device);
-  return run_forces(c, n, reinterpret_cast<const float4 *>(xyzm), eps, theta, active,
+  const int64_t off[2] = {0, n};
+  Systems sy;
+  int rc = make_systems(1, off, &eps, &theta, false, &sy);
+  if (rc) return rc;
+  return run_forces(c, sy, reinterpret_cast<const float4 *>(xyzm), active,
+                    reinterpret_cast<float4 *>(acc_pot), reinterpret_cast<hipStream_t>(stream));
+}
+
+int gothic_tree_forces_batched(gothic_ctx *c, int nsys, const int64_t *offsets, const float *xyzm,
+                               const float *eps, const float *theta, const uint8_t *active,
+                               float *acc_pot, void *stream) {
+  if (!c) return set_error(GOTHIC_EINVAL, "context is NULL");
+  Systems sy;
+  int rc = make_systems(nsys, offsets, eps, theta, true, &sy);
+  if (rc) return rc;
+  if (sy.n == 0) return GOTHIC_OK;
+  if (!xyzm || !acc_pot) return set_error(GOTHIC_EINVAL, "xyzm and acc_pot must not be NULL");
+  if ((const void *)xyzm == (const void *)acc_pot)
+    return set_error(GOTHIC_EINVAL, "xyzm and acc_pot must not overlap");
+  DeviceGuard guard(c->device);
+  return run_forces(c, sy, reinterpret_cast<const float4 *>(xyzm), active,
                     reinterpret_cast<float4 *>(acc_pot), reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -390,6 +539,7 @@ int gothic_get_stats(gothic_ctx *c, gothic_stats *out) {
   out->node_interactions = (int64_t)h.node_interactions;
   out->mac_tests = (int64_t)h.mac_tests;
   out->flags = (int32_t)h.flags;
+  out->n_systems = c->last_nsys;
   if (h.flags & kFlagNonFinite) return set_error(GOTHIC_ENONFINITE, "non-finite position or mass");
   if (h.flags & (kFlagNodeOverflow | kFlagSpillOverflow))
     return set_error(GOTHIC_EOVERFLOW, "capacity exceeded in the last evaluation");
@@ -421,12 +571,14 @@ int gothic_get_keys(gothic_ctx *c, uint64_t *keys_sorted, uint32_t *perm, double
   if (rc) return rc;
   hipStream_t s = c->last_stream;
   const size_t n = (size_t)c->last_n;
-  if ((rc = d2d(keys_sorted, c->b.keyA, n * 8, s)) || (rc = d2d(perm, c->b.idxA, n * 4, s)) ||
-      (rc = d2d(cube, c->b.ctl->cube, 4 * sizeof(double), s)))
+  if ((rc = d2d(keys_sorted, c->b.keyA, n * 8, s)) || (rc = d2d(perm, c->b.idxA, n * 4, s)))
     return rc;
+  if (cube) {
+    hipLaunchKernelGGL(extract_cubes_k, dim3(1), dim3(256), 0, s, c->last_nsys, c->b.sys, cube);
+    if ((rc = hip_check(hipGetLastError(), "extract_cubes_k"))) return rc;
+  }
   return hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
-
 int gothic_get_tree(gothic_ctx *c, uint32_t *first, uint32_t *count, uint32_t *child_first,
                     uint8_t *n_child, uint8_t *level) {
   if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
@@ -495,45 +647,66 @@ int gothic_get_walk_time(gothic_ctx *c, double *ms_total, int64_t *launches) {
   return GOTHIC_OK;
 }
 
-int gothic_sim_bind(gothic_ctx *c, int64_t n, double *pos, double *vel, const float *mass,
-                    float eps, float theta, double eta, int kmax, int shared_step, void *stream) {
-  if (!c) return set_error(GOTHIC_EINVAL, "context is NULL");
-  if (n <= 0 || n >= (int64_t)1 << 31) return set_error(GOTHIC_EINVAL, "n must be in [1, 2^31)");
+static int sim_bind_impl(gothic_ctx *c, const Systems &sy, double *pos, double *vel,
+                         const float *mass, double eta, int kmax, int shared_step,
+                         hipStream_t s) {
   if (!pos || !vel || !mass) return set_error(GOTHIC_EINVAL, "pos, vel and mass must not be NULL");
-  if (!(eps > 0.f) || !std::isfinite(eps)) return set_error(GOTHIC_EINVAL, "eps must be finite and > 0");
-  if (!(theta >= 0.f && theta < 1.f)) return set_error(GOTHIC_EINVAL, "theta must be in [0, 1)");
   if (!(eta > 0.0) || !std::isfinite(eta)) return set_error(GOTHIC_EINVAL, "eta must be finite and > 0");
   if (kmax < 0 || kmax > 30) return set_error(GOTHIC_EINVAL, "kmax must be in 0..30");
-  DeviceGuard guard(c->device);
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   SimState &S = c->sim;
+  const int64_t n = sy.n;
   int rc;
-  if (n > S.cap || !S.sc) {
+  free_graphs(c);
+  S.bound = false;
+  if (n > S.cap || sy.nsys > S.cap_sys || !S.sc) {
     free_sim(c);
+    const int cs = std::max(sy.nsys, 64);
     if ((rc = dev_alloc(&S.shadow, n)) || (rc = dev_alloc(&S.aold, n)) ||
         (rc = dev_alloc(&S.anew, n)) || (rc = dev_alloc(&S.si, n)) ||
         (rc = dev_alloc(&S.lev, n)) || (rc = dev_alloc(&S.act, n)) ||
+        (rc = dev_alloc(&S.soff, cs + 1)) || (rc = dev_alloc(&S.ss, cs)) ||
         (rc = dev_alloc(&S.sc, 1)))
       return rc;
     if ((rc = hip_check(hipHostMalloc(reinterpret_cast<void **>(&S.sc_host), sizeof(SimCtl),
+                                      hipHostMallocDefault), "hipHostMalloc")) ||
+        (rc = hip_check(hipHostMalloc(reinterpret_cast<void **>(&S.ss_host), sizeof(SimSys) * cs,
                                       hipHostMallocDefault), "hipHostMalloc")))
       return rc;
     S.cap = n;
+    S.cap_sys = cs;
   }
   S.n = n;
+  S.nsys = sy.nsys;
   S.pos = pos;
   S.vel = vel;
   S.mass = mass;
-  S.eps = eps;
-  S.theta = theta;
-  sim_launch_setup(c, s, eps, eta, kmax, shared_step ? 1 : 0);
+  S.offsets = sy.off;
+  S.eps = sy.eps;
+  S.theta = sy.theta;
+  ++c->generation;
+  // per-system clocks and offsets (the host copies stay alive until the
+  // stream has synchronised)
+  for (int k = 0; k < sy.nsys; ++k) {
+    S.ss_host[k].dt_fine = 1.0;
+    S.ss_host[k].dt_max = 1.0;
+    S.ss_host[k].eps = (double)sy.eps[k];
+    S.ss_host[k].min_dt_bits = ~0ull;
+  }
+  std::vector<uint32_t> off32(sy.off.begin(), sy.off.end());
+  if ((rc = hip_check(hipMemcpyAsync(S.ss, S.ss_host, sizeof(SimSys) * sy.nsys,
+                                     hipMemcpyHostToDevice, s), "hipMemcpyAsync")) ||
+      (rc = hip_check(hipMemcpyAsync(S.soff, off32.data(), 4 * off32.size(),
+                                     hipMemcpyHostToDevice, s), "hipMemcpyAsync")) ||
+      (rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize")))
+    return rc;
+  sim_launch_setup(c, s, eta, kmax, shared_step ? 1 : 0);
   sim_launch_reset(c, s);
   sim_launch_shadow(c, s);
   if ((rc = hip_check(hipGetLastError(), "kernel launch"))) return rc;
   // t = 0 forces on every particle (synchronous, checked)
   const int saved = c->prm.check;
   c->prm.check = 1;
-  rc = run_forces(c, n, S.shadow, eps, theta, nullptr, S.anew, s);
+  rc = run_forces(c, sy, S.shadow, nullptr, S.anew, s);
   c->prm.check = saved;
   if (rc) return rc;
   sim_launch_init(c, s);
@@ -544,14 +717,115 @@ int gothic_sim_bind(gothic_ctx *c, int64_t n, double *pos, double *vel, const fl
   return GOTHIC_OK;
 }
 
+int gothic_sim_bind(gothic_ctx *c, int64_t n, double *pos, double *vel, const float *mass,
+                    float eps, float theta, double eta, int kmax, int shared_step, void *stream) {
+  if (!c) return set_error(GOTHIC_EINVAL, "context is NULL");
+  if (n <= 0 || n >= (int64_t)1 << 31) return set_error(GOTHIC_EINVAL, "n must be in [1, 2^31)");
+  const int64_t off[2] = {0, n};
+  Systems sy;
+  int rc = make_systems(1, off, &eps, &theta, false, &sy);
+  if (rc) return rc;
+  DeviceGuard guard(c->device);
+  return sim_bind_impl(c, sy, pos, vel, mass, eta, kmax, shared_step,
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+int gothic_sim_bind_batched(gothic_ctx *c, int nsys, const int64_t *offsets, double *pos,
+                            double *vel, const float *mass, const float *eps,
+                            const float *theta, double eta, int kmax, int shared_step,
+                            void *stream) {
+  if (!c) return set_error(GOTHIC_EINVAL, "context is NULL");
+  Systems sy;
+  int rc = make_systems(nsys, offsets, eps, theta, false, &sy);
+  if (rc) return rc;
+  DeviceGuard guard(c->device);
+  return sim_bind_impl(c, sy, pos, vel, mass, eta, kmax, shared_step,
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+static Systems sim_systems(const SimState &S) {
+  Systems sy;
+  sy.nsys = S.nsys;
+  sy.n = S.n;
+  sy.off = S.offsets;
+  sy.eps = S.eps;
+  sy.theta = S.theta;
+  for (int k = 0; k < S.nsys; ++k) sy.max_n = std::max(sy.max_n, S.offsets[k + 1] - S.offsets[k]);
+  return sy;
+}
+
+// Capture the three segments of a sub-step (before the walk, the walk, after
+// it) on the context's own stream; buffers are already sized by the bind.
+static int capture_step(gothic_ctx *c) {
+  SimGraphs &G = c->graphs;
+  SimState &S = c->sim;
+  free_graphs(c);
+  int rc;
+  if (!G.cap_stream &&
+      (rc = hip_check(hipStreamCreateWithFlags(&G.cap_stream, hipStreamNonBlocking),
+                      "hipStreamCreateWithFlags")))
+    return rc;
+  const Systems sy = sim_systems(S);
+  if (sy.n > c->cap_n || sy.nsys > c->cap_sys || nodes_wanted(c, sy.n, sy.nsys) > c->cap_nodes ||
+      walk_slots(c) != c->walk_waves)
+    return set_error(GOTHIC_ECAPTURE, "scratch is not sized for this system; bind again");
+  for (int seg = 0; seg < 3; ++seg) {
+    hipGraph_t g = nullptr;
+    if ((rc = hip_check(hipStreamBeginCapture(G.cap_stream, hipStreamCaptureModeThreadLocal),
+                        "hipStreamBeginCapture")))
+      return rc;
+    if (seg == 0) {
+      sim_launch_predict(c, G.cap_stream);
+      enqueue_pre_walk(c, sy, S.shadow, S.act, G.cap_stream);
+    } else if (seg == 1) {
+      enqueue_walk(c, sy.n, S.anew, G.cap_stream, false);
+    } else {
+      sim_launch_correct(c, G.cap_stream);
+    }
+    const int lrc = hip_check(hipGetLastError(), "kernel launch");
+    rc = hip_check(hipStreamEndCapture(G.cap_stream, &g), "hipStreamEndCapture");
+    if (lrc || rc) {
+      if (g) (void)hipGraphDestroy(g);
+      free_graphs(c);
+      return lrc ? lrc : rc;
+    }
+    rc = hip_check(hipGraphInstantiate(&G.exec[seg], g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    (void)hipGraphDestroy(g);
+    if (rc) {
+      free_graphs(c);
+      return rc;
+    }
+  }
+  G.generation = c->generation;
+  G.valid = true;
+  return GOTHIC_OK;
+}
+
 int gothic_sim_step(gothic_ctx *c, void *stream) {
   if (!c) return set_error(GOTHIC_EINVAL, "context is NULL");
   SimState &S = c->sim;
   if (!S.bound) return set_error(GOTHIC_EINVAL, "no system bound (gothic_sim_bind)");
   DeviceGuard guard(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int rc;
+  if (c->prm.graph && !c->prm.check) {
+    if ((rc = ensure_events(c))) return rc;
+    if (!c->graphs.valid || c->graphs.generation != c->generation)
+      if ((rc = capture_step(c))) return rc;
+    c->last_n = S.n;
+    c->last_nsys = S.nsys;
+    c->last_stream = s;
+    c->have_last = true;
+    SimGraphs &G = c->graphs;
+    if ((rc = hip_check(hipGraphLaunch(G.exec[0], s), "hipGraphLaunch"))) return rc;
+    const bool timed = c->prm.timing && c->ev_used < (int)c->ev_start.size();
+    if (timed) (void)hipEventRecord(c->ev_start[c->ev_used], s);
+    if ((rc = hip_check(hipGraphLaunch(G.exec[1], s), "hipGraphLaunch"))) return rc;
+    if (timed) (void)hipEventRecord(c->ev_stop[c->ev_used++], s);
+    return hip_check(hipGraphLaunch(G.exec[2], s), "hipGraphLaunch");
+  }
   sim_launch_predict(c, s);
-  int rc = run_forces(c, S.n, S.shadow, S.eps, S.theta, S.act, S.anew, s);
+  rc = run_forces(c, sim_systems(S), S.shadow, S.act, S.anew, s);
   if (rc) return rc;
   sim_launch_correct(c, s);
   return hip_check(hipGetLastError(), "kernel launch");
@@ -565,31 +839,54 @@ int gothic_sim_reset_counters(gothic_ctx *c, void *stream) {
   return hip_check(hipGetLastError(), "kernel launch");
 }
 
+static int sim_fetch(gothic_ctx *c) {
+  SimState &S = c->sim;
+  hipStream_t s = c->last_stream;
+  int rc;
+  if ((rc = hip_check(hipMemcpyAsync(S.sc_host, S.sc, sizeof(SimCtl), hipMemcpyDeviceToHost, s),
+                      "hipMemcpyAsync")) ||
+      (rc = hip_check(hipMemcpyAsync(S.ss_host, S.ss, sizeof(SimSys) * S.nsys,
+                                     hipMemcpyDeviceToHost, s), "hipMemcpyAsync")))
+    return rc;
+  return hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
 int gothic_sim_get_info(gothic_ctx *c, gothic_sim_info *out) {
   if (!c || !out) return set_error(GOTHIC_EINVAL, "NULL argument");
   SimState &S = c->sim;
   if (!S.bound) return set_error(GOTHIC_EINVAL, "no system bound (gothic_sim_bind)");
   DeviceGuard guard(c->device);
-  hipStream_t s = c->last_stream;
-  sim_launch_hist(c, s);
-  int rc;
-  if ((rc = hip_check(hipMemcpyAsync(S.sc_host, S.sc, sizeof(SimCtl), hipMemcpyDeviceToHost, s),
-                      "hipMemcpyAsync")) ||
-      (rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize")))
-    return rc;
+  sim_launch_hist(c, c->last_stream);
+  int rc = sim_fetch(c);
+  if (rc) return rc;
   const SimCtl &h = *S.sc_host;
   memset(out, 0, sizeof(*out));
   out->n = S.n;
   out->substep = h.s;
-  out->dt_fine = h.dt_fine;
-  out->dt_max = h.dt_max;
-  out->t = (double)h.s * h.dt_fine;
+  out->dt_fine = S.ss_host[0].dt_fine;
+  out->dt_max = S.ss_host[0].dt_max;
+  out->t = (double)h.s * S.ss_host[0].dt_fine;
   out->steps = (int64_t)h.steps;
   out->last_active = (int64_t)h.last_active;
   out->active_total = (int64_t)h.active_total;
   out->interactions_total = (int64_t)h.inter_total;
   out->node_interactions_total = (int64_t)h.node_inter_total;
   for (int k = 0; k < 32; ++k) out->level_count[k] = (int64_t)h.level_count[k];
+  return GOTHIC_OK;
+}
+
+int gothic_sim_get_steps(gothic_ctx *c, int nsys, double *dt_fine, double *dt_max) {
+  if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
+  SimState &S = c->sim;
+  if (!S.bound) return set_error(GOTHIC_EINVAL, "no system bound (gothic_sim_bind)");
+  if (nsys != S.nsys) return set_error(GOTHIC_EINVAL, "nsys differs from the bound systems");
+  DeviceGuard guard(c->device);
+  int rc = sim_fetch(c);
+  if (rc) return rc;
+  for (int k = 0; k < nsys; ++k) {
+    if (dt_fine) dt_fine[k] = S.ss_host[k].dt_fine;
+    if (dt_max) dt_max[k] = S.ss_host[k].dt_max;
+  }
   return GOTHIC_OK;
 }
 
@@ -604,22 +901,6 @@ int gothic_sim_get_state(gothic_ctx *c, float *acc_pot, uint8_t *levels, int64_t
       (rc = d2d(last, S.si, (size_t)S.n * 8, s)))
     return rc;
   return hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-}
-
-int gothic_tree_forces_batched(gothic_ctx *c, int nsys, const int64_t *offsets, const float *xyzm,
-                               const float *eps, const float *theta, const uint8_t *active,
-                               float *acc_pot, void *stream) {
-  if (!c || nsys < 0 || (nsys > 0 && (!offsets || !eps || !theta)))
-    return set_error(GOTHIC_EINVAL, "bad batched arguments");
-  // one evaluation per system, in stream order
-  for (int sIdx = 0; sIdx < nsys; ++sIdx) {
-    const int64_t a = offsets[sIdx], b = offsets[sIdx + 1];
-    if (b < a) return set_error(GOTHIC_EINVAL, "offsets must be non-decreasing");
-    int rc = gothic_tree_forces(c, b - a, xyzm + 4 * a, eps[sIdx], theta[sIdx],
-                                active ? active + a : nullptr, acc_pot + 4 * a, stream);
-    if (rc) return rc;
-  }
-  return GOTHIC_OK;
 }
 
 }  // extern "C"

@@ -29,17 +29,37 @@ struct Ctl {
   unsigned n_active;
   unsigned n_groups;
   unsigned lvl_start[kMaxLevels + 2];  // nodes of level l: [lvl_start[l], lvl_start[l+1])
-  unsigned work;                       // (unused; kept for layout stability)
+  unsigned nsys;                       // systems of the evaluation (roots 0 .. nsys-1)
   unsigned xwork[8];                   // per-XCD group counters of the persistent walk
   unsigned scan_total;                 // scratch: total of the last scan
   unsigned pad0, pad1;
-  double cube[4];                      // x_min, y_min, z_min, L
   unsigned long long node_entries;     // summed over groups
   unsigned long long part_entries;
   unsigned long long interactions;     // summed over active i
   unsigned long long node_interactions;
   unsigned long long mac_tests;
 };
+
+// One independent system of a (batched) evaluation.  Its particles are the
+// index range [soff[s], soff[s+1]) both in the caller's order and in key order
+// (the sort orders by system first), and its tree root is node s.
+struct SysRec {
+  double cube[4];               // x_min, y_min, z_min, L of its bounding cube
+  float eps2, theta, inv_eps;   // softening^2, opening angle, 1/softening
+  float pad;
+};
+
+// Largest s with soff[s] <= k (k inside [soff[0], soff[nsys])): binary search
+// over the system offsets, which stay in the caches.
+__device__ __forceinline__ unsigned sys_of(const uint32_t *__restrict__ soff, unsigned nsys,
+                                           uint32_t k) {
+  unsigned lo = 0, hi = nsys;  // soff[lo] <= k < soff[hi]
+  while (hi - lo > 1) {
+    const unsigned mid = (lo + hi) >> 1;
+    if (soff[mid] <= k) lo = mid; else hi = mid;
+  }
+  return lo;
+}
 
 struct Buffers {
   // particles (capacity cap_n)
@@ -68,6 +88,9 @@ struct Buffers {
   float *bbox_part = nullptr;     // bbox partials
   // walk spill area
   uint32_t *spill = nullptr;
+  // systems (capacity cap_sys)
+  SysRec *sys = nullptr;
+  uint32_t *soff = nullptr;       // [nsys + 1] particle offsets
   // control
   Ctl *ctl = nullptr;
   Ctl *ctl_host = nullptr;        // pinned mirror for read-back
@@ -76,24 +99,43 @@ struct Buffers {
 // Block-step driver state on the device (sim.hip)
 struct SimCtl {
   long long s;                  // current finest sub-step
-  double dt_fine, dt_max, eps, eta;
+  double eta;
   int kmax, shared;
-  unsigned long long min_dt_bits;
   unsigned long long n_active;  // due particles of the step in progress
   unsigned long long last_active, steps, inter_total, node_inter_total, active_total;
   unsigned long long level_count[32];
 };
 
+// Per-system clock of the block-step driver: every system advances one of
+// its own finest sub-steps per driver step.
+struct SimSys {
+  double dt_fine, dt_max, eps;
+  unsigned long long min_dt_bits;
+};
+
 struct SimState {
   bool bound = false;
   int64_t n = 0, cap = 0;
+  int nsys = 0, cap_sys = 0;
   double *pos = nullptr, *vel = nullptr;  // caller-owned, float64 [n][3]
   const float *mass = nullptr;            // caller-owned [n]
-  float eps = 0.f, theta = 0.f;
+  std::vector<int64_t> offsets;           // host copy, nsys + 1
+  std::vector<float> eps, theta;          // host copies, nsys
   float4 *shadow = nullptr, *aold = nullptr, *anew = nullptr;
   int64_t *si = nullptr;
   uint8_t *lev = nullptr, *act = nullptr;
+  uint32_t *soff = nullptr;               // device copy of the offsets
+  SimSys *ss = nullptr, *ss_host = nullptr;
   SimCtl *sc = nullptr, *sc_host = nullptr;
+};
+
+// Captured sub-step of the block-step driver (params.graph): before the
+// walk, the walk, after the walk (split so the walk can still be timed).
+struct SimGraphs {
+  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;
+  uint64_t generation = 0;
+  bool valid = false;
 };
 
 }  // namespace gothic
@@ -102,18 +144,21 @@ struct gothic_ctx {
   int device = 0;
   int num_cus = 256;
   gothic_params prm{};
-  int64_t cap_n = 0, cap_nodes = 0, cap_groups = 0, cap_hist = 0;
+  int64_t cap_n = 0, cap_nodes = 0, cap_groups = 0, cap_hist = 0, cap_sys = 0;
   int64_t spill_per_wave = 0;
   int walk_waves = 0;             // persistent walk waves (slots)
   gothic::Buffers b;
+  uint64_t generation = 1;        // bumped whenever a device buffer or a parameter changes
   // last evaluation
   int64_t last_n = 0;
+  int last_nsys = 0;
   hipStream_t last_stream = nullptr;
   bool have_last = false;
   // walk-kernel timing (params.timing): event pairs recorded around each walk
   std::vector<hipEvent_t> ev_start, ev_stop;
   int ev_used = 0;
   gothic::SimState sim;
+  gothic::SimGraphs graphs;
 };
 
 namespace gothic {
@@ -130,25 +175,27 @@ void scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n_host, const uns
                     hipStream_t s);
 int scan_blocks();
 
-// keys.hip
-void launch_bbox_keys(gothic_ctx *c, const float4 *xyzm, int64_t n, hipStream_t s);
-// sort.hip
-void launch_radix_sort(gothic_ctx *c, int64_t n, hipStream_t s);  // keyA/idxA -> keyA/idxA
+// keys.hip (nsys systems, the largest holding max_n particles)
+void launch_bbox_keys(gothic_ctx *c, const float4 *xyzm, int64_t n, int nsys, int64_t max_n,
+                      hipStream_t s);
+int bbox_partials(int nsys, int64_t max_n);
+// sort.hip: (system, key, index) order in keyA / idxA
+void launch_radix_sort(gothic_ctx *c, int64_t n, int nsys, hipStream_t s);
+bool keys_to_B(int nsys);  // the key kernel writes keyB / idxB (odd pass count)
 int64_t radix_hist_entries(int64_t n);
 // tree.hip
 void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active, int64_t n,
                     hipStream_t s);
-void launch_build(gothic_ctx *c, int64_t n, hipStream_t s);
+void launch_build(gothic_ctx *c, int64_t n, int nsys, hipStream_t s);
 // moments.hip
-void launch_moments(gothic_ctx *c, int64_t n, hipStream_t s);
+void launch_moments(gothic_ctx *c, int64_t n, int nsys, hipStream_t s);
 // groups.hip
 void launch_groups(gothic_ctx *c, int64_t n, hipStream_t s);
 // walk.hip
-void launch_walk(gothic_ctx *c, int64_t n, float eps, float theta, float4 *acc_pot,
-                 hipStream_t s);
+void launch_walk(gothic_ctx *c, int64_t n, float4 *acc_pot, hipStream_t s);
 int walk_slots(gothic_ctx *c);
 // sim.hip
-void sim_launch_setup(gothic_ctx *c, hipStream_t s, double eps, double eta, int kmax, int shared);
+void sim_launch_setup(gothic_ctx *c, hipStream_t s, double eta, int kmax, int shared);
 void sim_launch_reset(gothic_ctx *c, hipStream_t s);
 void sim_launch_shadow(gothic_ctx *c, hipStream_t s);
 void sim_launch_init(gothic_ctx *c, hipStream_t s);

@@ -34,20 +34,30 @@ __device__ __forceinline__ double gap2(float4 p, float4 q) {
   return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
 }
 
-// brk[a] = 1 where a new run starts (first active particle or a gap > r_crit)
+// brk[a] = 1 where a new run starts (first active particle of a system, or a
+// gap > r_crit; a negative r_crit is that fraction of the system's cube side)
 __global__ void __launch_bounds__(256)
 group_breaks_k(int64_t n, float r_crit, const Ctl *__restrict__ ctl,
+               const uint32_t *__restrict__ soff, const SysRec *__restrict__ sys,
                const uint32_t *__restrict__ alist, const float4 *__restrict__ pos,
                uint32_t *__restrict__ brk) {
-  const unsigned na = ctl->n_active;
-  const double rc = r_crit < 0.f ? (double)(-r_crit) * ctl->cube[3] : (double)r_crit;
-  const double rc2 = __dmul_rn(rc, rc);
+  const unsigned na = ctl->n_active, nsys = ctl->nsys;
   for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < na;
        a += (int64_t)gridDim.x * blockDim.x) {
     unsigned b = (a == 0);
-    if (!b && rc > 0.0) {
+    if (!b) {
       const uint32_t i = alist[a], j = alist[a - 1];
-      b = (i < n && j < n) ? (gap2(pos[i], pos[j]) > rc2) : 1u;
+      if (i < n && j < n) {
+        const unsigned si = sys_of(soff, nsys, i);
+        if (si != sys_of(soff, nsys, j)) {
+          b = 1u;
+        } else {
+          const double rc = r_crit < 0.f ? (double)(-r_crit) * sys[si].cube[3] : (double)r_crit;
+          b = (rc > 0.0 && gap2(pos[i], pos[j]) > __dmul_rn(rc, rc)) ? 1u : 0u;
+        }
+      } else {
+        b = 1u;
+      }
     }
     brk[a] = b;
   }
@@ -126,8 +136,8 @@ void launch_groups(gothic_ctx *c, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(compact_k, dim3(g), dim3(256), 0, s, n, c->prm.group_size, B.flag, B.flag2,
                      B.alist, B.ctl);
   // runs between gaps > r_crit (flag: run breaks, flag2: run index, gA: run starts)
-  hipLaunchKernelGGL(group_breaks_k, dim3(g), dim3(256), 0, s, n, c->prm.r_crit, B.ctl, B.alist,
-                     B.pos, B.flag);
+  hipLaunchKernelGGL(group_breaks_k, dim3(g), dim3(256), 0, s, n, c->prm.r_crit, B.ctl, B.soff,
+                     B.sys, B.alist, B.pos, B.flag);
   scan_exclusive(B.flag, B.flag2, 0, na_dev, nullptr, n, &B.ctl->scan_total, B.part, s);
   hipLaunchKernelGGL(group_runs_k, dim3(g), dim3(256), 0, s, B.ctl, B.flag, B.flag2, B.gA);
   // groups: every G-th particle of a run starts one (gB: starts, flag: group index)

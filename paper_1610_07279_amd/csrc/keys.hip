@@ -81,17 +81,20 @@ __host__ __device__ __forceinline__ uint64_t spread3(uint64_t v) {
 }
 
 // ---------------------------------------------------------------- bbox
+// Grid (partials per system, systems): workgroup (b, s) reduces every
+// gridDim.x-th tile of system s.
 __device__ __forceinline__ bool finite4(float4 p) {
   return isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w);
 }
 
 __global__ void __launch_bounds__(kBboxThreads)
-bbox_partial_k(const float4 *__restrict__ xyzm, int64_t n, float *__restrict__ part,
-               Ctl *ctl) {
+bbox_partial_k(const float4 *__restrict__ xyzm, const uint32_t *__restrict__ soff,
+               float *__restrict__ part, Ctl *ctl) {
+  const int64_t i0 = soff[blockIdx.y], i1 = soff[blockIdx.y + 1];
   float lo0 = FLT_MAX, lo1 = FLT_MAX, lo2 = FLT_MAX;
   float hi0 = -FLT_MAX, hi1 = -FLT_MAX, hi2 = -FLT_MAX;
   bool bad = false;
-  for (int64_t i = (int64_t)blockIdx.x * kBboxThreads + threadIdx.x; i < n;
+  for (int64_t i = i0 + (int64_t)blockIdx.x * kBboxThreads + threadIdx.x; i < i1;
        i += (int64_t)gridDim.x * kBboxThreads) {
     const float4 p = xyzm[i];
     bad |= !finite4(p);
@@ -112,17 +115,19 @@ bbox_partial_k(const float4 *__restrict__ xyzm, int64_t n, float *__restrict__ p
     float v = sh[0][threadIdx.x];
     for (int k = 1; k < kBboxThreads / 64; ++k)
       v = threadIdx.x < 3 ? fminf(v, sh[k][threadIdx.x]) : fmaxf(v, sh[k][threadIdx.x]);
-    part[blockIdx.x * 6 + threadIdx.x] = v;
+    part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 6 + threadIdx.x] = v;
   }
 }
 
+// one wave per system
 __global__ void __launch_bounds__(64) bbox_final_k(const float *__restrict__ part, int nblk,
-                                                   Ctl *ctl) {
+                                                   SysRec *__restrict__ sys) {
+  const float *ps = part + (int64_t)blockIdx.x * nblk * 6;
   float lo[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, hi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
   for (int b = lane_id(); b < nblk; b += 64)
     for (int a = 0; a < 3; ++a) {
-      lo[a] = fminf(lo[a], part[b * 6 + a]);
-      hi[a] = fmaxf(hi[a], part[b * 6 + 3 + a]);
+      lo[a] = fminf(lo[a], ps[b * 6 + a]);
+      hi[a] = fmaxf(hi[a], ps[b * 6 + 3 + a]);
     }
   for (int a = 0; a < 3; ++a) {
     lo[a] = wave_min(lo[a]);
@@ -140,24 +145,28 @@ __global__ void __launch_bounds__(64) bbox_final_k(const float *__restrict__ par
       const double f = frexp(ext, &ex);
       L = (f == 0.5) ? ext : ldexp(1.0, ex);
     }
-    for (int a = 0; a < 3; ++a) ctl->cube[a] = (double)lo[a];
-    ctl->cube[3] = L;
+    SysRec &r = sys[blockIdx.x];
+    for (int a = 0; a < 3; ++a) r.cube[a] = (double)lo[a];
+    r.cube[3] = L;
   }
 }
 
 // ---------------------------------------------------------------- keys
+// Grid (workgroups per system, systems).
 __global__ void __launch_bounds__(256)
-keys_k(const float4 *__restrict__ xyzm, int64_t n, int key_kind, const Ctl *__restrict__ ctl,
-       uint64_t *__restrict__ keys, uint32_t *__restrict__ idx) {
+keys_k(const float4 *__restrict__ xyzm, const uint32_t *__restrict__ soff, int key_kind,
+       const SysRec *__restrict__ sys, uint64_t *__restrict__ keys, uint32_t *__restrict__ idx) {
   __shared__ unsigned short tab[48 * 8];
   if (key_kind == GOTHIC_KEY_PEANO_HILBERT) {
     for (int t = threadIdx.x; t < 48 * 8; t += blockDim.x) tab[t] = kPh.e[t];
     __syncthreads();
   }
-  const double x0 = ctl->cube[0], y0 = ctl->cube[1], z0 = ctl->cube[2];
-  const double scale = ldexp(1.0, kNlev) / ctl->cube[3];
+  const int64_t i0 = soff[blockIdx.y], i1 = soff[blockIdx.y + 1];
+  const SysRec &r = sys[blockIdx.y];
+  const double x0 = r.cube[0], y0 = r.cube[1], z0 = r.cube[2];
+  const double scale = ldexp(1.0, kNlev) / r.cube[3];
   const uint64_t qmax = (1ull << kNlev) - 1;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+  for (int64_t i = i0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < i1;
        i += (int64_t)gridDim.x * blockDim.x) {
     const float4 p = xyzm[i];
     const double tx = floor(__dmul_rn(__dsub_rn((double)p.x, x0), scale));
@@ -186,16 +195,30 @@ keys_k(const float4 *__restrict__ xyzm, int64_t n, int key_kind, const Ctl *__re
   }
 }
 
-void launch_bbox_keys(gothic_ctx *c, const float4 *xyzm, int64_t n, hipStream_t s) {
-  int nblk = (int)((n + kBboxThreads - 1) / kBboxThreads);
-  nblk = nblk < 1 ? 1 : (nblk > kBboxBlocks ? kBboxBlocks : nblk);
-  hipLaunchKernelGGL(bbox_partial_k, dim3(nblk), dim3(kBboxThreads), 0, s, xyzm, n,
+// partial bounding boxes per system: enough workgroups to cover the largest
+// system, about kBboxBlocks in all
+int bbox_partials(int nsys, int64_t max_n) {
+  int64_t b = (max_n + kBboxThreads - 1) / kBboxThreads;
+  int64_t cap = kBboxBlocks / (nsys > 0 ? nsys : 1);
+  if (cap < 1) cap = 1;
+  if (b > cap) b = cap;
+  return (int)(b < 1 ? 1 : b);
+}
+
+void launch_bbox_keys(gothic_ctx *c, const float4 *xyzm, int64_t n, int nsys, int64_t max_n,
+                      hipStream_t s) {
+  (void)n;
+  const int nb = bbox_partials(nsys, max_n);
+  hipLaunchKernelGGL(bbox_partial_k, dim3(nb, nsys), dim3(kBboxThreads), 0, s, xyzm, c->b.soff,
                      c->b.bbox_part, c->b.ctl);
-  hipLaunchKernelGGL(bbox_final_k, dim3(1), dim3(64), 0, s, c->b.bbox_part, nblk, c->b.ctl);
-  int64_t kb = (n + 255) / 256;
-  int kblk = (int)(kb > 8192 ? 8192 : (kb < 1 ? 1 : kb));
-  hipLaunchKernelGGL(keys_k, dim3(kblk), dim3(256), 0, s, xyzm, n, c->prm.key_kind, c->b.ctl,
-                     c->b.keyA, c->b.idxA);
+  hipLaunchKernelGGL(bbox_final_k, dim3(nsys), dim3(64), 0, s, c->b.bbox_part, nb, c->b.sys);
+  int64_t kb = (max_n + 255) / 256;
+  int64_t kcap = 8192 / nsys;
+  if (kcap < 1) kcap = 1;
+  const int kx = (int)(kb > kcap ? kcap : (kb < 1 ? 1 : kb));
+  const bool toB = keys_to_B(nsys);
+  hipLaunchKernelGGL(keys_k, dim3(kx, nsys), dim3(256), 0, s, xyzm, c->b.soff, c->prm.key_kind,
+                     c->b.sys, toB ? c->b.keyB : c->b.keyA, toB ? c->b.idxB : c->b.idxA);
 }
 
 }  // namespace gothic

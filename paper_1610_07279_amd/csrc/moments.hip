@@ -234,7 +234,7 @@ radius_k(Ctl *__restrict__ ctl, int64_t n, const float4 *__restrict__ pos,
   }
 }
 
-void launch_moments(gothic_ctx *c, int64_t n, hipStream_t s) {
+void launch_moments(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
   Buffers &B = c->b;
   const int wq = c->prm.multipole == 2 ? 1 : 0;
   int64_t nb = (c->cap_nodes + 255) / 256;
@@ -242,7 +242,7 @@ void launch_moments(gothic_ctx *c, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(leaf_moments_k, dim3(g), dim3(256), 0, s, B.ctl, n, B.first, B.count,
                      B.n_child, B.pos, B.leaf_of, B.nrec, B.quad, wq);
   for (int l = kNlev - 1; l >= 0; --l) {
-    int64_t widest = 1;
+    int64_t widest = nsys;
     for (int q = 0; q < l && widest < c->cap_nodes; ++q) widest *= 8;
     if (widest > c->cap_nodes) widest = c->cap_nodes;
     int64_t lb = (widest + 255) / 256;

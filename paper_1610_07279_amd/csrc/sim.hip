@@ -15,7 +15,9 @@
 //   multiple of that coarser step.  Time is counted in finest sub-steps s
 //   (t = s dt_fine); particle i is due at s when s - s_i = 2^(kmax - k_i).
 // The sub-step counter and every count live on the device, so a step needs
-// no host round-trip.
+// no host round-trip.  Several independent systems can be stepped together:
+// each has its own dt_fine / dt_max (from its own minimum step) and the
+// shared counter s counts every system's own finest sub-steps.
 #include "common.h"
 #include "primitives.h"
 
@@ -43,94 +45,125 @@ sim_shadow_k(int64_t n, const double *__restrict__ pos, const float *__restrict_
                             mass[i]);
 }
 
-// t = 0: store a as a_old, find min dt (positive doubles order like their bits)
+// Every kernel below is wave-uniform in its loop control: waves step over
+// 64-particle tiles, so the cross-lane reductions never sit under a
+// lane-dependent loop condition.  A particle's system (for its clock and
+// softening) is found from the offsets; most tiles lie inside one system.
+
+// t = 0: store a as a_old, find each system's min dt (positive doubles order
+// like their bits)
 __global__ void __launch_bounds__(256)
-sim_init_k(int64_t n, const float4 *__restrict__ acc, float4 *__restrict__ aold,
-           int64_t *__restrict__ si, SimCtl *sc) {
-  const double eps = sc->eps, eta = sc->eta;
-  unsigned long long best = ~0ull;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const float4 a = acc[i];
-    aold[i] = a;
-    si[i] = 0;
-    const double dt = step_of(a, eps, eta);
-    const unsigned long long b = __double_as_longlong(dt);
-    best = b < best ? b : best;
+sim_init_k(int64_t n, unsigned nsys, const uint32_t *__restrict__ soff,
+           const float4 *__restrict__ acc, float4 *__restrict__ aold, int64_t *__restrict__ si,
+           SimSys *ss, const SimCtl *__restrict__ sc) {
+  const double eta = sc->eta;
+  const int lane = lane_id();
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t base = w0 * 64; base < n; base += nw * 64) {
+    const int64_t i = base + lane;
+    const bool ok = i < n;
+    unsigned long long b = ~0ull;
+    unsigned sy = 0;
+    if (ok) {
+      sy = sys_of(soff, nsys, (uint32_t)i);
+      const float4 a = acc[i];
+      aold[i] = a;
+      si[i] = 0;
+      b = __double_as_longlong(step_of(a, ss[sy].eps, eta));
+    }
+    const unsigned s0 = __builtin_amdgcn_readfirstlane(sy);
+    if (__ballot(ok && sy != s0) == 0ull) {  // one system in this tile
+      for (int d = 32; d >= 1; d >>= 1) {
+        const unsigned long long o = __shfl_xor(b, d, 64);
+        b = o < b ? o : b;
+      }
+      if (lane == 0) atomicMin(&ss[s0].min_dt_bits, b);
+    } else if (ok) {
+      atomicMin(&ss[sy].min_dt_bits, b);
+    }
   }
-  for (int d = 32; d >= 1; d >>= 1) {
-    const unsigned long long o = __shfl_xor(best, d, 64);
-    best = o < best ? o : best;
-  }
-  if (lane_id() == 0) atomicMin(&sc->min_dt_bits, best);
 }
 
-__global__ void sim_anchor_k(SimCtl *sc) {
-  if (threadIdx.x == 0) {
-    const double m = __longlong_as_double((long long)sc->min_dt_bits);
+// dt_fine = largest power of two <= min dt of the system, dt_max = dt_fine 2^kmax
+__global__ void sim_anchor_k(unsigned nsys, SimSys *ss, SimCtl *sc) {
+  for (unsigned k = threadIdx.x; k < nsys; k += blockDim.x) {
+    const double m = __longlong_as_double((long long)ss[k].min_dt_bits);
     int e = 0;
+    double dtf = 1.0;
     if (m > 0.0 && m < HUGE_VAL) {
       (void)frexp(m, &e);  // m = f 2^e, f in [0.5, 1)
-      sc->dt_fine = ldexp(1.0, e - 1);
-    } else {
-      sc->dt_fine = 1.0;
+      dtf = ldexp(1.0, e - 1);
     }
-    sc->dt_max = ldexp(sc->dt_fine, sc->kmax);
-    sc->s = 0;
+    ss[k].dt_fine = dtf;
+    ss[k].dt_max = ldexp(dtf, sc->kmax);
   }
+  if (threadIdx.x == 0) sc->s = 0;
 }
 
 __global__ void __launch_bounds__(256)
-sim_levels_k(int64_t n, const float4 *__restrict__ aold, uint8_t *__restrict__ lev,
-             const SimCtl *__restrict__ sc) {
-  const double eps = sc->eps, eta = sc->eta, dt_max = sc->dt_max;
+sim_levels_k(int64_t n, unsigned nsys, const uint32_t *__restrict__ soff,
+             const float4 *__restrict__ aold, uint8_t *__restrict__ lev,
+             const SimSys *__restrict__ ss, const SimCtl *__restrict__ sc) {
+  const double eta = sc->eta;
   const int kmax = sc->kmax, shared = sc->shared;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    lev[i] = (uint8_t)(shared ? kmax : level_for(step_of(aold[i], eps, eta), dt_max, kmax));
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const SimSys &r = ss[sys_of(soff, nsys, (uint32_t)i)];
+    lev[i] = (uint8_t)(shared ? kmax : level_for(step_of(aold[i], r.eps, eta), r.dt_max, kmax));
+  }
 }
 
 // sub-step s+1: predict everybody into the float32 shadow, flag the due ones
 __global__ void __launch_bounds__(256)
-sim_predict_k(int64_t n, const double *__restrict__ pos, const double *__restrict__ vel,
+sim_predict_k(int64_t n, unsigned nsys, const uint32_t *__restrict__ soff,
+              const double *__restrict__ pos, const double *__restrict__ vel,
               const float *__restrict__ mass, const float4 *__restrict__ aold,
               const int64_t *__restrict__ si, const uint8_t *__restrict__ lev,
-              float4 *__restrict__ shadow, uint8_t *__restrict__ act, SimCtl *sc) {
+              float4 *__restrict__ shadow, uint8_t *__restrict__ act,
+              const SimSys *__restrict__ ss, SimCtl *sc) {
   const int64_t s = sc->s + 1;
-  const double dtf = sc->dt_fine;
   const int kmax = sc->kmax;
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
   unsigned cnt = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t el = s - si[i];
-    const double tau = (double)el * dtf;
-    const float4 a = aold[i];
-    const double h = 0.5 * tau * tau;
-    const double x = pos[3 * i] + tau * vel[3 * i] + h * (double)a.x;
-    const double y = pos[3 * i + 1] + tau * vel[3 * i + 1] + h * (double)a.y;
-    const double z = pos[3 * i + 2] + tau * vel[3 * i + 2] + h * (double)a.z;
-    shadow[i] = make_float4((float)x, (float)y, (float)z, mass[i]);
-    const bool due = el == ((int64_t)1 << (kmax - lev[i]));
-    act[i] = due ? 1 : 0;
-    cnt += due ? 1u : 0u;
+  for (int64_t base = w0 * 64; base < n; base += nw * 64) {
+    const int64_t i = base + lane_id();
+    if (i < n) {
+      const double dtf = ss[sys_of(soff, nsys, (uint32_t)i)].dt_fine;
+      const int64_t el = s - si[i];
+      const double tau = (double)el * dtf;
+      const float4 a = aold[i];
+      const double h = 0.5 * tau * tau;
+      const double x = pos[3 * i] + tau * vel[3 * i] + h * (double)a.x;
+      const double y = pos[3 * i + 1] + tau * vel[3 * i + 1] + h * (double)a.y;
+      const double z = pos[3 * i + 2] + tau * vel[3 * i + 2] + h * (double)a.z;
+      shadow[i] = make_float4((float)x, (float)y, (float)z, mass[i]);
+      const bool due = el == ((int64_t)1 << (kmax - lev[i]));
+      act[i] = due ? 1 : 0;
+      cnt += due ? 1u : 0u;
+    }
   }
   cnt = wave_sum(cnt);
   if (lane_id() == 0 && cnt) atomicAdd(&sc->n_active, (unsigned long long)cnt);
 }
 
 __global__ void __launch_bounds__(256)
-sim_correct_k(int64_t n, double *__restrict__ pos, double *__restrict__ vel,
+sim_correct_k(int64_t n, unsigned nsys, const uint32_t *__restrict__ soff,
+              double *__restrict__ pos, double *__restrict__ vel,
               const float4 *__restrict__ anew, float4 *__restrict__ aold,
               int64_t *__restrict__ si, uint8_t *__restrict__ lev,
-              const uint8_t *__restrict__ act, const SimCtl *__restrict__ sc) {
+              const uint8_t *__restrict__ act, const SimSys *__restrict__ ss,
+              const SimCtl *__restrict__ sc) {
   const int64_t s = sc->s + 1;
-  const double dtf = sc->dt_fine, eps = sc->eps, eta = sc->eta, dt_max = sc->dt_max;
+  const double eta = sc->eta;
   const int kmax = sc->kmax, shared = sc->shared;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     if (!act[i]) continue;
+    const SimSys &r = ss[sys_of(soff, nsys, (uint32_t)i)];
     const int k = lev[i];
-    const double dt = ldexp(dtf, kmax - k);
+    const double dt = ldexp(r.dt_fine, kmax - k);
     const float4 ao = aold[i], an = anew[i];
     const double h = 0.5 * dt * dt;
     pos[3 * i] += dt * vel[3 * i] + h * (double)ao.x;
@@ -142,7 +175,7 @@ sim_correct_k(int64_t n, double *__restrict__ pos, double *__restrict__ vel,
     aold[i] = an;
     si[i] = s;
     if (!shared) {
-      const int kw = level_for(step_of(an, eps, eta), dt_max, kmax);
+      const int kw = level_for(step_of(an, r.eps, eta), r.dt_max, kmax);
       int kn = k;
       if (kw > k) {
         kn = kw;  // finer at once
@@ -167,9 +200,8 @@ __global__ void sim_advance_k(SimCtl *sc, const Ctl *ctl) {
   }
 }
 
-__global__ void sim_setup_k(SimCtl *sc, double eps, double eta, int kmax, int shared) {
+__global__ void sim_setup_k(SimCtl *sc, double eta, int kmax, int shared) {
   if (threadIdx.x == 0) {
-    sc->eps = eps;
     sc->eta = eta;
     sc->kmax = kmax;
     sc->shared = shared;
@@ -180,7 +212,6 @@ __global__ void sim_setup_k(SimCtl *sc, double eps, double eta, int kmax, int sh
 __global__ void sim_reset_k(SimCtl *sc) {
   if (threadIdx.x == 0) {
     sc->n_active = 0;
-    sc->min_dt_bits = ~0ull;
     sc->steps = 0;
     sc->inter_total = 0;
     sc->node_inter_total = 0;
@@ -211,9 +242,8 @@ static int grid_for(int64_t n) {
   return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
 }
 
-void sim_launch_setup(gothic_ctx *c, hipStream_t s, double eps, double eta, int kmax,
-                      int shared) {
-  hipLaunchKernelGGL(sim_setup_k, dim3(1), dim3(64), 0, s, c->sim.sc, eps, eta, kmax, shared);
+void sim_launch_setup(gothic_ctx *c, hipStream_t s, double eta, int kmax, int shared) {
+  hipLaunchKernelGGL(sim_setup_k, dim3(1), dim3(64), 0, s, c->sim.sc, eta, kmax, shared);
 }
 
 void sim_launch_reset(gothic_ctx *c, hipStream_t s) {
@@ -228,23 +258,25 @@ void sim_launch_shadow(gothic_ctx *c, hipStream_t s) {
 
 void sim_launch_init(gothic_ctx *c, hipStream_t s) {
   SimState &S = c->sim;
-  hipLaunchKernelGGL(sim_init_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, S.anew, S.aold, S.si,
-                     S.sc);
-  hipLaunchKernelGGL(sim_anchor_k, dim3(1), dim3(64), 0, s, S.sc);
-  hipLaunchKernelGGL(sim_levels_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, S.aold, S.lev,
-                     S.sc);
+  const unsigned ns = (unsigned)S.nsys;
+  hipLaunchKernelGGL(sim_init_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, ns, S.soff, S.anew,
+                     S.aold, S.si, S.ss, S.sc);
+  hipLaunchKernelGGL(sim_anchor_k, dim3(1), dim3(256), 0, s, ns, S.ss, S.sc);
+  hipLaunchKernelGGL(sim_levels_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, ns, S.soff, S.aold,
+                     S.lev, S.ss, S.sc);
 }
 
 void sim_launch_predict(gothic_ctx *c, hipStream_t s) {
   SimState &S = c->sim;
-  hipLaunchKernelGGL(sim_predict_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, S.pos, S.vel,
-                     S.mass, S.aold, S.si, S.lev, S.shadow, S.act, S.sc);
+  hipLaunchKernelGGL(sim_predict_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, (unsigned)S.nsys,
+                     S.soff, S.pos, S.vel, S.mass, S.aold, S.si, S.lev, S.shadow, S.act, S.ss,
+                     S.sc);
 }
 
 void sim_launch_correct(gothic_ctx *c, hipStream_t s) {
   SimState &S = c->sim;
-  hipLaunchKernelGGL(sim_correct_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, S.pos, S.vel,
-                     S.anew, S.aold, S.si, S.lev, S.act, S.sc);
+  hipLaunchKernelGGL(sim_correct_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, (unsigned)S.nsys,
+                     S.soff, S.pos, S.vel, S.anew, S.aold, S.si, S.lev, S.act, S.ss, S.sc);
   hipLaunchKernelGGL(sim_advance_k, dim3(1), dim3(64), 0, s, S.sc, c->b.ctl);
 }
 

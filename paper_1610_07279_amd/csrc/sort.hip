@@ -8,7 +8,10 @@
 //            order, then lane order) with ballot-based digit matching and
 //            writes them to their bucket.
 // Equal keys keep the order of their indices, so the result is the
-// lexicographic (key, original index) order.
+// lexicographic (key, original index) order.  With several systems the key
+// passes are followed by passes on the digits of the system id (derived from
+// the index), which makes the order (system, key, index): each system's
+// particles stay in their own index range, sorted as if alone.
 #include "common.h"
 #include "primitives.h"
 
@@ -21,14 +24,31 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kPasses = 8;
 
+// passes over the digits of the system id (0 for one system)
+static int sys_passes(int nsys) {
+  int bits = 0;
+  while (nsys > 1 && (1 << bits) < nsys) ++bits;
+  return (bits + kRadixBits - 1) / kRadixBits;
+}
+
+bool keys_to_B(int nsys) { return ((kPasses + sys_passes(nsys)) & 1) != 0; }
+
+// radix digit of an element: of the key, or (sys_shift >= 0) of its system id
+__device__ __forceinline__ unsigned digit_of(uint64_t key, uint32_t id, int shift, int sys_shift,
+                                             const uint32_t *__restrict__ soff, unsigned nsys) {
+  if (sys_shift < 0) return (unsigned)(key >> shift) & (kRadix - 1);
+  return (sys_of(soff, nsys, id) >> sys_shift) & (kRadix - 1);
+}
+
 int64_t radix_hist_entries(int64_t n) {
   int64_t tiles = (n + kSortTile - 1) / kSortTile;
   return (tiles < 1 ? 1 : tiles) * kRadix;
 }
 
 __global__ void __launch_bounds__(kSortThreads)
-radix_hist_k(const uint64_t *__restrict__ keys, int64_t n, int shift, int64_t ntiles,
-             uint32_t *__restrict__ hist) {
+radix_hist_k(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ ids, int64_t n,
+             int shift, int sys_shift, const uint32_t *__restrict__ soff, unsigned nsys,
+             int64_t ntiles, uint32_t *__restrict__ hist) {
   __shared__ unsigned cnt[kRadix];
   for (int t = threadIdx.x; t < kRadix; t += kSortThreads) cnt[t] = 0;
   __syncthreads();
@@ -36,7 +56,11 @@ radix_hist_k(const uint64_t *__restrict__ keys, int64_t n, int shift, int64_t nt
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t e = base + r * kSortThreads + threadIdx.x;
-    if (e < n) atomicAdd(&cnt[(unsigned)(keys[e] >> shift) & (kRadix - 1)], 1u);
+    if (e < n) {
+      const unsigned d = sys_shift < 0 ? (unsigned)(keys[e] >> shift) & (kRadix - 1)
+                                       : digit_of(0, ids[e], 0, sys_shift, soff, nsys);
+      atomicAdd(&cnt[d], 1u);
+    }
   }
   __syncthreads();
   for (int t = threadIdx.x; t < kRadix; t += kSortThreads)
@@ -46,7 +70,8 @@ radix_hist_k(const uint64_t *__restrict__ keys, int64_t n, int shift, int64_t nt
 __global__ void __launch_bounds__(kSortThreads)
 radix_scatter_k(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ iin,
                 uint64_t *__restrict__ kout, uint32_t *__restrict__ iout, int64_t n, int shift,
-                int64_t ntiles, const uint32_t *__restrict__ ofs) {
+                int sys_shift, const uint32_t *__restrict__ soff, unsigned nsys, int64_t ntiles,
+                const uint32_t *__restrict__ ofs) {
   constexpr int NW = kSortThreads / 64;
   __shared__ unsigned gofs[kRadix];
   __shared__ unsigned run[kRadix];
@@ -64,7 +89,7 @@ radix_scatter_k(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ i
     const bool valid = e < n;
     uint64_t key = valid ? kin[e] : 0;
     uint32_t id = valid ? iin[e] : 0;
-    const unsigned d = (unsigned)(key >> shift) & (kRadix - 1);
+    const unsigned d = digit_of(key, id, shift, sys_shift, soff, nsys);
     unsigned long long m = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
@@ -94,25 +119,32 @@ radix_scatter_k(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ i
   }
 }
 
-void launch_radix_sort(gothic_ctx *c, int64_t n, hipStream_t s) {
-  if (n <= 1) return;
-  const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+void launch_radix_sort(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
+  const int passes = kPasses + sys_passes(nsys);
+  // the key kernel wrote to B when the pass count is odd: the result always
+  // ends in keyA / idxA
   uint64_t *ka = c->b.keyA, *kb = c->b.keyB;
   uint32_t *ia = c->b.idxA, *ib = c->b.idxB;
+  if (passes & 1) {
+    ka = c->b.keyB; kb = c->b.keyA;
+    ia = c->b.idxB; ib = c->b.idxA;
+  }
+  if (n <= 1) return;  // then nsys <= 1 (systems are never empty): an even count, in A
+  const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
   uint32_t *hist = c->b.hist;
   uint32_t *ofs = c->b.hist + ntiles * kRadix;
-  for (int p = 0; p < kPasses; ++p) {
-    const int shift = p * kRadixBits;
-    hipLaunchKernelGGL(radix_hist_k, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, ka, n,
-                       shift, ntiles, hist);
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p < kPasses ? p * kRadixBits : 0;
+    const int sys_shift = p < kPasses ? -1 : (p - kPasses) * kRadixBits;
+    hipLaunchKernelGGL(radix_hist_k, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, ka, ia, n,
+                       shift, sys_shift, c->b.soff, (unsigned)nsys, ntiles, hist);
     scan_exclusive(hist, ofs, ntiles * kRadix, nullptr, nullptr, ntiles * kRadix,
                    &c->b.ctl->scan_total, c->b.part, s);
     hipLaunchKernelGGL(radix_scatter_k, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, ka, ia,
-                       kb, ib, n, shift, ntiles, ofs);
+                       kb, ib, n, shift, sys_shift, c->b.soff, (unsigned)nsys, ntiles, ofs);
     uint64_t *tk = ka; ka = kb; kb = tk;
     uint32_t *ti = ia; ia = ib; ib = ti;
   }
-  // an even number of passes leaves the result in keyA / idxA
 }
 
 }  // namespace gothic

@@ -44,17 +44,21 @@ void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active, in
                      c->b.flag, c->b.ctl);
 }
 
-__global__ void build_init_k(Ctl *ctl, int64_t n, uint32_t *first, uint32_t *count,
-                             uint32_t *parent, uint8_t *level) {
-  if (threadIdx.x == 0) {
-    first[0] = 0;
-    count[0] = (uint32_t)n;
-    parent[0] = kNone;
-    level[0] = 0;
+// level 0 holds one root per system: node s covers the system's index range
+__global__ void __launch_bounds__(256)
+build_init_k(Ctl *ctl, int nsys, const uint32_t *__restrict__ soff, uint32_t *first,
+             uint32_t *count, uint32_t *parent, uint8_t *level) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nsys; r += gridDim.x * blockDim.x) {
+    first[r] = soff[r];
+    count[r] = soff[r + 1] - soff[r];
+    parent[r] = kNone;
+    level[r] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->lvl_start[0] = 0;
-    ctl->lvl_start[1] = 1;
-    for (int l = 2; l < kMaxLevels + 2; ++l) ctl->lvl_start[l] = 1;
-    ctl->n_nodes = 1;
+    for (int l = 1; l < kMaxLevels + 2; ++l) ctl->lvl_start[l] = (unsigned)nsys;
+    ctl->n_nodes = (unsigned)nsys;
+    ctl->nsys = (unsigned)nsys;
   }
 }
 
@@ -191,14 +195,15 @@ __global__ void build_final_k(Ctl *ctl, int64_t cap_nodes) {
   }
 }
 
-void launch_build(gothic_ctx *c, int64_t n, hipStream_t s) {
+void launch_build(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
   Buffers &B = c->b;
-  hipLaunchKernelGGL(build_init_k, dim3(1), dim3(64), 0, s, B.ctl, n, B.first, B.count, B.parent,
-                     B.level);
+  const int ib = (nsys + 255) / 256;
+  hipLaunchKernelGGL(build_init_k, dim3(ib > 1024 ? 1024 : ib), dim3(256), 0, s, B.ctl, nsys,
+                     B.soff, B.first, B.count, B.parent, B.level);
   const int64_t cap = c->cap_nodes;
-  // grid large enough for the widest level (at most min(cap, 8^l) nodes)
+  // grid large enough for the widest level (at most min(cap, nsys 8^l) nodes)
   for (int l = 0; l <= kNlev; ++l) {
-    int64_t widest = 1;
+    int64_t widest = nsys;
     for (int q = 0; q < l && widest < cap; ++q) widest *= 8;
     if (widest > cap) widest = cap;
     int64_t nb = (widest + kBuildThreads - 1) / kBuildThreads;

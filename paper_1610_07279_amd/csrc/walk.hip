@@ -1,7 +1,10 @@
 // Tree walk and force (Sections 2.2, 2.3 and 2.5 of the paper).
 //
 // One wave64 walks the tree for one group of G i-particles at a time
-// (persistent waves claim groups from a device counter).  The group is
+// (persistent waves claim groups from a device counter).  In a batched
+// evaluation every group belongs to one system and starts at that system's
+// root with that system's softening and opening angle, so one launch walks
+// all systems.  The group is
 // represented by its pseudo i-particle (r_I, b_I); a candidate pseudo
 // j-particle J is at distance d = lambda r_JI with lambda = 1 - b_I / r_JI
 // (0 when b_I >= r_JI), and is accepted when b_J <= theta d (the opening-angle
@@ -54,10 +57,11 @@ struct WalkArgs {
   uint32_t *gent;
   uint32_t *spill;
   int64_t spill_cap;
+  const SysRec *sys;
+  const uint32_t *soff;
   int G, logG, D, DQ;
   int wave_bytes;
   int compensated;
-  float eps2, theta, inv_eps;
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -79,10 +83,9 @@ struct Acc {
 template <int MULTI>
 __device__ __forceinline__ void flush(const WalkArgs &a, const float4 *pl, const float4 *ql0,
                                       const float4 *ql1, const float4 *ql2, int np, int nq,
-                                      float4 pi, int sub, int S, Acc &acc) {
+                                      float4 pi, float eps2, int sub, int S, Acc &acc) {
   wave_sync();
   float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
-  const float eps2 = a.eps2;
 #pragma unroll 4
   for (int k = sub; k < np; k += S) {
     const float4 j = pl[k];
@@ -154,8 +157,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   const int il = lane & (G - 1), sub = lane >> a.logG;
   Ctl *ctl = a.ctl;
   if (ctl->flags & kFlagNodeOverflow) return;  // no valid tree: the host repeats
-  const unsigned ng = ctl->n_groups, na = ctl->n_active, nn = ctl->n_nodes;
-  const float theta = a.theta;
+  const unsigned ng = ctl->n_groups, nn = ctl->n_nodes, nsys = ctl->nsys;
   const int D = a.D, DQ = a.DQ;
 
   unsigned long long t_node = 0, t_part = 0, t_int = 0, t_nint = 0, t_mac = 0;
@@ -189,6 +191,11 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     const uint32_t ki0 = a.alist[gs + (vi ? il : 0)];
     const uint32_t ki = ki0 < a.n ? ki0 : 0u;
     const float4 pi = a.pos[ki];
+    // the group's system (groups never span two): its root is node sys
+    const uint32_t k_first = __builtin_amdgcn_readfirstlane(a.alist[gs]);
+    const unsigned sy = __builtin_amdgcn_readfirstlane(
+        sys_of(a.soff, nsys, k_first < a.n ? k_first : 0u));
+    const float eps2 = a.sys[sy].eps2, theta = a.sys[sy].theta, inv_eps = a.sys[sy].inv_eps;
     Acc acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int np = 0, nq = 0;
     // LDS ring holds stack entries [qb, qt) (ring positions mod kQueueCap);
@@ -196,7 +203,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     unsigned qb = 0, qt = 1;
     int64_t stop = 0;
     unsigned long long e_node = 0, e_part = 0, n_mac = 0;
-    if (lane == 0) queue[0] = 0;
+    if (lane == 0) queue[0] = sy;
     wave_sync();
 
     // a valid walk pops every node at most once; the bound only guards
@@ -237,14 +244,14 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       if (nacc) {
         if (MULTI == 1) {
           if (np + nacc > D) {
-            flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, sub, S, acc);
+            flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, eps2, sub, S, acc);
             np = 0; nq = 0;
           }
           if (accept) pl[np + lanes_below(am)] = r0;
           np += nacc;
         } else {
           if (nq + nacc > DQ) {
-            flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, sub, S, acc);
+            flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, eps2, sub, S, acc);
             np = 0; nq = 0;
           }
           if (accept) {
@@ -297,7 +304,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
         wave_sync();
         for (unsigned t0 = 0; t0 < P; t0 += 64) {
           if (np + 64 > D) {
-            flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, sub, S, acc);
+            flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, eps2, sub, S, acc);
             np = 0; nq = 0;
           }
           const unsigned t = t0 + lane;
@@ -316,7 +323,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       }
     }
     if (pops > (unsigned long long)nn) atomicOr(&ctl->flags, kFlagBadIndex);
-    flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, sub, S, acc);
+    flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, eps2, sub, S, acc);
 
     float ax = acc.x + acc.cx, ay = acc.y + acc.cy, az = acc.z + acc.cz, ap = acc.p + acc.cp;
     for (int m = G; m < 64; m <<= 1) {
@@ -327,7 +334,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     }
     const uint32_t dst = a.perm[ki];
     if (sub == 0 && vi && ki0 < a.n && dst < a.n)
-      a.out[dst] = make_float4(ax, ay, az, -ap + pi.w * a.inv_eps);
+      a.out[dst] = make_float4(ax, ay, az, -ap + pi.w * inv_eps);
     // same value from every lane
     a.gent[2 * (size_t)g] = (uint32_t)e_node;
     a.gent[2 * (size_t)g + 1] = (uint32_t)e_part;
@@ -385,8 +392,7 @@ int walk_slots(gothic_ctx *c) {
   return c->num_cus * per_cu * wpb;
 }
 
-void launch_walk(gothic_ctx *c, int64_t n, float eps, float theta, float4 *acc_pot,
-                 hipStream_t s) {
+void launch_walk(gothic_ctx *c, int64_t n, float4 *acc_pot, hipStream_t s) {
   Buffers &B = c->b;
   WalkArgs a;
   const int multi = c->prm.multipole;
@@ -403,6 +409,8 @@ void launch_walk(gothic_ctx *c, int64_t n, float eps, float theta, float4 *acc_p
   a.gent = B.gent;
   a.spill = B.spill;
   a.spill_cap = c->spill_per_wave;
+  a.sys = B.sys;
+  a.soff = B.soff;
   a.G = c->prm.group_size;
   int lg = 0;
   while ((1 << lg) < a.G) ++lg;
@@ -410,9 +418,6 @@ void launch_walk(gothic_ctx *c, int64_t n, float eps, float theta, float4 *acc_p
   list_dims(multi, c->prm.list_depth, &a.D, &a.DQ);
   a.wave_bytes = wave_bytes_for(multi, a.D, a.DQ);
   a.compensated = c->prm.compensated;
-  a.eps2 = eps * eps;
-  a.theta = theta;
-  a.inv_eps = 1.0f / eps;
   const int wpb = waves_per_block(a.wave_bytes);
   const int slots = c->walk_waves;
   const int blocks = slots / wpb;

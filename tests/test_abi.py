@@ -30,7 +30,7 @@ def test_defaults_and_cpu_only_errors():
     import paper_1610_07279_amd as g
     p = g.default_params()
     assert (p.key_kind, p.n_leaf, p.multipole, p.group_size, p.list_depth, p.compensated,
-            p.check, p.timing, p.node_capacity) == (0, 16, 1, 32, 384, 1, 1, 0, 0)
+            p.check, p.timing, p.graph, p.node_capacity) == (0, 16, 1, 32, 384, 1, 1, 0, 0, 0)
     assert p.r_crit == -0.0625
     # a NULL context is rejected before any device call
     rc = g.lib.gothic_tree_forces(None, 10, None, ctypes.c_float(0.1), ctypes.c_float(0.5),
@@ -38,6 +38,34 @@ def test_defaults_and_cpu_only_errors():
     assert rc == g.EINVAL
     assert b"NULL" in g.lib.gothic_last_error()
     assert g.lib.gothic_destroy(None) == g.OK
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """Field offsets and sizes of the binding's structs equal the C compiler's."""
+    import shutil
+    import subprocess
+
+    import paper_1610_07279_amd as g
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    structs = {"gothic_params": g.Params, "gothic_stats": g.Stats, "gothic_sim_info": g.SimInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gothic.h"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 def test_oracle_does_not_enter_the_package():

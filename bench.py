@@ -35,7 +35,8 @@ sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32, 256 CU x 2.4 GHz x 256 flop/clk
 FLOP_MONO = 24                    # per monopole interaction (20 + rsqrt weighted 4)
-FLOP_QUAD = 65                    # per quadrupole node interaction (count of the kernel's ops)
+FLOP_QUAD = 60                    # per quadrupole node interaction (operations of the factored
+                                  # quadrupole term, rsq weighted 4)
 METRIC = "s/step + interactions/s, NFW 2^24 block vs shared step; % FP32 VALU peak"
 
 
@@ -49,7 +50,11 @@ def run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, shared, steps, warmup)
     vel = vel0.clone()
     ctx.set_params(check=1)
     ctx.sim_bind(pos, vel, mass, eps, theta, eta=eta, kmax=kmax, shared=shared)
-    for _ in range(warmup):      # first steps in check mode grow any scratch
+    # warm-up: checked steps (they grow any scratch), the last one unchecked
+    # (with params.graph it is the capture)
+    for i in range(warmup):
+        if i == warmup - 1:
+            ctx.set_params(check=0)
         ctx.sim_step()
     ctx.set_params(check=0)
     torch.cuda.synchronize()
@@ -205,6 +210,8 @@ def main():
                     help="critical separation splitting groups (Section 2.4)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-shared", action="store_true", help="skip the shared-step run")
+    ap.add_argument("--graph", type=int, default=1, choices=(0, 1),
+                    help="replay each timed sub-step as captured HIP graphs (default 1)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-system batched / captured sub-step comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -240,7 +247,7 @@ def main():
     vel0 = torch.from_numpy(v).to(dev)
     mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).to(dev)
     ctx = g.Context(device=0, multipole=multipole, group_size=args.group_size,
-                    list_depth=args.list_depth, r_crit=args.r_crit, timing=1)
+                    list_depth=args.list_depth, r_crit=args.r_crit, timing=1, graph=args.graph)
 
     log(f"bench: block steps (warmup {args.warmup}, timed {args.steps})")
     blk = run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, False, args.steps, args.warmup)
@@ -275,7 +282,7 @@ def main():
         "config": {"workload": f"NFW sphere N={n}, c=10, eps=1/512, theta=0.5 quadrupole, "
                                f"block steps kmax=8 (eta=0.1), finest sub-steps",
                    "n": n, "group_size": args.group_size, "list_depth": args.list_depth,
-                   "r_crit": args.r_crit,
+                   "r_crit": args.r_crit, "graph": args.graph,
                    "parallelism": "single GPU"},
         "block": {"s_per_step": blk["seconds"] / args.steps,
                   "interactions_per_s": inter / blk["seconds"],

@@ -89,6 +89,30 @@ typedef struct {
                          launching some two hundred kernels; it is captured on
                          first use and again after any buffer or parameter
                          change (default 0) */
+  int autotune;       /* 1: gothic_sim_step tunes r_crit while it runs, as in
+                         Section 2.4: the walk time of each sub-step is
+                         minimised over r_crit with Brent's method, searching
+                         log2(r_crit / L) in [-12, 0] (r_crit a fraction of each
+                         system's key-cube side L), and every finished search
+                         is followed by a new one on a narrower bracket about
+                         its best point (the perturbation that follows a
+                         drifting optimum).  One search per class of
+                         sub-steps with the same due levels.  Synchronises on
+                         the previous sub-step's walk (default 0) */
+  int rebuild_interval; /* tree reuse (Section 2.6): 1 = build a new tree for
+                         every evaluation (default); k > 1 = build one every
+                         k evaluations and walk the last one in between, with
+                         the current positions (moments, radii, groups and
+                         walk are always recomputed, so every evaluation is an
+                         exact Barnes-Hut evaluation of its tree); 0 =
+                         automatic: rebuild when the paper's growth models of
+                         the walk time (linear, power law, parabolic, chosen
+                         by reduced chi^2) say the mean cost per step is
+                         minimal; synchronises on the previous evaluation's
+                         walk.  With k != 1 the caller must pass the same
+                         particles (same order) on the same systems between
+                         rebuilds; a change of n or of the systems always
+                         rebuilds */
   int64_t node_capacity; /* initial size of the node arrays in nodes; 0 = from
                          n and n_leaf (about n + 8 n / n_leaf).  Trees that do
                          not fit are abandoned on the device, the arrays grow
@@ -167,6 +191,34 @@ int gothic_tree_forces_batched(gothic_ctx *c, int nsys, const int64_t *offsets,
                                const float *xyzm, const float *eps, const float *theta,
                                const uint8_t *active, float *acc_pot, void *stream);
 
+/* Result of gothic_autotune. */
+typedef struct {
+  int group_size;         /* chosen G */
+  int list_depth;         /* chosen list budget */
+  float r_crit;           /* chosen critical separation (< 0: fraction of each
+                             system's key-cube side) */
+  int evaluations;        /* timed evaluations spent; 0 = taken from the cache */
+  double ms;              /* best measured time of one evaluation (ms) */
+} gothic_tune_result;
+
+/*
+ * Timed search for the fastest tunables of one workload (Section 2.4 tunes
+ * r_crit by Brent's method on the measured time; here the group size G and
+ * the list budget are searched as well): every G in {8, 16, 32, 64} with
+ * every list_depth in {128, 256, 384, 512, 768} at the current r_crit, then
+ * Brent's method over log2(r_crit / L) in [-12, 0] at the best pair.  Each
+ * candidate is one whole evaluation timed with HIP events (after an untimed
+ * one).  The winner is stored in the context's parameters and cached under
+ * (batched or not, floor(log2 n), floor(log2(n / n_active)), multipole); a
+ * later call in the same bucket costs one evaluation.  Arguments as in
+ * gothic_tree_forces_batched (nsys = 1 for one system); acc_pot receives the
+ * forces of a final checked evaluation with the chosen tunables.
+ * Synchronises.  Returns as gothic_tree_forces, and EINVAL for a NULL out.
+ */
+int gothic_autotune(gothic_ctx *c, int nsys, const int64_t *offsets, const float *xyzm,
+                    const float *eps, const float *theta, const uint8_t *active,
+                    float *acc_pot, gothic_tune_result *out, void *stream);
+
 /* Sum of the walk-kernel durations recorded since the previous call (timing
  * = 1; up to 4096 launches are kept), in milliseconds, and their number.
  * Synchronises on the recorded events. */
@@ -200,6 +252,8 @@ typedef struct {
   int64_t active_total;        /* summed over the counted sub-steps */
   int64_t interactions_total;  /* list entries x i-particles, summed likewise */
   int64_t node_interactions_total;
+  int64_t tree_builds;         /* sub-steps that built a new tree, counted likewise
+                                  (all of them unless rebuild_interval != 1) */
   int64_t level_count[32];     /* particles per level now */
 } gothic_sim_info;
 
@@ -223,6 +277,12 @@ int gothic_sim_get_state(gothic_ctx *c, float *acc_pot, uint8_t *levels, int64_t
 /* dt_fine and dt_max of every bound system: HOST double arrays of nsys
  * entries (gothic_sim_info reports system 0).  Synchronises. */
 int gothic_sim_get_steps(gothic_ctx *c, int nsys, double *dt_fine, double *dt_max);
+/* Online r_crit tuning (params.autotune): for each sub-step class c =
+ * 0..nclass-1 (class c = sub-steps whose index has its lowest set bit at c,
+ * capped at kmax), the best r_crit of the last finished search (0 if none
+ * finished yet) and the number of finished searches.  HOST arrays; either
+ * may be NULL. */
+int gothic_sim_get_tuning(gothic_ctx *c, int nclass, float *r_crit_best, int *searches);
 
 /* Counts of the last evaluation; synchronises the stream of that call. */
 int gothic_get_stats(gothic_ctx *c, gothic_stats *out);

@@ -33,7 +33,16 @@ class Params(C.Structure):
     _fields_ = [("key_kind", C.c_int), ("n_leaf", C.c_int), ("multipole", C.c_int),
                 ("group_size", C.c_int), ("list_depth", C.c_int), ("compensated", C.c_int),
                 ("check", C.c_int), ("timing", C.c_int), ("r_crit", C.c_float),
-                ("graph", C.c_int), ("node_capacity", C.c_int64)]
+                ("graph", C.c_int), ("autotune", C.c_int), ("rebuild_interval", C.c_int),
+                ("node_capacity", C.c_int64)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("group_size", C.c_int), ("list_depth", C.c_int), ("r_crit", C.c_float),
+                ("evaluations", C.c_int), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Stats(C.Structure):
@@ -52,7 +61,7 @@ class SimInfo(C.Structure):
                 ("dt_fine", C.c_double), ("dt_max", C.c_double), ("steps", C.c_int64),
                 ("last_active", C.c_int64), ("active_total", C.c_int64),
                 ("interactions_total", C.c_int64), ("node_interactions_total", C.c_int64),
-                ("level_count", C.c_int64 * 32)]
+                ("tree_builds", C.c_int64), ("level_count", C.c_int64 * 32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "level_count"}
@@ -84,6 +93,8 @@ def _load():
     lib.gothic_sim_bind.argtypes = [P, i64, P, P, P, f32, f32, C.c_double, i32, i32, P]
     lib.gothic_sim_bind_batched.argtypes = [P, i32, P, P, P, P, P, P, C.c_double, i32, i32, P]
     lib.gothic_sim_get_steps.argtypes = [P, i32, P, P]
+    lib.gothic_sim_get_tuning.argtypes = [P, i32, P, P]
+    lib.gothic_autotune.argtypes = [P, i32, P, P, P, P, P, P, C.POINTER(TuneResult), P]
     lib.gothic_sim_step.argtypes = [P, P]
     lib.gothic_sim_reset_counters.argtypes = [P, P]
     lib.gothic_sim_get_info.argtypes = [P, C.POINTER(SimInfo)]
@@ -93,7 +104,8 @@ def _load():
                  "gothic_get_keys", "gothic_get_tree", "gothic_get_nodes", "gothic_get_groups",
                  "gothic_get_walk_time", "gothic_sim_bind", "gothic_sim_bind_batched",
                  "gothic_sim_step", "gothic_sim_reset_counters", "gothic_sim_get_info",
-                 "gothic_sim_get_state", "gothic_sim_get_steps"):
+                 "gothic_sim_get_state", "gothic_sim_get_steps", "gothic_sim_get_tuning",
+                 "gothic_autotune"):
         getattr(lib, name).restype = i32
     return lib
 
@@ -234,6 +246,33 @@ class Context:
             s))
         return out
 
+    def autotune(self, xyzm, eps, theta, active=None, offsets=None, out=None, stream=None):
+        """Timed search of (group_size, list_depth, r_crit) for this workload (one
+        system, or the systems given by offsets); sets them in the context and
+        returns the result dict (evaluations = 0 for a cached bucket).  out
+        receives the forces of a final checked evaluation."""
+        import numpy as np
+        import torch
+        n = xyzm.shape[0]
+        if offsets is None:
+            offsets = np.array([0, n], np.int64)
+        offs, nsys, e, t = self._systems(offsets, eps, theta)
+        if xyzm.dtype != torch.float32 or xyzm.dim() != 2 or xyzm.shape[1] != 4 or \
+                not xyzm.is_cuda or not xyzm.is_contiguous() or offs[-1] != n:
+            raise ValueError("xyzm must be a contiguous float32 [n,4] GPU tensor covering offsets")
+        if active is not None and (active.dtype != torch.uint8 or active.shape != (n,)
+                                   or not active.is_cuda or not active.is_contiguous()):
+            raise ValueError("active must be a contiguous uint8 [n] GPU tensor")
+        if out is None:
+            out = torch.zeros((n, 4), dtype=torch.float32, device=xyzm.device)
+        res = TuneResult()
+        s = _stream_of(xyzm, stream)
+        self._last_stream = s
+        _check(lib.gothic_autotune(self._h, nsys, offs.ctypes.data_as(C.c_void_p), _ptr(xyzm),
+                                   e.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p),
+                                   _ptr(active), _ptr(out), C.byref(res), s))
+        return res.as_dict()
+
     # ---------------------------------------------------------------- block steps
     def sim_bind(self, pos, vel, mass, eps, theta, eta=0.1, kmax=8, shared=False, stream=None):
         """Bind float64 [n,3] pos/vel and float32 [n] mass (GPU tensors, updated in
@@ -283,6 +322,16 @@ class Context:
         _check(lib.gothic_sim_get_steps(self._h, ns, f.ctypes.data_as(C.c_void_p),
                                         m.ctypes.data_as(C.c_void_p)))
         return f, m
+
+    def sim_tuning(self, nclass: int = 32):
+        """(best r_crit per sub-step class [nclass] float32, finished searches [nclass])
+        of the online tuner (params.autotune)."""
+        import numpy as np
+        r = np.zeros(nclass, np.float32)
+        k = np.zeros(nclass, np.int32)
+        _check(lib.gothic_sim_get_tuning(self._h, nclass, r.ctypes.data_as(C.c_void_p),
+                                         k.ctypes.data_as(C.c_void_p)))
+        return r, k
 
     def sim_step(self, nsteps: int = 1, stream=None):
         s = _stream_of(self._sim_keep[0], stream)

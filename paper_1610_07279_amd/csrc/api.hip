@@ -32,9 +32,26 @@ int hip_check(hipError_t e, const char *what) {
   } while (0)
 
 // ---------------------------------------------------------------- helpers
-__global__ void ctl_reset_k(Ctl *ctl) {
+// Zero the control block before an evaluation.  keep_tree keeps the tree of
+// the last build (node count, level starts, systems); a tree whose build
+// overflowed is not reusable and is reported as a node overflow.
+__global__ void ctl_reset_k(Ctl *ctl, int keep_tree) {
+  const unsigned keep_nodes = ctl->n_nodes, keep_sys = ctl->nsys, ok = ctl->tree_ok;
+  unsigned lv = 0;
+  if (threadIdx.x < kMaxLevels + 2) lv = ctl->lvl_start[threadIdx.x];
+  __syncthreads();
   unsigned *w = reinterpret_cast<unsigned *>(ctl);
   for (unsigned i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) w[i] = 0u;
+  __syncthreads();
+  if (keep_tree) {
+    if (threadIdx.x < kMaxLevels + 2) ctl->lvl_start[threadIdx.x] = lv;
+    if (threadIdx.x == 0) {
+      ctl->n_nodes = keep_nodes;
+      ctl->nsys = keep_sys;
+      ctl->tree_ok = ok;
+      if (!ok) ctl->flags = kFlagNodeOverflow;
+    }
+  }
 }
 
 // The system table travels in kernel arguments (captured by value in a
@@ -57,6 +74,10 @@ __global__ void sys_upload_k(SysChunk ch, SysRec *sys, uint32_t *soff) {
     r.inv_eps = ch.inv_eps[t];
   }
   if (t <= ch.count) soff[ch.first + t] = ch.off[t];
+}
+
+__global__ void set_rcrit_k(float r, float *dst) {
+  if (threadIdx.x == 0) *dst = r;
 }
 
 __global__ void extract_cubes_k(int nsys, const SysRec *sys, double *cube) {
@@ -109,13 +130,14 @@ static void free_all(gothic_ctx *c) {
                   B.gA, B.gB, B.gfirst,
                   B.first, B.count, B.child_first, B.parent, B.n_child, B.level, B.nch, B.bnd,
                   B.nrec, B.quad, B.ball, B.gent, B.hist, B.part, B.bbox_part, B.spill, B.sys,
-                  B.soff, B.ctl};
+                  B.soff, B.rcrit, B.ctl};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (B.ctl_host) (void)hipHostFree(B.ctl_host);
   B = Buffers();
   c->cap_n = c->cap_nodes = c->cap_groups = c->cap_hist = c->cap_sys = 0;
   ++c->generation;
+  ++c->buffers;
 }
 
 static int validate_params(const gothic_params *p) {
@@ -136,6 +158,10 @@ static int validate_params(const gothic_params *p) {
   if (p->timing != 0 && p->timing != 1) return set_error(GOTHIC_EINVAL, "timing must be 0 or 1");
   if (!std::isfinite(p->r_crit)) return set_error(GOTHIC_EINVAL, "r_crit must be finite");
   if (p->graph != 0 && p->graph != 1) return set_error(GOTHIC_EINVAL, "graph must be 0 or 1");
+  if (p->autotune != 0 && p->autotune != 1)
+    return set_error(GOTHIC_EINVAL, "autotune must be 0 or 1");
+  if (p->rebuild_interval < 0 || p->rebuild_interval > (1 << 20))
+    return set_error(GOTHIC_EINVAL, "rebuild_interval must be in 0..2^20");
   return GOTHIC_OK;
 }
 
@@ -148,7 +174,9 @@ static int ensure(gothic_ctx *c, int64_t n, int nsys, int64_t want_nodes, int64_
     GCHECK(hipHostMalloc(reinterpret_cast<void **>(&B.ctl_host), sizeof(Ctl), hipHostMallocDefault));
     int rc;
     if ((rc = dev_alloc(&B.part, scan_blocks() + 64)) != GOTHIC_OK) return rc;
+    if ((rc = dev_alloc(&B.rcrit, 1)) != GOTHIC_OK) return rc;
     ++c->generation;
+    ++c->buffers;
   }
   int rc;
   if (nsys > c->cap_sys) {
@@ -159,6 +187,7 @@ static int ensure(gothic_ctx *c, int64_t n, int nsys, int64_t want_nodes, int64_
       return rc;
     c->cap_sys = cs;
     ++c->generation;
+    ++c->buffers;
   }
   if (n > c->cap_n) {
     const int64_t cn = std::max<int64_t>(n, 1024);
@@ -178,6 +207,7 @@ static int ensure(gothic_ctx *c, int64_t n, int nsys, int64_t want_nodes, int64_
     c->cap_groups = cn;
     c->cap_hist = hist;
     ++c->generation;
+    ++c->buffers;
   }
   const int64_t nodes = std::max<int64_t>(want_nodes, 64);
   if (nodes > c->cap_nodes) {
@@ -188,6 +218,7 @@ static int ensure(gothic_ctx *c, int64_t n, int nsys, int64_t want_nodes, int64_
       return rc;
     c->cap_nodes = nodes;
     ++c->generation;
+    ++c->buffers;
   }
   const int slots = walk_slots(c);
   const int64_t spill = std::max<int64_t>(want_spill, 16384);
@@ -196,6 +227,7 @@ static int ensure(gothic_ctx *c, int64_t n, int nsys, int64_t want_nodes, int64_
     c->walk_waves = slots;
     c->spill_per_wave = spill;
     ++c->generation;
+    ++c->buffers;
   }
   return GOTHIC_OK;
 }
@@ -220,11 +252,17 @@ struct Systems {
   std::vector<float> eps, theta;
 };
 
-// Everything before the walk: system table, keys, sort, tree, moments, groups.
-static void enqueue_pre_walk(gothic_ctx *c, const Systems &sy, const float4 *xyzm,
-                             const uint8_t *active, hipStream_t s) {
+// The pipeline of one evaluation, in the pieces a captured sub-step is cut
+// into:  begin (control block, r_crit; never captured), upload (system
+// table), make (keys, sort, octree; skipped when the last tree is reused),
+// post (permute to key order, moments, groups), walk.
+static void enqueue_begin(gothic_ctx *c, bool keep_tree, float r_crit, hipStream_t s) {
+  hipLaunchKernelGGL(ctl_reset_k, dim3(1), dim3(64), 0, s, c->b.ctl, keep_tree ? 1 : 0);
+  hipLaunchKernelGGL(set_rcrit_k, dim3(1), dim3(64), 0, s, r_crit, c->b.rcrit);
+}
+
+static void enqueue_upload(gothic_ctx *c, const Systems &sy, hipStream_t s) {
   Buffers &B = c->b;
-  hipLaunchKernelGGL(ctl_reset_k, dim3(1), dim3(64), 0, s, B.ctl);
   for (int f = 0; f < sy.nsys; f += kSysChunk) {
     SysChunk ch;
     memset(&ch, 0, sizeof(ch));
@@ -239,25 +277,46 @@ static void enqueue_pre_walk(gothic_ctx *c, const Systems &sy, const float4 *xyz
     }
     hipLaunchKernelGGL(sys_upload_k, dim3(1), dim3(64), 0, s, ch, B.sys, B.soff);
   }
-  const int64_t n = sy.n;
-  launch_bbox_keys(c, xyzm, n, sy.nsys, sy.max_n, s);
-  launch_radix_sort(c, n, sy.nsys, s);
-  launch_permute(c, xyzm, active, n, s);
-  launch_build(c, n, sy.nsys, s);
-  launch_moments(c, n, sy.nsys, s);
-  launch_groups(c, n, s);
+}
+
+static void enqueue_make(gothic_ctx *c, const Systems &sy, const float4 *xyzm, hipStream_t s) {
+  launch_bbox_keys(c, xyzm, sy.n, sy.nsys, sy.max_n, s);
+  launch_radix_sort(c, sy.n, sy.nsys, s);
+  launch_build(c, sy.n, sy.nsys, s);
+}
+
+static void enqueue_post(gothic_ctx *c, const Systems &sy, const float4 *xyzm,
+                         const uint8_t *active, hipStream_t s) {
+  launch_permute(c, xyzm, active, sy.n, s);
+  launch_moments(c, sy.n, sy.nsys, s);
+  launch_groups(c, sy.n, s);
 }
 
 static void enqueue_walk(gothic_ctx *c, int64_t n, float4 *out, hipStream_t s, bool timed) {
   timed = timed && c->prm.timing && c->ev_used < (int)c->ev_start.size();
+  const bool tuned = c->tune.recording;
+  if (tuned) (void)hipEventRecord(c->tune.ev0, s);
   if (timed) (void)hipEventRecord(c->ev_start[c->ev_used], s);
   launch_walk(c, n, out, s);
   if (timed) (void)hipEventRecord(c->ev_stop[c->ev_used++], s);
+  if (tuned) (void)hipEventRecord(c->tune.ev1, s);
 }
 
+// One evaluation (eager).  rebuild = false walks the tree of the last build
+// with the current positions.  The construction is timed when the rebuild
+// models are being fed.
 static int enqueue_forces(gothic_ctx *c, const Systems &sy, const float4 *xyzm,
-                          const uint8_t *active, float4 *out, hipStream_t s) {
-  enqueue_pre_walk(c, sy, xyzm, active, s);
+                          const uint8_t *active, float4 *out, hipStream_t s, float r_crit,
+                          bool rebuild) {
+  enqueue_begin(c, !rebuild, r_crit, s);
+  enqueue_upload(c, sy, s);
+  if (rebuild) {
+    const bool tm = c->tune.recording && c->tree.mk0;
+    if (tm) (void)hipEventRecord(c->tree.mk0, s);
+    enqueue_make(c, sy, xyzm, s);
+    if (tm) (void)hipEventRecord(c->tree.mk1, s);
+  }
+  enqueue_post(c, sy, xyzm, active, s);
   enqueue_walk(c, sy.n, out, s, true);
   return hip_check(hipGetLastError(), "kernel launch");
 }
@@ -349,8 +408,117 @@ static int64_t nodes_wanted(gothic_ctx *c, int64_t n, int nsys) {
                                              : n + 8 * (n / c->prm.n_leaf) + 1024 + nsys);
 }
 
+// ---------------------------------------------------------------- tree reuse
+// Does this evaluation build a new tree?  Always when there is no tree for
+// these systems (or the buffers or the tree parameters changed since it was
+// built); otherwise by params.rebuild_interval: 1 every time, k > 1 after k
+// evaluations on one tree, 0 when the paper's growth models say so.
+static bool must_rebuild(gothic_ctx *c, const Systems &sy) {
+  const TreeState &T = c->tree;
+  if (!T.valid || T.n != sy.n || T.off != sy.off || T.buffers != c->buffers ||
+      T.n_leaf != c->prm.n_leaf || T.key_kind != c->prm.key_kind)
+    return true;
+  const int k = c->prm.rebuild_interval;
+  if (k == 1) return true;
+  if (k >= 2) return T.since >= k;
+  return T.models.due();
+}
+
+static void tree_used(gothic_ctx *c, const Systems &sy, bool rebuilt) {
+  TreeState &T = c->tree;
+  if (rebuilt) {
+    T.valid = true;
+    T.n = sy.n;
+    T.off = sy.off;
+    T.n_leaf = c->prm.n_leaf;
+    T.key_kind = c->prm.key_kind;
+    T.buffers = c->buffers;
+    T.since = 1;
+  } else {
+    ++T.since;
+  }
+}
+
+// ---------------------------------------------------------------- measurement
+// The online tuners (params.autotune: r_crit per sub-step class;
+// rebuild_interval = 0: the growth models) are fed with the walk time of each
+// evaluation and the construction time of each rebuild, read one evaluation
+// late so the host does not wait for the walk it has just enqueued.
+static bool metering(const gothic_ctx *c) {
+  return c->prm.autotune || c->prm.rebuild_interval == 0;
+}
+
+static int meter_prepare(gothic_ctx *c) {
+  TuneState &T = c->tune;
+  TreeState &R = c->tree;
+  int rc;
+  if (!T.ev0 && (rc = hip_check(hipEventCreate(&T.ev0), "hipEventCreate"))) return rc;
+  if (!T.ev1 && (rc = hip_check(hipEventCreate(&T.ev1), "hipEventCreate"))) return rc;
+  if (!R.mk0 && (rc = hip_check(hipEventCreate(&R.mk0), "hipEventCreate"))) return rc;
+  if (!R.mk1 && (rc = hip_check(hipEventCreate(&R.mk1), "hipEventCreate"))) return rc;
+  if (!T.ready) {
+    for (auto &t : T.cls) t.init(-12.0, 0.0, 0.25, 20);
+    T.ready = true;
+    T.pending = -1;
+  }
+  return GOTHIC_OK;
+}
+
+// weight of sub-step class k among kmax + 1 classes (how often it occurs)
+static double class_weight(int k, int kmax) {
+  return std::ldexp(1.0, k < kmax ? -(k + 1) : -kmax);
+}
+
+static int meter_collect(gothic_ctx *c, int kmax) {
+  TuneState &T = c->tune;
+  TreeState &R = c->tree;
+  if (T.pending < 0) return GOTHIC_OK;
+  const int k = T.pending;
+  T.pending = -1;
+  int rc;
+  if ((rc = hip_check(hipEventSynchronize(T.ev1), "hipEventSynchronize"))) return rc;
+  float walk = 0.f;
+  if ((rc = hip_check(hipEventElapsedTime(&walk, T.ev0, T.ev1), "hipEventElapsedTime"))) return rc;
+  if (T.pending_tuned) T.cls[k].observe((double)walk);
+  if (c->prm.rebuild_interval == 0) {
+    if (T.pending_rebuilt) {
+      float make = 0.f;
+      if ((rc = hip_check(hipEventElapsedTime(&make, R.mk0, R.mk1), "hipEventElapsedTime")))
+        return rc;
+      R.models.rebuilt((double)make);
+      for (bool &f : R.fresh) f = false;
+    }
+    // walk times of different sub-step classes (different due levels) are
+    // put on one scale: relative to the class's time on a fresh tree, times
+    // the mean over classes of those times
+    if (!R.fresh[k]) {
+      R.ref[k] = walk;
+      R.have_ref[k] = true;
+      R.fresh[k] = true;
+    }
+    double num = 0.0, den = 0.0;
+    for (int j = 0; j <= kmax && j < 32; ++j)
+      if (R.have_ref[j]) {
+        num += class_weight(j, kmax) * R.ref[j];
+        den += class_weight(j, kmax);
+      }
+    const double scaled = (R.ref[k] > 0.0 && den > 0.0) ? walk * (num / den) / R.ref[k] : walk;
+    R.models.sample(scaled);
+  }
+  return GOTHIC_OK;
+}
+
+// note the evaluation just enqueued for the next collection
+static void meter_mark(gothic_ctx *c, int k, bool rebuilt, bool tuned) {
+  TuneState &T = c->tune;
+  T.pending = k;
+  T.pending_rebuilt = rebuilt;
+  T.pending_tuned = tuned;
+}
+
 static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const uint8_t *active,
-                      float4 *o4, hipStream_t s) {
+                      float4 *o4, hipStream_t s, float r_crit, int meter_class = 0,
+                      bool tuned = false, int kmax = 0) {
   const int64_t n = sy.n;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(s, &cap);
@@ -365,14 +533,21 @@ static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const 
   int rc = ensure(c, n, sy.nsys, want_nodes, c->spill_per_wave);
   if (rc) return rc;
   if ((rc = ensure_events(c))) return rc;
+  const bool meter = metering(c) && !capturing;
+  if (meter && ((rc = meter_prepare(c)) || (rc = meter_collect(c, kmax)))) return rc;
   c->last_n = n;
   c->last_nsys = sy.nsys;
   c->last_stream = s;
   c->have_last = true;
+  bool rebuild = must_rebuild(c, sy);
   constexpr int kAttempts = 6;
   for (int attempt = 0; attempt < kAttempts; ++attempt) {
-    if ((rc = enqueue_forces(c, sy, x4, active, o4, s))) return rc;
-    if (!c->prm.check || capturing) return GOTHIC_OK;
+    c->tune.recording = meter;
+    rc = enqueue_forces(c, sy, x4, active, o4, s, r_crit, rebuild);
+    c->tune.recording = false;
+    if (rc) return rc;
+    tree_used(c, sy, rebuild);
+    if (!c->prm.check || capturing) break;
     if ((rc = hip_check(hipMemcpyAsync(c->b.ctl_host, c->b.ctl, sizeof(Ctl),
                                        hipMemcpyDeviceToHost, s), "hipMemcpyAsync")))
       return rc;
@@ -381,8 +556,18 @@ static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const 
     if (f & kFlagNonFinite) return set_error(GOTHIC_ENONFINITE, "non-finite position or mass");
     if (f & kFlagBadIndex)
       return set_error(GOTHIC_EDEVICE, "internal index check failed (flags " + std::to_string(f) + ")");
-    if (!(f & (kFlagNodeOverflow | kFlagSpillOverflow))) return GOTHIC_OK;
-    if (attempt == kAttempts - 1) break;
+    if (!(f & (kFlagNodeOverflow | kFlagSpillOverflow))) break;
+    if (attempt == kAttempts - 1) {
+      const Ctl &h = *c->b.ctl_host;
+      std::string msg = "node or frontier capacity still exceeded after growing (flags " +
+                        std::to_string(h.flags) + ", nodes " + std::to_string(h.n_nodes) +
+                        " of " + std::to_string(c->cap_nodes) + ", groups " +
+                        std::to_string(h.n_groups) + ", spill/wave " +
+                        std::to_string(c->spill_per_wave) + ", level starts";
+      for (int l = 0; l < kMaxLevels + 1; ++l) msg += " " + std::to_string(h.lvl_start[l]);
+      c->tree.valid = false;
+      return set_error(GOTHIC_EOVERFLOW, msg + ")");
+    }
     // the abandoned level already knows how many nodes it needed at least
     int64_t need = 0;
     for (int l = 0; l < kMaxLevels + 1; ++l)
@@ -392,14 +577,10 @@ static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const 
         (f & kFlagNodeOverflow) ? std::max<int64_t>(2 * c->cap_nodes, 2 * need) : c->cap_nodes;
     const int64_t spill = (f & kFlagSpillOverflow) ? 4 * c->spill_per_wave : c->spill_per_wave;
     if ((rc = ensure(c, n, sy.nsys, nodes, spill))) return rc;
+    rebuild = true;  // the grown buffers hold no tree
   }
-  const Ctl &h = *c->b.ctl_host;
-  std::string msg = "node or frontier capacity still exceeded after growing (flags " +
-                    std::to_string(h.flags) + ", nodes " + std::to_string(h.n_nodes) + " of " +
-                    std::to_string(c->cap_nodes) + ", groups " + std::to_string(h.n_groups) +
-                    ", spill/wave " + std::to_string(c->spill_per_wave) + ", level starts";
-  for (int l = 0; l < kMaxLevels + 1; ++l) msg += " " + std::to_string(h.lvl_start[l]);
-  return set_error(GOTHIC_EOVERFLOW, msg + ")");
+  if (meter) meter_mark(c, meter_class, rebuild, tuned);
+  return GOTHIC_OK;
 }
 
 }  // namespace gothic
@@ -420,6 +601,8 @@ void gothic_default_params(gothic_params *p) {
   p->timing = 0;
   p->r_crit = -0.0625f;
   p->graph = 0;
+  p->autotune = 0;
+  p->rebuild_interval = 1;
   p->node_capacity = 0;
 }
 
@@ -456,6 +639,10 @@ int gothic_destroy(gothic_ctx *c) {
     (void)hipDeviceSynchronize();
     free_graphs(c);
     if (c->graphs.cap_stream) (void)hipStreamDestroy(c->graphs.cap_stream);
+    if (c->tune.ev0) (void)hipEventDestroy(c->tune.ev0);
+    if (c->tune.ev1) (void)hipEventDestroy(c->tune.ev1);
+    if (c->tree.mk0) (void)hipEventDestroy(c->tree.mk0);
+    if (c->tree.mk1) (void)hipEventDestroy(c->tree.mk1);
     free_sim(c);
     free_events(c);
     free_all(c);
@@ -468,8 +655,15 @@ int gothic_set_params(gothic_ctx *c, const gothic_params *p) {
   if (!c || !p) return set_error(GOTHIC_EINVAL, "NULL argument");
   int rc = validate_params(p);
   if (rc) return rc;
+  // r_crit is read from device memory and check, timing and autotune act
+  // outside the captured segments: only the other fields invalidate them
+  const gothic_params &a = c->prm, &b = *p;
+  if (a.key_kind != b.key_kind || a.n_leaf != b.n_leaf || a.multipole != b.multipole ||
+      a.group_size != b.group_size || a.list_depth != b.list_depth ||
+      a.compensated != b.compensated || a.graph != b.graph ||
+      a.node_capacity != b.node_capacity)
+    ++c->generation;
   c->prm = *p;
-  ++c->generation;
   return GOTHIC_OK;
 }
 
@@ -495,7 +689,8 @@ int gothic_tree_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, f
   int rc = make_systems(1, off, &eps, &theta, false, &sy);
   if (rc) return rc;
   return run_forces(c, sy, reinterpret_cast<const float4 *>(xyzm), active,
-                    reinterpret_cast<float4 *>(acc_pot), reinterpret_cast<hipStream_t>(stream));
+                    reinterpret_cast<float4 *>(acc_pot), reinterpret_cast<hipStream_t>(stream),
+                    c->prm.r_crit);
 }
 
 int gothic_tree_forces_batched(gothic_ctx *c, int nsys, const int64_t *offsets, const float *xyzm,
@@ -511,7 +706,8 @@ int gothic_tree_forces_batched(gothic_ctx *c, int nsys, const int64_t *offsets, 
     return set_error(GOTHIC_EINVAL, "xyzm and acc_pot must not overlap");
   DeviceGuard guard(c->device);
   return run_forces(c, sy, reinterpret_cast<const float4 *>(xyzm), active,
-                    reinterpret_cast<float4 *>(acc_pot), reinterpret_cast<hipStream_t>(stream));
+                    reinterpret_cast<float4 *>(acc_pot), reinterpret_cast<hipStream_t>(stream),
+                    c->prm.r_crit);
 }
 
 int gothic_get_stats(gothic_ctx *c, gothic_stats *out) {
@@ -683,6 +879,17 @@ static int sim_bind_impl(gothic_ctx *c, const Systems &sy, double *pos, double *
   S.offsets = sy.off;
   S.eps = sy.eps;
   S.theta = sy.theta;
+  S.host_s = 0;
+  S.builds = 0;
+  S.kmax = kmax;
+  c->tune.ready = false;
+  c->tune.pending = -1;
+  {  // a new system: no tree to reuse, no growth history (the events stay)
+    hipEvent_t m0 = c->tree.mk0, m1 = c->tree.mk1;
+    c->tree = TreeState();
+    c->tree.mk0 = m0;
+    c->tree.mk1 = m1;
+  }
   ++c->generation;
   // per-system clocks and offsets (the host copies stay alive until the
   // stream has synchronised)
@@ -706,7 +913,7 @@ static int sim_bind_impl(gothic_ctx *c, const Systems &sy, double *pos, double *
   // t = 0 forces on every particle (synchronous, checked)
   const int saved = c->prm.check;
   c->prm.check = 1;
-  rc = run_forces(c, sy, S.shadow, nullptr, S.anew, s);
+  rc = run_forces(c, sy, S.shadow, nullptr, S.anew, s, c->prm.r_crit);
   c->prm.check = saved;
   if (rc) return rc;
   sim_launch_init(c, s);
@@ -754,8 +961,8 @@ static Systems sim_systems(const SimState &S) {
   return sy;
 }
 
-// Capture the three segments of a sub-step (before the walk, the walk, after
-// it) on the context's own stream; buffers are already sized by the bind.
+// Capture the segments of a sub-step on the context's own stream; buffers
+// are already sized by the bind.
 static int capture_step(gothic_ctx *c) {
   SimGraphs &G = c->graphs;
   SimState &S = c->sim;
@@ -769,18 +976,20 @@ static int capture_step(gothic_ctx *c) {
   if (sy.n > c->cap_n || sy.nsys > c->cap_sys || nodes_wanted(c, sy.n, sy.nsys) > c->cap_nodes ||
       walk_slots(c) != c->walk_waves)
     return set_error(GOTHIC_ECAPTURE, "scratch is not sized for this system; bind again");
-  for (int seg = 0; seg < 3; ++seg) {
+  for (int seg = 0; seg < kSegments; ++seg) {
     hipGraph_t g = nullptr;
     if ((rc = hip_check(hipStreamBeginCapture(G.cap_stream, hipStreamCaptureModeThreadLocal),
                         "hipStreamBeginCapture")))
       return rc;
-    if (seg == 0) {
-      sim_launch_predict(c, G.cap_stream);
-      enqueue_pre_walk(c, sy, S.shadow, S.act, G.cap_stream);
-    } else if (seg == 1) {
-      enqueue_walk(c, sy.n, S.anew, G.cap_stream, false);
-    } else {
-      sim_launch_correct(c, G.cap_stream);
+    switch (seg) {
+      case 0:
+        sim_launch_predict(c, G.cap_stream);
+        enqueue_upload(c, sy, G.cap_stream);
+        break;
+      case 1: enqueue_make(c, sy, S.shadow, G.cap_stream); break;
+      case 2: enqueue_post(c, sy, S.shadow, S.act, G.cap_stream); break;
+      case 3: enqueue_walk(c, sy.n, S.anew, G.cap_stream, false); break;
+      default: sim_launch_correct(c, G.cap_stream); break;
     }
     const int lrc = hip_check(hipGetLastError(), "kernel launch");
     rc = hip_check(hipStreamEndCapture(G.cap_stream, &g), "hipStreamEndCapture");
@@ -807,28 +1016,221 @@ int gothic_sim_step(gothic_ctx *c, void *stream) {
   if (!S.bound) return set_error(GOTHIC_EINVAL, "no system bound (gothic_sim_bind)");
   DeviceGuard guard(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  TuneState &T = c->tune;
   int rc;
+  // class of the coming sub-step: position of the lowest set bit of its index
+  const uint64_t snext = (uint64_t)(S.host_s + 1);
+  int cls = __builtin_ctzll(snext);
+  if (cls > S.kmax) cls = S.kmax;
+  float r_crit = c->prm.r_crit;
+  if (c->prm.autotune) {
+    if ((rc = meter_prepare(c))) return rc;
+    r_crit = -(float)std::exp2(T.cls[cls].current());
+  }
   if (c->prm.graph && !c->prm.check) {
     if ((rc = ensure_events(c))) return rc;
     if (!c->graphs.valid || c->graphs.generation != c->generation)
       if ((rc = capture_step(c))) return rc;
+    const Systems sy = sim_systems(S);
+    const bool meter = metering(c);
+    if (meter && ((rc = meter_prepare(c)) || (rc = meter_collect(c, S.kmax)))) return rc;
+    // the captured segments were built for these buffers: the reused tree
+    // must be one they built
+    const bool rebuild = must_rebuild(c, sy);
     c->last_n = S.n;
     c->last_nsys = S.nsys;
     c->last_stream = s;
     c->have_last = true;
     SimGraphs &G = c->graphs;
+    enqueue_begin(c, !rebuild, r_crit, s);
     if ((rc = hip_check(hipGraphLaunch(G.exec[0], s), "hipGraphLaunch"))) return rc;
+    if (rebuild) {
+      if (meter) (void)hipEventRecord(c->tree.mk0, s);
+      if ((rc = hip_check(hipGraphLaunch(G.exec[1], s), "hipGraphLaunch"))) return rc;
+      if (meter) (void)hipEventRecord(c->tree.mk1, s);
+    }
+    if ((rc = hip_check(hipGraphLaunch(G.exec[2], s), "hipGraphLaunch"))) return rc;
     const bool timed = c->prm.timing && c->ev_used < (int)c->ev_start.size();
+    if (meter) (void)hipEventRecord(T.ev0, s);
     if (timed) (void)hipEventRecord(c->ev_start[c->ev_used], s);
-    if ((rc = hip_check(hipGraphLaunch(G.exec[1], s), "hipGraphLaunch"))) return rc;
+    if ((rc = hip_check(hipGraphLaunch(G.exec[3], s), "hipGraphLaunch"))) return rc;
     if (timed) (void)hipEventRecord(c->ev_stop[c->ev_used++], s);
-    return hip_check(hipGraphLaunch(G.exec[2], s), "hipGraphLaunch");
+    if (meter) (void)hipEventRecord(T.ev1, s);
+    if ((rc = hip_check(hipGraphLaunch(G.exec[4], s), "hipGraphLaunch"))) return rc;
+    tree_used(c, sy, rebuild);
+    if (rebuild) ++S.builds;
+    if (meter) meter_mark(c, cls, rebuild, c->prm.autotune != 0);
+  } else {
+    sim_launch_predict(c, s);
+    rc = run_forces(c, sim_systems(S), S.shadow, S.act, S.anew, s, r_crit, cls,
+                    c->prm.autotune != 0, S.kmax);
+    if (rc) return rc;
+    if (c->tree.since == 1) ++S.builds;
+    sim_launch_correct(c, s);
+    if ((rc = hip_check(hipGetLastError(), "kernel launch"))) return rc;
   }
-  sim_launch_predict(c, s);
-  rc = run_forces(c, sim_systems(S), S.shadow, S.act, S.anew, s);
+  ++S.host_s;
+  return GOTHIC_OK;
+}
+
+int gothic_sim_get_tuning(gothic_ctx *c, int nclass, float *r_crit_best, int *searches) {
+  if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
+  if (nclass < 0 || nclass > kTuneClasses)
+    return set_error(GOTHIC_EINVAL, "nclass must be in 0..32");
+  const TuneState &T = c->tune;
+  for (int k = 0; k < nclass; ++k) {
+    const bool have = T.ready && T.cls[k].have_best;
+    if (r_crit_best) r_crit_best[k] = have ? -(float)std::exp2(T.cls[k].best) : 0.f;
+    if (searches) searches[k] = T.ready ? T.cls[k].searches : 0;
+  }
+  return GOTHIC_OK;
+}
+
+// One evaluation with the current tunables and a new tree, timed with the
+// tuner's events (enqueued directly: no checks, no user timing).  Flags make
+// it invalid.
+static int timed_eval(gothic_ctx *c, const Systems &sy, const float4 *x4, const uint8_t *act,
+                      float4 *o4, hipStream_t s, float r_crit, double *ms) {
+  TuneState &T = c->tune;
+  int rc;
+  if ((rc = ensure(c, sy.n, sy.nsys, nodes_wanted(c, sy.n, sy.nsys), c->spill_per_wave)))
+    return rc;
+  (void)hipEventRecord(T.ev0, s);
+  if ((rc = enqueue_forces(c, sy, x4, act, o4, s, r_crit, true))) return rc;
+  (void)hipEventRecord(T.ev1, s);
+  tree_used(c, sy, true);
+  if ((rc = hip_check(hipMemcpyAsync(c->b.ctl_host, c->b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
+                                     s), "hipMemcpyAsync")) ||
+      (rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize")))
+    return rc;
+  float t = 0.f;
+  if ((rc = hip_check(hipEventElapsedTime(&t, T.ev0, T.ev1), "hipEventElapsedTime"))) return rc;
+  *ms = c->b.ctl_host->flags ? HUGE_VAL : (double)t;
+  return GOTHIC_OK;
+}
+
+static int autotune_impl(gothic_ctx *c, const Systems &sy, const float4 *x4, const uint8_t *act,
+                         float4 *o4, hipStream_t s, gothic_tune_result *out) {
+  TuneState &T = c->tune;
+  int rc;
+  if ((rc = meter_prepare(c))) return rc;
+  T.pending = -1;  // the events are reused below
+  const gothic_params saved = c->prm;
+  // a checked evaluation with a new tree and the current tunables sizes the
+  // scratch and counts the active particles
+  c->prm.autotune = 0;
+  c->prm.rebuild_interval = 1;
+  rc = run_forces(c, sy, x4, act, o4, s, saved.r_crit);
+  c->prm = saved;
   if (rc) return rc;
-  sim_launch_correct(c, s);
-  return hip_check(hipGetLastError(), "kernel launch");
+  const int64_t na = c->b.ctl_host->n_active;
+  memset(out, 0, sizeof(*out));
+  out->group_size = c->prm.group_size;
+  out->list_depth = c->prm.list_depth;
+  out->r_crit = c->prm.r_crit;
+  if (na == 0) return GOTHIC_OK;
+  int lg_n = 0, lg_f = 0;
+  while ((int64_t)2 << lg_n <= sy.n) ++lg_n;
+  while (lg_f < 16 && ((na << (lg_f + 1)) <= sy.n)) ++lg_f;
+  const auto key = std::make_tuple(sy.nsys > 1 ? 1 : 0, lg_n, lg_f, c->prm.multipole);
+  auto hit = T.cache.find(key);
+  if (hit != T.cache.end()) {
+    *out = hit->second;
+    out->evaluations = 0;
+  } else {
+    c->prm.check = 0;
+    c->prm.timing = 0;
+    int evals = 0;
+    double best = HUGE_VAL;
+    int bestG = saved.group_size, bestD = saved.list_depth;
+    const int Gs[4] = {8, 16, 32, 64};
+    const int Ds[5] = {128, 256, 384, 512, 768};
+    for (int G : Gs)
+      for (int D : Ds) {
+        c->prm.group_size = G;
+        c->prm.list_depth = D;
+        double t1, t2;
+        if ((rc = timed_eval(c, sy, x4, act, o4, s, saved.r_crit, &t1)) ||
+            (rc = timed_eval(c, sy, x4, act, o4, s, saved.r_crit, &t2))) {
+          c->prm = saved;
+          return rc;
+        }
+        evals += 2;
+        const double t = std::min(t1, t2);
+        if (t < best) {
+          best = t;
+          bestG = G;
+          bestD = D;
+        }
+      }
+    c->prm.group_size = bestG;
+    c->prm.list_depth = bestD;
+    // Brent over log2(r_crit / L), the quantity the paper tunes
+    BrentMin bm;
+    bm.start(-12.0, 0.0, 0.25, 16);
+    double best_u = 0.0, best_rt = HUGE_VAL;
+    while (!bm.done()) {
+      const double u = bm.ask();
+      double t1, t2;
+      const float r = -(float)std::exp2(u);
+      if ((rc = timed_eval(c, sy, x4, act, o4, s, r, &t1)) ||
+          (rc = timed_eval(c, sy, x4, act, o4, s, r, &t2))) {
+        c->prm = saved;
+        return rc;
+      }
+      evals += 2;
+      const double t = std::min(t1, t2);
+      if (t < best_rt) {
+        best_rt = t;
+        best_u = u;
+      }
+      bm.tell(t);
+    }
+    c->prm = saved;
+    const float rbest = -(float)std::exp2(best_u);
+    const bool r_wins = best_rt < best;
+    out->group_size = bestG;
+    out->list_depth = bestD;
+    out->r_crit = r_wins ? rbest : saved.r_crit;
+    out->ms = r_wins ? best_rt : best;
+    out->evaluations = evals;
+    T.cache[key] = *out;
+  }
+  gothic_params chosen = c->prm;
+  chosen.group_size = out->group_size;
+  chosen.list_depth = out->list_depth;
+  chosen.r_crit = out->r_crit;
+  if ((rc = gothic_set_params(c, &chosen))) return rc;
+  // the caller's forces, with the chosen tunables, a new tree and the usual checks
+  c->prm.check = 1;
+  c->prm.autotune = 0;
+  c->prm.rebuild_interval = 1;
+  rc = run_forces(c, sy, x4, act, o4, s, c->prm.r_crit);
+  c->prm.check = chosen.check;
+  c->prm.autotune = chosen.autotune;
+  c->prm.rebuild_interval = chosen.rebuild_interval;
+  return rc;
+}
+
+int gothic_autotune(gothic_ctx *c, int nsys, const int64_t *offsets, const float *xyzm,
+                    const float *eps, const float *theta, const uint8_t *active,
+                    float *acc_pot, gothic_tune_result *out, void *stream) {
+  if (!c || !out) return set_error(GOTHIC_EINVAL, "NULL argument");
+  Systems sy;
+  int rc = make_systems(nsys, offsets, eps, theta, true, &sy);
+  if (rc) return rc;
+  if (sy.n == 0) return set_error(GOTHIC_EINVAL, "no particles to tune on");
+  if (!xyzm || !acc_pot) return set_error(GOTHIC_EINVAL, "xyzm and acc_pot must not be NULL");
+  if ((const void *)xyzm == (const void *)acc_pot)
+    return set_error(GOTHIC_EINVAL, "xyzm and acc_pot must not overlap");
+  DeviceGuard guard(c->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(s, &cap);
+  if (cap != hipStreamCaptureStatusNone)
+    return set_error(GOTHIC_ECAPTURE, "gothic_autotune times evaluations and cannot be captured");
+  return autotune_impl(c, sy, reinterpret_cast<const float4 *>(xyzm), active,
+                       reinterpret_cast<float4 *>(acc_pot), s, out);
 }
 
 int gothic_sim_reset_counters(gothic_ctx *c, void *stream) {
@@ -836,6 +1238,7 @@ int gothic_sim_reset_counters(gothic_ctx *c, void *stream) {
   if (!c->sim.bound) return set_error(GOTHIC_EINVAL, "no system bound (gothic_sim_bind)");
   DeviceGuard guard(c->device);
   sim_launch_reset(c, reinterpret_cast<hipStream_t>(stream));
+  c->sim.builds = 0;
   return hip_check(hipGetLastError(), "kernel launch");
 }
 
@@ -871,6 +1274,7 @@ int gothic_sim_get_info(gothic_ctx *c, gothic_sim_info *out) {
   out->active_total = (int64_t)h.active_total;
   out->interactions_total = (int64_t)h.inter_total;
   out->node_interactions_total = (int64_t)h.node_inter_total;
+  out->tree_builds = S.builds;
   for (int k = 0; k < 32; ++k) out->level_count[k] = (int64_t)h.level_count[k];
   return GOTHIC_OK;
 }

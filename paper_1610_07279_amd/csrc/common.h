@@ -4,10 +4,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/gothic.h"
+#include "tune.h"
 
 namespace gothic {
 
@@ -32,7 +35,8 @@ struct Ctl {
   unsigned nsys;                       // systems of the evaluation (roots 0 .. nsys-1)
   unsigned xwork[8];                   // per-XCD group counters of the persistent walk
   unsigned scan_total;                 // scratch: total of the last scan
-  unsigned pad0, pad1;
+  unsigned tree_ok;                    // the last build finished without overflow
+  unsigned pad1;
   unsigned long long node_entries;     // summed over groups
   unsigned long long part_entries;
   unsigned long long interactions;     // summed over active i
@@ -94,6 +98,7 @@ struct Buffers {
   // control
   Ctl *ctl = nullptr;
   Ctl *ctl_host = nullptr;        // pinned mirror for read-back
+  float *rcrit = nullptr;         // r_crit of the evaluation (device, set before each one)
 };
 
 // Block-step driver state on the device (sim.hip)
@@ -121,6 +126,9 @@ struct SimState {
   const float *mass = nullptr;            // caller-owned [n]
   std::vector<int64_t> offsets;           // host copy, nsys + 1
   std::vector<float> eps, theta;          // host copies, nsys
+  int64_t host_s = 0;                     // sub-steps enqueued since the bind
+  int64_t builds = 0;                     // of them, with a new tree (since the counter reset)
+  int kmax = 0;
   float4 *shadow = nullptr, *aold = nullptr, *anew = nullptr;
   int64_t *si = nullptr;
   uint8_t *lev = nullptr, *act = nullptr;
@@ -129,13 +137,49 @@ struct SimState {
   SimCtl *sc = nullptr, *sc_host = nullptr;
 };
 
-// Captured sub-step of the block-step driver (params.graph): before the
-// walk, the walk, after the walk (split so the walk can still be timed).
+// Captured sub-step of the block-step driver (params.graph), in segments:
+// predict + system table, tree construction (skipped when the tree is
+// reused), permute + moments + groups, walk, correct.  The pieces between
+// them (control block, r_crit) and the events timing the construction and
+// the walk are launched outside.
+constexpr int kSegments = 5;
 struct SimGraphs {
-  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t exec[kSegments] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   hipStream_t cap_stream = nullptr;
   uint64_t generation = 0;
   bool valid = false;
+};
+
+// The tree of the last build, for reuse between rebuilds (params.rebuild_interval).
+struct TreeState {
+  bool valid = false;
+  int64_t n = 0;
+  std::vector<int64_t> off;   // systems it was built for
+  int n_leaf = 0, key_kind = 0;
+  uint64_t buffers = 0;       // gothic_ctx::buffers when it was built
+  int since = 0;              // evaluations on this tree so far
+  RebuildModels models;       // rebuild_interval = 0: the paper's growth models
+  double ref[32] = {0};       // walk time of each sub-step class on a fresh tree
+  bool have_ref[32] = {false};
+  bool fresh[32] = {false};   // ref[k] measured since the last rebuild
+  hipEvent_t mk0 = nullptr, mk1 = nullptr;  // around the last construction
+};
+
+// Tuning state (params.autotune and gothic_autotune).  The online tuner keeps
+// one Brent search per active-level class of the block steps: the sub-steps
+// whose index has its lowest set bit at position c (all levels >= kmax - c
+// are due) are timed against each other only.
+constexpr int kTuneClasses = 32;
+struct TuneState {
+  OnlineTuner cls[kTuneClasses];
+  bool ready = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // walk of the last tuned sub-step
+  int pending = -1;                          // its class, or -1
+  bool pending_rebuilt = false;              // ... whether it built its tree
+  bool pending_tuned = false;                // ... whether its r_crit came from cls[]
+  bool recording = false;                    // record ev0 / ev1 around the next walk
+  // gothic_autotune results by (batched, log2 n, log2 of n / n_active, multipole)
+  std::map<std::tuple<int, int, int, int>, gothic_tune_result> cache;
 };
 
 }  // namespace gothic
@@ -149,6 +193,7 @@ struct gothic_ctx {
   int walk_waves = 0;             // persistent walk waves (slots)
   gothic::Buffers b;
   uint64_t generation = 1;        // bumped whenever a device buffer or a parameter changes
+  uint64_t buffers = 1;           // bumped whenever a device buffer is (re)allocated
   // last evaluation
   int64_t last_n = 0;
   int last_nsys = 0;
@@ -159,6 +204,8 @@ struct gothic_ctx {
   int ev_used = 0;
   gothic::SimState sim;
   gothic::SimGraphs graphs;
+  gothic::TuneState tune;
+  gothic::TreeState tree;
 };
 
 namespace gothic {

@@ -1,7 +1,8 @@
 // Active i-particles and their groups (Sections 2.3-2.4; block time steps,
 // Section 2.7).  The active particles are compacted in key order.  Following
 // Section 2.4, consecutive active particles farther apart than the critical
-// separation r_crit start a new group (the squared gap is compared with
+// separation r_crit (read from device memory, so a tuner can change it
+// between replays of a captured step) start a new group (the squared gap is compared with
 // r_crit^2 in float64 without fused operations, so the bounds are exact and
 // reproducible); every run between such gaps is cut into groups of at most G.
 // Each group gets its pseudo i-particle: the geometric centre r_I of the
@@ -37,11 +38,12 @@ __device__ __forceinline__ double gap2(float4 p, float4 q) {
 // brk[a] = 1 where a new run starts (first active particle of a system, or a
 // gap > r_crit; a negative r_crit is that fraction of the system's cube side)
 __global__ void __launch_bounds__(256)
-group_breaks_k(int64_t n, float r_crit, const Ctl *__restrict__ ctl,
+group_breaks_k(int64_t n, const float *__restrict__ rcrit, const Ctl *__restrict__ ctl,
                const uint32_t *__restrict__ soff, const SysRec *__restrict__ sys,
                const uint32_t *__restrict__ alist, const float4 *__restrict__ pos,
                uint32_t *__restrict__ brk) {
   const unsigned na = ctl->n_active, nsys = ctl->nsys;
+  const float r_crit = *rcrit;
   for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < na;
        a += (int64_t)gridDim.x * blockDim.x) {
     unsigned b = (a == 0);
@@ -136,7 +138,7 @@ void launch_groups(gothic_ctx *c, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(compact_k, dim3(g), dim3(256), 0, s, n, c->prm.group_size, B.flag, B.flag2,
                      B.alist, B.ctl);
   // runs between gaps > r_crit (flag: run breaks, flag2: run index, gA: run starts)
-  hipLaunchKernelGGL(group_breaks_k, dim3(g), dim3(256), 0, s, n, c->prm.r_crit, B.ctl, B.soff,
+  hipLaunchKernelGGL(group_breaks_k, dim3(g), dim3(256), 0, s, n, B.rcrit, B.ctl, B.soff,
                      B.sys, B.alist, B.pos, B.flag);
   scan_exclusive(B.flag, B.flag2, 0, na_dev, nullptr, n, &B.ctl->scan_total, B.part, s);
   hipLaunchKernelGGL(group_runs_k, dim3(g), dim3(256), 0, s, B.ctl, B.flag, B.flag2, B.gA);

@@ -192,6 +192,7 @@ __global__ void build_final_k(Ctl *ctl, int64_t cap_nodes) {
   if (threadIdx.x == 0) {
     int64_t e = ctl->lvl_start[kMaxLevels];
     ctl->n_nodes = (unsigned)(e > cap_nodes ? cap_nodes : e);
+    ctl->tree_ok = (ctl->flags & kFlagNodeOverflow) ? 0u : 1u;
   }
 }
 

@@ -31,6 +31,7 @@
 //   monopole    a += M d / R^3,  phi -= M / R
 //   quadrupole  a += d (7.5 q / R^7 - 1.5 tr S / R^5) - 3 S d / R^5,
 //               phi -= 1.5 q / R^5 - 0.5 tr S / R^3,   q = d.S.d
+// (evaluated in the factored form given at flush()).
 // (second-order Taylor term of the softened kernel about the centre of mass).
 // The self pair adds no force and m_i/eps to -phi, which is removed.
 #include "common.h"
@@ -80,11 +81,24 @@ struct Acc {
   float cx, cy, cz, cp; // compensation terms
 };
 
-template <int MULTI>
-__device__ __forceinline__ void flush(const WalkArgs &a, const float4 *pl, const float4 *ql0,
-                                      const float4 *ql1, const float4 *ql2, int np, int nq,
-                                      float4 pi, float eps2, int sub, int S, Acc &acc) {
+// Lanes per i-particle S = 2^LOGS; LOGS < 0 reads it at run time.  A
+// compile-time S lets the unrolled list reads use immediate LDS offsets.
+template <int LOGS>
+__device__ __forceinline__ int lanes_per_i(int S) {
+  return LOGS >= 0 ? (1 << LOGS) : S;
+}
+
+// Quadrupole list entries hold three float4 (one LDS array, 48 bytes each):
+//   (x, y, z, M), (3Sxx, 3Syy, 3Szz, 3Sxy), (3Sxz, 3Syz, -tr/2, -3tr/2)
+// so that with d = r_J - r_i, ri = 1/R, u = ri^2, s = 3 S d, w = 1.5 u d.S.d:
+//   a   += d ri^3 (M + u (5 w - 1.5 tr)) - u ri^3 s
+//   phi -= ri (M + u (w - 0.5 tr))
+template <int MULTI, int LOGS>
+__device__ __forceinline__ void flush(const WalkArgs &a, const float4 *pl, const float4 *ql,
+                                      int np, int nq, float4 pi, float eps2, int sub, int S_rt,
+                                      Acc &acc) {
   wave_sync();
+  const int S = lanes_per_i<LOGS>(S_rt);
   float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
 #pragma unroll 4
   for (int k = sub; k < np; k += S) {
@@ -102,24 +116,24 @@ __device__ __forceinline__ void flush(const WalkArgs &a, const float4 *pl, const
   if (MULTI == 2) {
 #pragma unroll 2
     for (int k = sub; k < nq; k += S) {
-      const float4 q0 = ql0[k], q1 = ql1[k], q2 = ql2[k];
+      const float4 q0 = ql[3 * k], q1 = ql[3 * k + 1], q2 = ql[3 * k + 2];
       const float dx = q0.x - pi.x, dy = q0.y - pi.y, dz = q0.z - pi.z;
       const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
       const float ri = __builtin_amdgcn_rsqf(r2);
-      const float ri2 = ri * ri;
-      const float r3 = ri * ri2, r5 = r3 * ri2, r7 = r5 * ri2;
-      // S = (xx yy zz xy | xz yz tr)
-      const float sdx = fmaf(q1.x, dx, fmaf(q1.w, dy, q2.x * dz));
-      const float sdy = fmaf(q1.w, dx, fmaf(q1.y, dy, q2.y * dz));
-      const float sdz = fmaf(q2.x, dx, fmaf(q2.y, dy, q1.z * dz));
-      const float qq = fmaf(dx, sdx, fmaf(dy, sdy, dz * sdz));
-      const float tr = q2.z;
-      const float coef = fmaf(q0.w, r3, fmaf(7.5f * qq, r7, -1.5f * tr * r5));
-      const float s3 = 3.f * r5;
-      fx = fmaf(coef, dx, fmaf(-s3, sdx, fx));
-      fy = fmaf(coef, dy, fmaf(-s3, sdy, fy));
-      fz = fmaf(coef, dz, fmaf(-s3, sdz, fz));
-      fp += fmaf(q0.w, ri, fmaf(1.5f * qq, r5, -0.5f * tr * r3));
+      const float u = ri * ri;
+      const float ri3 = ri * u;
+      // s = 3 S d   (q1 = 3(xx yy zz xy), q2 = 3(xz yz) | -tr/2, -3tr/2)
+      const float sx = fmaf(q1.x, dx, fmaf(q1.w, dy, q2.x * dz));
+      const float sy = fmaf(q1.w, dx, fmaf(q1.y, dy, q2.y * dz));
+      const float sz = fmaf(q2.x, dx, fmaf(q2.y, dy, q1.z * dz));
+      const float q3 = fmaf(dx, sx, fmaf(dy, sy, dz * sz));  // 3 d.S.d
+      const float w = (0.5f * u) * q3;                         // 1.5 u d.S.d
+      const float coef = ri3 * fmaf(u, fmaf(5.0f, w, q2.w), q0.w);
+      const float r5 = ri3 * u;
+      fx = fmaf(-r5, sx, fmaf(coef, dx, fx));
+      fy = fmaf(-r5, sy, fmaf(coef, dy, fy));
+      fz = fmaf(-r5, sz, fmaf(coef, dz, fz));
+      fp = fmaf(ri, fmaf(u, w + q2.z, q0.w), fp);
     }
   }
   if (a.compensated) {
@@ -133,17 +147,15 @@ __device__ __forceinline__ void flush(const WalkArgs &a, const float4 *pl, const
   wave_sync();
 }
 
-template <int MULTI>
+template <int MULTI, int LOGS>
 __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   extern __shared__ float4 smem[];
   const int w = threadIdx.x >> 6;
   const int lane = lane_id();
   char *wbase = reinterpret_cast<char *>(smem) + (size_t)w * a.wave_bytes;
   float4 *pl = reinterpret_cast<float4 *>(wbase);
-  float4 *ql0 = pl + a.D;
-  float4 *ql1 = ql0 + (MULTI == 2 ? a.DQ : 0);
-  float4 *ql2 = ql1 + (MULTI == 2 ? a.DQ : 0);
-  uint32_t *queue = reinterpret_cast<uint32_t *>(ql2 + (MULTI == 2 ? a.DQ : 0));
+  float4 *ql = pl + a.D;  // quadrupole entries, three float4 each
+  uint32_t *queue = reinterpret_cast<uint32_t *>(ql + (MULTI == 2 ? 3 * a.DQ : 0));
   uint32_t *tpre = queue + kQueueCap;
   uint32_t *tsrc = tpre + 64;
 
@@ -244,21 +256,22 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       if (nacc) {
         if (MULTI == 1) {
           if (np + nacc > D) {
-            flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, eps2, sub, S, acc);
+            flush<MULTI, LOGS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
             np = 0; nq = 0;
           }
           if (accept) pl[np + lanes_below(am)] = r0;
           np += nacc;
         } else {
           if (nq + nacc > DQ) {
-            flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, eps2, sub, S, acc);
+            flush<MULTI, LOGS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
             np = 0; nq = 0;
           }
           if (accept) {
             const int q = nq + (int)lanes_below(am);
-            ql0[q] = r0;
-            ql1[q] = a.quad[2 * (size_t)node];
-            ql2[q] = a.quad[2 * (size_t)node + 1];
+            const float4 s0 = a.quad[2 * (size_t)node], s1 = a.quad[2 * (size_t)node + 1];
+            ql[3 * q] = r0;
+            ql[3 * q + 1] = make_float4(3.f * s0.x, 3.f * s0.y, 3.f * s0.z, 3.f * s0.w);
+            ql[3 * q + 2] = make_float4(3.f * s1.x, 3.f * s1.y, -0.5f * s1.z, -1.5f * s1.z);
           }
           nq += nacc;
         }
@@ -304,7 +317,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
         wave_sync();
         for (unsigned t0 = 0; t0 < P; t0 += 64) {
           if (np + 64 > D) {
-            flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, eps2, sub, S, acc);
+            flush<MULTI, LOGS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
             np = 0; nq = 0;
           }
           const unsigned t = t0 + lane;
@@ -323,7 +336,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       }
     }
     if (pops > (unsigned long long)nn) atomicOr(&ctl->flags, kFlagBadIndex);
-    flush<MULTI>(a, pl, ql0, ql1, ql2, np, nq, pi, eps2, sub, S, acc);
+    flush<MULTI, LOGS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
 
     float ax = acc.x + acc.cx, ay = acc.y + acc.cy, az = acc.z + acc.cz, ap = acc.p + acc.cp;
     for (int m = G; m < 64; m <<= 1) {
@@ -376,6 +389,29 @@ static int waves_per_block(int wb) {
   return w >= 4 ? 4 : (w < 1 ? 1 : w);
 }
 
+// walk_k<MULTI, LOGS> for the S = 64 / G the launch uses: compile-time S for
+// G = 64, 32, 16, 8 (the tuner's candidates), run-time S otherwise
+typedef void (*WalkFn)(WalkArgs);
+static WalkFn walk_fn(int multi, int G) {
+  const int S = 64 / G;
+  if (multi == 2) {
+    switch (S) {
+      case 1: return walk_k<2, 0>;
+      case 2: return walk_k<2, 1>;
+      case 4: return walk_k<2, 2>;
+      case 8: return walk_k<2, 3>;
+      default: return walk_k<2, -1>;
+    }
+  }
+  switch (S) {
+    case 1: return walk_k<1, 0>;
+    case 2: return walk_k<1, 1>;
+    case 4: return walk_k<1, 2>;
+    case 8: return walk_k<1, 3>;
+    default: return walk_k<1, -1>;
+  }
+}
+
 int walk_slots(gothic_ctx *c) {
   const int multi = c->prm.multipole;
   int D, DQ;
@@ -383,11 +419,8 @@ int walk_slots(gothic_ctx *c) {
   const int wb = wave_bytes_for(multi, D, DQ);
   const int wpb = waves_per_block(wb);
   int per_cu = 0;
-  hipError_t e;
-  if (multi == 2)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walk_k<2>, wpb * 64, wpb * wb);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walk_k<1>, wpb * 64, wpb * wb);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, walk_fn(multi, c->prm.group_size), wpb * 64, wpb * wb);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   return c->num_cus * per_cu * wpb;
 }
@@ -421,10 +454,7 @@ void launch_walk(gothic_ctx *c, int64_t n, float4 *acc_pot, hipStream_t s) {
   const int wpb = waves_per_block(a.wave_bytes);
   const int slots = c->walk_waves;
   const int blocks = slots / wpb;
-  if (multi == 2)
-    hipLaunchKernelGGL(walk_k<2>, dim3(blocks), dim3(wpb * 64), wpb * a.wave_bytes, s, a);
-  else
-    hipLaunchKernelGGL(walk_k<1>, dim3(blocks), dim3(wpb * 64), wpb * a.wave_bytes, s, a);
+  hipLaunchKernelGGL(walk_fn(multi, a.G), dim3(blocks), dim3(wpb * 64), wpb * a.wave_bytes, s, a);
 }
 
 }  // namespace gothic

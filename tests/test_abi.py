@@ -30,7 +30,8 @@ def test_defaults_and_cpu_only_errors():
     import paper_1610_07279_amd as g
     p = g.default_params()
     assert (p.key_kind, p.n_leaf, p.multipole, p.group_size, p.list_depth, p.compensated,
-            p.check, p.timing, p.graph, p.node_capacity) == (0, 16, 1, 32, 384, 1, 1, 0, 0, 0)
+            p.check, p.timing, p.graph, p.autotune, p.node_capacity) == \
+        (0, 16, 1, 32, 384, 1, 1, 0, 0, 0, 0)
     assert p.r_crit == -0.0625
     # a NULL context is rejected before any device call
     rc = g.lib.gothic_tree_forces(None, 10, None, ctypes.c_float(0.1), ctypes.c_float(0.5),
@@ -48,7 +49,8 @@ def test_ctypes_structs_match_the_header(tmp_path):
     import paper_1610_07279_amd as g
     if shutil.which("gcc") is None:
         pytest.skip("no host C compiler")
-    structs = {"gothic_params": g.Params, "gothic_stats": g.Stats, "gothic_sim_info": g.SimInfo}
+    structs = {"gothic_params": g.Params, "gothic_stats": g.Stats, "gothic_sim_info": g.SimInfo,
+               "gothic_tune_result": g.TuneResult}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gothic.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

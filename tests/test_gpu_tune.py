@@ -1,0 +1,126 @@
+"""Tuning (Section 2.4: r_crit by Brent's method on the measured time, kept
+perturbed; plus the group size and list budget) through the C ABI.
+
+Tuning chooses among configurations that are all exact evaluations of the
+method, so the checks are: the choice is one of the candidates, the forces
+of the chosen configuration match the float64 oracle run with the same
+configuration, the cache answers a repeated bucket without timing, the
+online tuner finishes searches while the block steps stay valid, and a
+captured sub-step reads r_crit from device memory.
+"""
+import numpy as np
+import pytest
+
+import ics
+import oracle
+from gpu_util import rel_rms, say, tie_params
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1610_07279_amd as g  # noqa: E402
+
+
+def _oracle_rms(x, eps, theta, out, active, **kw):
+    ref = oracle.tree_forces(x, eps, theta, active=active, **kw, **tie_params())
+    og = ref["groups"]
+    clean = ref["counts"][:, 2] == 0
+    rows = np.concatenate([og["alist"][og["first"][q]:og["first"][q] + og["count"][q]]
+                           for q in np.flatnonzero(clean)])
+    orig = ref["perm"][rows]
+    return rel_rms(out[orig], ref["acc_pot"][orig]), clean.mean()
+
+
+def test_autotune_choice_cache_and_parity():
+    n, eps, theta = 30000, 1 / 128, 0.5
+    x = ics.nfw(n, seed=81)
+    act = ics.random_active(n, 0.25, seed=82)
+    xt = torch.from_numpy(x).cuda()
+    at = torch.from_numpy(act).cuda()
+    ctx = g.Context(device=0, multipole=2)
+    out = torch.full((n, 4), float("nan"), device="cuda")
+    say("[gpu] autotune NFW 30000, 25% active")
+    res = ctx.autotune(xt, eps, theta, active=at, out=out)
+    say(f"  {res}")
+    assert res["group_size"] in (8, 16, 32, 64)
+    assert res["list_depth"] in (128, 256, 384, 512, 768)
+    assert res["r_crit"] < 0 and res["evaluations"] > 40 and res["ms"] > 0
+    p = ctx.params
+    assert (p["group_size"], p["list_depth"]) == (res["group_size"], res["list_depth"])
+    assert p["r_crit"] == pytest.approx(res["r_crit"])
+    o = out.cpu().numpy()
+    assert np.all(np.isnan(o[act == 0])) and np.all(np.isfinite(o[act == 1]))
+    e, clean = _oracle_rms(x, eps, theta, o, act, multipole=2, group_size=res["group_size"],
+                           r_crit=res["r_crit"])
+    say(f"  chosen configuration vs oracle: rms {e:.2e}, tie-free groups {clean:.3f}")
+    assert e <= 1e-5 and clean >= 0.9
+    # same bucket: from the cache, identical choice
+    res2 = ctx.autotune(xt, eps, theta, active=at, out=out)
+    assert res2["evaluations"] == 0
+    assert (res2["group_size"], res2["list_depth"], res2["r_crit"]) == \
+        (res["group_size"], res["list_depth"], res["r_crit"])
+    # another active fraction is another bucket
+    res3 = ctx.autotune(xt, eps, theta, out=out)
+    assert res3["evaluations"] > 0
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_online_rcrit_tuning_in_block_steps(graph):
+    kmax = 3
+    x, v = ics.nfw(20000, seed=83, with_vel=True)
+    say(f"[gpu] online r_crit tuning, graph={graph}")
+    runs = []
+    for tune in (0, 1):
+        ctx = g.Context(device=0, multipole=2, graph=graph, autotune=tune)
+        pos = torch.from_numpy(x[:, :3].astype(np.float64)).cuda()
+        vel = torch.from_numpy(v).cuda()
+        mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).cuda()
+        ctx.sim_bind(pos, vel, mass, 1 / 128, 0.5, eta=0.1, kmax=kmax)
+        ctx.set_params(check=0)
+        ctx.sim_step(16 << kmax)
+        torch.cuda.synchronize()
+        assert ctx.stats()["flags"] == 0
+        runs.append((ctx, pos.cpu().numpy(), vel.cpu().numpy()))
+    (c0, p0, _), (c1, p1, _) = runs
+    r, k = c1.sim_tuning(kmax + 1)
+    say(f"  searches per class {k.tolist()}, best r_crit {r.tolist()}")
+    assert k[0] >= 2 and k[1] >= 1
+    assert np.all(r[k > 0] < 0)
+    # the tuned run follows the untuned one (different groups only change the
+    # truncation error of the tree force)
+    dx = np.abs(p1 - p0).max(1) / (np.abs(p0).max(1) + 1e-3)
+    say(f"  position difference to the untuned run: p99 {np.percentile(dx, 99):.2e}")
+    assert np.percentile(dx, 99) < 1e-3
+    i0, i1 = c0.sim_info(), c1.sim_info()
+    assert i0["substep"] == i1["substep"] == 16 << kmax
+
+
+def test_captured_step_reads_rcrit_from_device():
+    kmax = 3
+    x, v = ics.plummer(5000, seed=84, with_vel=True)
+    say("[gpu] r_crit changed between replays without re-capture")
+    runs = []
+    for graph in (0, 1):
+        ctx = g.Context(device=0, graph=graph, r_crit=-0.0625)
+        pos = torch.from_numpy(x[:, :3].astype(np.float64)).cuda()
+        vel = torch.from_numpy(v).cuda()
+        mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).cuda()
+        ctx.sim_bind(pos, vel, mass, 1 / 64, 0.5, eta=0.1, kmax=kmax)
+        ctx.set_params(check=0)
+        runs.append((ctx, pos, vel))
+    groups = []
+    for phase, rc in enumerate((-0.0625, 0.02, -0.0625)):
+        for ctx, _, _ in runs:
+            ctx.set_params(r_crit=rc)
+        for step in range(1 << kmax):
+            for ctx, _, _ in runs:
+                ctx.sim_step()
+            torch.cuda.synchronize()
+            (c0, p0, v0), (c1, p1, v1) = runs
+            assert torch.equal(p0, p1) and torch.equal(v0, v1), (phase, step)
+        groups.append(runs[1][0].stats()["n_groups"])
+    say(f"  groups at the last sub-step of each phase {groups}")
+    assert groups[1] != groups[0] and groups[2] == groups[0]

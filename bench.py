@@ -9,7 +9,9 @@ finest.  Inputs are synthetic (seeded generator), resident on the GPU before
 timing.
 
 One "step" is one finest sub-step of the block scheme: predict every
-particle, build keys / sort / octree / moments, walk the groups of the
+particle, build keys / sort / octree when the tree is rebuilt (by default
+when the growth models of Section 2.6 say so, otherwise the last tree is
+walked with the current positions), moments, groups, walk the groups of the
 particles due at that time, correct them and assign new levels.  The same
 number of shared steps (every particle at the finest step, leap-frog) is timed
 for the block-versus-shared comparison.
@@ -34,6 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32, 256 CU x 2.4 GHz x 256 flop/clk
+                                  # (packed FP32; one non-packed FMA per lane-slot is half)
 FLOP_MONO = 24                    # per monopole interaction (20 + rsqrt weighted 4)
 FLOP_QUAD = 60                    # per quadrupole node interaction (operations of the factored
                                   # quadrupole term, rsq weighted 4)
@@ -210,6 +213,9 @@ def main():
                     help="critical separation splitting groups (Section 2.4)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-shared", action="store_true", help="skip the shared-step run")
+    ap.add_argument("--rebuild-interval", type=int, default=0,
+                    help="tree reuse: 0 = automatic (the growth models of Section 2.6), "
+                         "1 = new tree every sub-step, k = every k sub-steps")
     ap.add_argument("--graph", type=int, default=1, choices=(0, 1),
                     help="replay each timed sub-step as captured HIP graphs (default 1)")
     ap.add_argument("--no-batched", action="store_true",
@@ -247,7 +253,8 @@ def main():
     vel0 = torch.from_numpy(v).to(dev)
     mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).to(dev)
     ctx = g.Context(device=0, multipole=multipole, group_size=args.group_size,
-                    list_depth=args.list_depth, r_crit=args.r_crit, timing=1, graph=args.graph)
+                    list_depth=args.list_depth, r_crit=args.r_crit, timing=1, graph=args.graph,
+                    rebuild_interval=args.rebuild_interval)
 
     log(f"bench: block steps (warmup {args.warmup}, timed {args.steps})")
     blk = run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, False, args.steps, args.warmup)
@@ -283,20 +290,25 @@ def main():
                                f"block steps kmax=8 (eta=0.1), finest sub-steps",
                    "n": n, "group_size": args.group_size, "list_depth": args.list_depth,
                    "r_crit": args.r_crit, "graph": args.graph,
+                   "rebuild_interval": args.rebuild_interval,
                    "parallelism": "single GPU"},
         "block": {"s_per_step": blk["seconds"] / args.steps,
                   "interactions_per_s": inter / blk["seconds"],
                   "active_per_step": ib["active_total"] / args.steps,
                   "level_count": ib["level_count"][:kmax + 1],
+                  "tree_builds": ib["tree_builds"],
                   "walk_ms_per_step": blk["walk_ms"] / max(blk["walk_launches"], 1)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "peak_nonpacked": FP32_PEAK_TFLOPS / 2,
+                     "frac_nonpacked": achieved / (FP32_PEAK_TFLOPS / 2),
                      "kernel": "walk_k<2>", "flops_per_interaction": {"mono": FLOP_MONO,
                                                                        "quad": FLOP_QUAD}},
     }
     if shd is not None:
         inter_s = shd["info"]["interactions_total"]
         out["shared"] = {"s_per_step": shd["seconds"] / args.steps,
+                         "tree_builds": shd["info"]["tree_builds"],
                          "interactions_per_s": inter_s / shd["seconds"],
                          "walk_ms_per_step": shd["walk_ms"] / max(shd["walk_launches"], 1)}
         out["speedup_block_vs_shared"] = shd["seconds"] / blk["seconds"]

@@ -173,6 +173,9 @@ radius_k(Ctl *__restrict__ ctl, int64_t n, const float4 *__restrict__ pos,
       const unsigned key = part ? node : kNone;
       const unsigned ns = part ? node : 0u;
       const float4 r = nrec[2 * (size_t)ns];
+      // a parent is one level up (breadth-first levels): only the parent
+      // index is needed for the next level, loaded together with the record
+      const unsigned up0 = parent[ns];
       const float dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z;
       float dist = (part && r.w > 0.f) ? sqrtf(dx * dx + dy * dy + dz * dz) : 0.f;
       // segmented max over contiguous runs of equal key: the first lane of
@@ -220,11 +223,9 @@ radius_k(Ctl *__restrict__ ctl, int64_t n, const float4 *__restrict__ pos,
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
       }
-      const unsigned up0 = parent[ns];
       const unsigned up = up0 < nn ? up0 : kNone;  // the root's parent is kNone
-      const int uplv = (up != kNone) ? (int)level[up != kNone ? up : 0] : -1;
       node = part ? up : node;
-      lv = part ? uplv : lv;
+      lv = part ? (up != kNone ? lv - 1 : -1) : lv;
     }
   }
   // carried runs of the last tile

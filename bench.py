@@ -47,6 +47,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def walk_traffic():
+    """HBM bytes per timed walk launch from the committed counter summary, while
+    the walk source is the one the counters were taken on (else None)."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "walk_nfw16m_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_1610_07279_amd", "csrc", "walk.hip")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
+                      if line.startswith(("traffic_bytes_per_launch: ", "walk_source_sha256: ")))
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields["walk_source_sha256"]:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, shared, steps, warmup):
     import torch
     pos = pos0.clone()
@@ -220,6 +236,9 @@ def main():
                     help="replay each timed sub-step as captured HIP graphs (default 1)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-system batched / captured sub-step comparison")
+    ap.add_argument("--forces-only", type=int, default=0, metavar="K",
+                    help="only K all-active force evaluations of the workload (one checked, "
+                         "K-1 unchecked; for counter runs) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profile to bytes) and exit")
@@ -249,6 +268,22 @@ def main():
     log(f"bench: generating NFW N={n} (seed 501)")
     x, v = ics.nfw(n, seed=501, with_vel=True)
     dev = torch.device("cuda", 0)
+    if args.forces_only:
+        ctx = g.Context(device=0, multipole=multipole, group_size=args.group_size,
+                        list_depth=args.list_depth, r_crit=args.r_crit, timing=1)
+        xd = torch.from_numpy(x).to(dev)
+        out = ctx.tree_forces(xd, eps, theta)
+        st = ctx.stats()
+        ctx.set_params(check=0)
+        for _ in range(args.forces_only - 1):
+            ctx.tree_forces(xd, eps, theta, out=out)
+        torch.cuda.synchronize()
+        ms, k = ctx.walk_time()
+        flags = ctx.stats()["flags"]
+        print(json.dumps({"forces_only": args.forces_only, "n": n, "interactions": st["interactions"],
+                          "node_interactions": st["node_interactions"],
+                          "walk_ms_mean": ms / max(k, 1), "flags": flags}), flush=True)
+        return
     pos0 = torch.from_numpy(x[:, :3].astype(np.float64)).to(dev)
     vel0 = torch.from_numpy(v).to(dev)
     mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).to(dev)
@@ -299,7 +334,8 @@ def main():
                   "tree_builds": ib["tree_builds"],
                   "walk_ms_per_step": blk["walk_ms"] / max(blk["walk_launches"], 1)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": walk_traffic(),
                      "peak_nonpacked": FP32_PEAK_TFLOPS / 2,
                      "frac_nonpacked": achieved / (FP32_PEAK_TFLOPS / 2),
                      "kernel": "walk_k<2>", "flops_per_interaction": {"mono": FLOP_MONO,

@@ -113,6 +113,20 @@ typedef struct {
                          particles (same order) on the same systems between
                          rebuilds; a change of n or of the systems always
                          rebuilds */
+  int mac;            /* multipole acceptance criterion (Section 2.2):
+                         0 = opening angle b_J <= theta d (default);
+                         1 = acceleration MAC: d^4 >= m_J b_J^2 / (mac_delta
+                             |a_old|), |a_old| the smallest previous
+                             acceleration in the group (needs
+                             gothic_tree_forces_ex or the block-step driver);
+                         2 = multipole MAC of Warren & Salmon: d >= b_J/2 +
+                             sqrt(b_J^2/4 + sqrt(3 B2 / mac_delta)), B2 = sum
+                             m |r - r_J|^2.
+                         With 1 and 2 theta is not used, and a node of positive
+                         size is never accepted when b_J >= d (it may hold a
+                         member of the group) */
+  float mac_delta;    /* accuracy of mac 1 (dimensionless) and mac 2 (an
+                         acceleration); > 0 (default 2^-7) */
   int64_t node_capacity; /* initial size of the node arrays in nodes; 0 = from
                          n and n_leaf (about n + 8 n / n_leaf).  Trees that do
                          not fit are abandoned on the device, the arrays grow
@@ -191,6 +205,18 @@ int gothic_tree_forces_batched(gothic_ctx *c, int nsys, const int64_t *offsets,
                                const float *xyzm, const float *eps, const float *theta,
                                const uint8_t *active, float *acc_pot, void *stream);
 
+/*
+ * The general evaluation: nsys systems as in gothic_tree_forces_batched, plus
+ *   acc_old  [n][4] float DEVICE (ax, ay, az, unused) previous accelerations
+ *            in the caller's order, read by the acceleration MAC (mac = 1;
+ *            may be NULL otherwise), e.g. the acc_pot of the last step
+ * Same rules as gothic_tree_forces_batched; EINVAL when mac = 1 and acc_old
+ * is NULL.  acc_old may not overlap acc_pot.
+ */
+int gothic_tree_forces_ex(gothic_ctx *c, int nsys, const int64_t *offsets, const float *xyzm,
+                          const float *eps, const float *theta, const uint8_t *active,
+                          const float *acc_old, float *acc_pot, void *stream);
+
 /* Result of gothic_autotune. */
 typedef struct {
   int group_size;         /* chosen G */
@@ -213,7 +239,8 @@ typedef struct {
  * later call in the same bucket costs one evaluation.  Arguments as in
  * gothic_tree_forces_batched (nsys = 1 for one system); acc_pot receives the
  * forces of a final checked evaluation with the chosen tunables.
- * Synchronises.  Returns as gothic_tree_forces, and EINVAL for a NULL out.
+ * Synchronises.  Returns as gothic_tree_forces, and EINVAL for a NULL out or
+ * with the acceleration MAC (mac = 1), which needs previous accelerations.
  */
 int gothic_autotune(gothic_ctx *c, int nsys, const int64_t *offsets, const float *xyzm,
                     const float *eps, const float *theta, const uint8_t *active,
@@ -238,7 +265,10 @@ int gothic_get_walk_time(gothic_ctx *c, double *ms_total, int64_t *launches);
  *   mass       [n] float DEVICE array (masses >= 0)
  *   shared_step  1: every particle on the finest level every sub-step (the
  *              scheme is then the leap-frog of the paper's shared-step runs)
- * gothic_sim_bind computes the t = 0 forces and levels and synchronises.
+ * gothic_sim_bind computes the t = 0 forces and levels and synchronises
+ * (with the acceleration MAC, whose a_old does not exist yet at t = 0, the
+ * t = 0 forces use the opening angle theta; every sub-step then uses each
+ * particle's last acceleration).
  * gothic_sim_step advances one finest sub-step and is asynchronous (check
  * mode synchronises inside the force evaluation).  The arrays must stay
  * valid until the next bind or gothic_destroy.

@@ -51,7 +51,7 @@ def _load():
     lib.orc_groups.restype = i64
     lib.orc_groups.argtypes = [i64, P, P, i32, f64, P, P, P, P]
     lib.orc_walk.argtypes = [i64, P, P, P, P, P, P, P, P, P, i64, P, P, P,
-                             f64, f64, i32, f64, f64, P, i64, P, P, P]
+                             f64, f64, i32, f64, f64, P, i64, P, P, P, i32, f64, P]
     _lib = lib
     return lib
 
@@ -148,8 +148,12 @@ def groups(act_sorted: np.ndarray, ps: np.ndarray, G: int, r_crit: float = 0.0):
 
 
 def walk(tree, mom, ps, grp, eps, theta, multipole=1, tie_rel=1e-5, tie_abs=0.0,
-         gsel=None):
+         gsel=None, mac=0, delta=0.0, amag=None):
+    """mac 0: opening angle theta; 1: acceleration MAC with accuracy delta and
+    amag = |a_old| of every particle in key order; 2: Warren-Salmon with delta."""
     com, b, S = mom
+    if mac == 1:
+        amag = np.ascontiguousarray(amag, dtype=np.float64)
     n = ps.shape[0]
     ng = grp["first"].size
     out = np.full((n, 4), np.nan, np.float64)
@@ -163,15 +167,19 @@ def walk(tree, mom, ps, grp, eps, theta, multipole=1, tie_rel=1e-5, tie_abs=0.0,
                      _p(grp["ball"]), float(eps), float(theta), int(multipole),
                      float(tie_rel), float(tie_abs),
                      _p(gsel) if gsel is not None else None,
-                     0 if gsel is None else gsel.size, _p(out), _p(cnt), _p(mass))
+                     0 if gsel is None else gsel.size, _p(out), _p(cnt), _p(mass),
+                     int(mac), float(delta), _p(amag) if mac == 1 else None)
     return out, cnt[:ng], mass[:ng]
 
 
 def tree_forces(xyzm, eps, theta, active=None, n_leaf=16, group_size=32, multipole=1,
-                key_kind=0, tie_rel=1e-5, tie_abs=0.0, gsel=None, r_crit=-0.0625):
+                key_kind=0, tie_rel=1e-5, tie_abs=0.0, gsel=None, r_crit=-0.0625, mac=0,
+                delta=0.0, acc_old=None):
     """All steps of the method in float64; acc_pot is [n,4] in the caller's
     order (NaN rows for inactive particles).  r_crit < 0 is a fraction of the
-    key-cube side (the library's convention); 0 disables the gap split."""
+    key-cube side (the library's convention); 0 disables the gap split.
+    mac / delta: the acceptance criterion (see walk); acc_old [n,>=3] in the
+    caller's order for the acceleration MAC."""
     xyzm = np.ascontiguousarray(xyzm, dtype=np.float32)
     n = xyzm.shape[0]
     k, cb = keys(xyzm, key_kind)
@@ -184,8 +192,12 @@ def tree_forces(xyzm, eps, theta, active=None, n_leaf=16, group_size=32, multipo
     if rc < 0:
         rc = -rc * float(cb[3])
     grp = groups(act[perm], ps, group_size, rc)
+    amag = None
+    if mac == 1:
+        a3 = np.asarray(acc_old, np.float64)[:, :3]
+        amag = np.sqrt((a3 * a3).sum(1))[perm]
     out_sorted, cnt, mass = walk(tree, mom, ps, grp, eps, theta, multipole, tie_rel, tie_abs,
-                                 gsel)
+                                 gsel, mac=mac, delta=delta, amag=amag)
     acc = np.full((n, 4), np.nan, np.float64)
     acc[perm] = out_sorted
     return dict(keys=k, cube=cb, keys_sorted=ks, perm=perm, tree=tree, com=mom[0], b=mom[1],

@@ -17,8 +17,10 @@
  *                   enclosing radius) + a quadrupole extension (second moments)
  *   groups          Section 2.3 (pseudo i-particles, geometric-centre ball of
  *                   Appendix B)
- *   walk            Sections 2.2-2.3 (opening-angle MAC, Eq. of Barnes & Hut,
- *                   with the lambda-distance of the pseudo i-particle)
+ *   walk            Sections 2.2-2.3 (opening-angle MAC of Barnes & Hut, or the
+ *                   acceleration MAC of Springel, or the multipole MAC of
+ *                   Warren & Salmon, with the lambda-distance of the pseudo
+ *                   i-particle)
  *   direct          Section 1, the softened direct sum
  *   time levels and RK2 / leap-frog integration, Section 2.7
  * Readings where the paper is silent are stated at each function.
@@ -404,6 +406,26 @@ static void pair_quad(const double yi[3], const double rj[3], const double S[6],
  * mass[g] = summed mass of the list (mass closure).
  * gsel: optional subset of groups to evaluate (ngsel entries), NULL = all.
  * out: [n][4] in sorted order; rows of evaluated active particles written.   */
+/* Multipole acceptance criteria of Section 2.2 for node J seen from a group
+ * at lambda-distance d:
+ *   mac 0  opening angle (Barnes & Hut):      b_J <= theta d
+ *   mac 1  acceleration (Springel):           d >= (m_J b_J^2 / (Delta |a_old|))^(1/4)
+ *          with |a_old| the smallest previous acceleration in the group
+ *   mac 2  multipole (Warren & Salmon):       d >= b_J/2 + sqrt(b_J^2/4 + sqrt(3 B2 / Delta)),
+ *          B2 = sum m |r - r_J|^2 (the trace of the second moments)
+ * Reading: with mac 1 and 2 a node of positive size is also never accepted
+ * when b_J >= d, i.e. when it may hold a member of the group (a node holding
+ * group member i has d <= b_J, with equality when i is its farthest member);
+ * so the self pair of every i-particle stays an explicit particle term.
+ * Point nodes (b_J = 0) are exact and always pass this guard. */
+static int mac_accept(int mac, double d, double bJ, double mJ, double B2, double theta,
+                      double delta, double amin) {
+  if (mac == 0) return bJ <= theta * d;
+  if (bJ > 0.0 && bJ >= d) return 0;
+  if (mac == 1) return mJ * bJ * bJ <= delta * amin * (d * d) * (d * d);
+  return d >= 0.5 * bJ + sqrt(0.25 * bJ * bJ + sqrt(3.0 * B2 / delta));
+}
+
 void orc_walk(int64_t nn, const uint32_t *first, const uint32_t *count,
               const uint32_t *child_first, const uint8_t *n_child,
               const double *com, const double *b, const double *S,
@@ -411,7 +433,7 @@ void orc_walk(int64_t nn, const uint32_t *first, const uint32_t *count,
               const uint32_t *gfirst, const uint32_t *gcount, const double *ball,
               double eps, double theta, int multipole, double tie_rel, double tie_abs,
               const int64_t *gsel, int64_t ngsel, double *out, int64_t *cnt,
-              double *mass) {
+              double *mass, int mac, double delta, const double *amag) {
   const double e2 = eps * eps;
   const int64_t nsel = gsel ? ngsel : ng;
 #pragma omp parallel
@@ -425,6 +447,10 @@ void orc_walk(int64_t nn, const uint32_t *first, const uint32_t *count,
       const int64_t g = gsel ? gsel[t] : t;
       const double rI[3] = {ball[4 * g], ball[4 * g + 1], ball[4 * g + 2]};
       const double bI = ball[4 * g + 3];
+      double amin = INFINITY;
+      if (mac == 1)
+        for (uint32_t a = gfirst[g]; a < gfirst[g] + gcount[g]; ++a)
+          if (amag[alist[a]] < amin) amin = amag[alist[a]];
       int64_t nl = 0, np = 0, ties = 0, qh = 0, qt = 0;
       if (nn > 0) q[qt++] = 0;
       while (qh < qt) {
@@ -438,8 +464,19 @@ void orc_walk(int64_t nn, const uint32_t *first, const uint32_t *count,
         const double big = b[J] > td ? b[J] : td;
         const double scale = fabs(com[4 * J]) + fabs(com[4 * J + 1]) + fabs(com[4 * J + 2]) +
                              fabs(rI[0]) + fabs(rI[1]) + fabs(rI[2]) + bI;
-        if (b[J] > 0 && fabs(b[J] - td) <= tie_rel * big + tie_abs * scale) ++ties;
-        if (b[J] <= td) {
+        const double B2 = S[6 * J] + S[6 * J + 1] + S[6 * J + 2];
+        const int acc = mac_accept(mac, d, b[J], com[4 * J + 3], B2, theta, delta, amin);
+        if (mac == 0) {
+          if (b[J] > 0 && fabs(b[J] - td) <= tie_rel * big + tie_abs * scale) ++ties;
+        } else {
+          /* a near tie: the decision changes within single-precision rounding of d */
+          const double dlo = d * (1.0 - tie_rel) - tie_abs * scale;
+          const double dhi = d * (1.0 + tie_rel) + tie_abs * scale;
+          if (mac_accept(mac, dlo > 0 ? dlo : 0, b[J], com[4 * J + 3], B2, theta, delta, amin) !=
+              mac_accept(mac, dhi, b[J], com[4 * J + 3], B2, theta, delta, amin))
+            ++ties;
+        }
+        if (acc) {
           lst[nl++] = J;
         } else if (n_child[J] == 0) {
           if ((size_t)(np + count[J]) > cap_p) {

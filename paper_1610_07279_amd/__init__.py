@@ -34,7 +34,7 @@ class Params(C.Structure):
                 ("group_size", C.c_int), ("list_depth", C.c_int), ("compensated", C.c_int),
                 ("check", C.c_int), ("timing", C.c_int), ("r_crit", C.c_float),
                 ("graph", C.c_int), ("autotune", C.c_int), ("rebuild_interval", C.c_int),
-                ("node_capacity", C.c_int64)]
+                ("mac", C.c_int), ("mac_delta", C.c_float), ("node_capacity", C.c_int64)]
 
 
 class TuneResult(C.Structure):
@@ -84,6 +84,7 @@ def _load():
     lib.gothic_get_params.argtypes = [P, C.POINTER(Params)]
     lib.gothic_tree_forces.argtypes = [P, i64, P, f32, f32, P, P, P]
     lib.gothic_tree_forces_batched.argtypes = [P, i32, P, P, P, P, P, P, P]
+    lib.gothic_tree_forces_ex.argtypes = [P, i32, P, P, P, P, P, P, P, P]
     lib.gothic_get_stats.argtypes = [P, C.POINTER(Stats)]
     lib.gothic_get_keys.argtypes = [P, P, P, P]
     lib.gothic_get_tree.argtypes = [P, P, P, P, P, P]
@@ -100,7 +101,8 @@ def _load():
     lib.gothic_sim_get_info.argtypes = [P, C.POINTER(SimInfo)]
     lib.gothic_sim_get_state.argtypes = [P, P, P, P]
     for name in ("gothic_create", "gothic_destroy", "gothic_set_params", "gothic_get_params",
-                 "gothic_tree_forces", "gothic_tree_forces_batched", "gothic_get_stats",
+                 "gothic_tree_forces", "gothic_tree_forces_batched", "gothic_tree_forces_ex",
+                 "gothic_get_stats",
                  "gothic_get_keys", "gothic_get_tree", "gothic_get_nodes", "gothic_get_groups",
                  "gothic_get_walk_time", "gothic_sim_bind", "gothic_sim_bind_batched",
                  "gothic_sim_step", "gothic_sim_reset_counters", "gothic_sim_get_info",
@@ -131,6 +133,16 @@ def default_params() -> Params:
     return p
 
 
+_FLOAT_PARAMS = ("r_crit", "mac_delta")
+
+
+def _check_acc_old(acc_old, n):
+    import torch
+    if acc_old is not None and (acc_old.dtype != torch.float32 or tuple(acc_old.shape) != (n, 4)
+                                or not acc_old.is_cuda or not acc_old.is_contiguous()):
+        raise ValueError("acc_old must be a contiguous float32 [n,4] GPU tensor")
+
+
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
@@ -150,7 +162,7 @@ class Context:
         for k, v in params.items():
             if not hasattr(p, k):
                 raise TypeError(f"unknown parameter {k}")
-            setattr(p, k, float(v) if k == "r_crit" else int(v))
+            setattr(p, k, float(v) if k in _FLOAT_PARAMS else int(v))
         h = C.c_void_p()
         _check(lib.gothic_create(C.byref(h), int(device), C.byref(p)))
         self._h = h
@@ -181,12 +193,14 @@ class Context:
         for k, v in params.items():
             if not hasattr(p, k):
                 raise TypeError(f"unknown parameter {k}")
-            setattr(p, k, float(v) if k == "r_crit" else int(v))
+            setattr(p, k, float(v) if k in _FLOAT_PARAMS else int(v))
         _check(lib.gothic_set_params(self._h, C.byref(p)))
 
     # ---------------------------------------------------------------- forces
-    def tree_forces(self, xyzm, eps: float, theta: float, active=None, out=None, stream=None):
-        """acc_pot [n,4] float32 (ax, ay, az, phi) for the active rows of xyzm."""
+    def tree_forces(self, xyzm, eps: float, theta: float, active=None, out=None, stream=None,
+                    acc_old=None):
+        """acc_pot [n,4] float32 (ax, ay, az, phi) for the active rows of xyzm;
+        acc_old [n,4] (previous accelerations) feeds the acceleration MAC."""
         import torch
         if xyzm.dtype != torch.float32 or xyzm.dim() != 2 or xyzm.shape[1] != 4:
             raise ValueError("xyzm must be a float32 [n,4] tensor")
@@ -203,8 +217,12 @@ class Context:
             raise ValueError("out must be a contiguous float32 [n,4] tensor")
         s = _stream_of(xyzm, stream)
         self._last_stream = s
-        _check(lib.gothic_tree_forces(self._h, n, _ptr(xyzm), float(eps), float(theta),
-                                      _ptr(active), _ptr(out), s))
+        if acc_old is None:
+            _check(lib.gothic_tree_forces(self._h, n, _ptr(xyzm), float(eps), float(theta),
+                                          _ptr(active), _ptr(out), s))
+        else:
+            return self.tree_forces_batched(xyzm, [0, n], eps, theta, active=active, out=out,
+                                            stream=stream, acc_old=acc_old)
         return out
 
     @staticmethod
@@ -218,7 +236,8 @@ class Context:
         t = np.ascontiguousarray(np.broadcast_to(np.asarray(theta, np.float32), (nsys,)))
         return offs, nsys, e, t
 
-    def tree_forces_batched(self, xyzm, offsets, eps, theta, active=None, out=None, stream=None):
+    def tree_forces_batched(self, xyzm, offsets, eps, theta, active=None, out=None, stream=None,
+                            acc_old=None):
         """Forces of nsys independent systems in one evaluation: system s owns rows
         offsets[s]:offsets[s+1] of xyzm (eps, theta: scalars or one per system)."""
         import torch
@@ -238,12 +257,13 @@ class Context:
             out = torch.zeros((n, 4), dtype=torch.float32, device=xyzm.device)
         elif out.dtype != torch.float32 or out.shape != (n, 4) or not out.is_contiguous():
             raise ValueError("out must be a contiguous float32 [n,4] tensor")
+        _check_acc_old(acc_old, n)
         s = _stream_of(xyzm, stream)
         self._last_stream = s
-        _check(lib.gothic_tree_forces_batched(
+        _check(lib.gothic_tree_forces_ex(
             self._h, nsys, offs.ctypes.data_as(C.c_void_p), _ptr(xyzm),
-            e.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p), _ptr(active), _ptr(out),
-            s))
+            e.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p), _ptr(active),
+            _ptr(acc_old), _ptr(out), s))
         return out
 
     def autotune(self, xyzm, eps, theta, active=None, offsets=None, out=None, stream=None):

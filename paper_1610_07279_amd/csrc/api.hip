@@ -130,7 +130,7 @@ static void free_all(gothic_ctx *c) {
                   B.gA, B.gB, B.gfirst,
                   B.first, B.count, B.child_first, B.parent, B.n_child, B.level, B.nch, B.bnd,
                   B.nrec, B.quad, B.ball, B.gent, B.hist, B.part, B.bbox_part, B.spill, B.sys,
-                  B.soff, B.rcrit, B.ctl};
+                  B.soff, B.rcrit, B.mcrit, B.amag, B.gamin, B.ctl};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (B.ctl_host) (void)hipHostFree(B.ctl_host);
@@ -162,6 +162,9 @@ static int validate_params(const gothic_params *p) {
     return set_error(GOTHIC_EINVAL, "autotune must be 0 or 1");
   if (p->rebuild_interval < 0 || p->rebuild_interval > (1 << 20))
     return set_error(GOTHIC_EINVAL, "rebuild_interval must be in 0..2^20");
+  if (p->mac < 0 || p->mac > 2) return set_error(GOTHIC_EINVAL, "mac must be 0, 1 or 2");
+  if (!(p->mac_delta > 0.f) || !std::isfinite(p->mac_delta))
+    return set_error(GOTHIC_EINVAL, "mac_delta must be finite and > 0");
   return GOTHIC_OK;
 }
 
@@ -199,7 +202,8 @@ static int ensure(gothic_ctx *c, int64_t n, int nsys, int64_t want_nodes, int64_
         (rc = dev_alloc(&B.gA, cn + 1)) || (rc = dev_alloc(&B.gB, cn + 1)) ||
         (rc = dev_alloc(&B.gfirst, cn + 1)) ||
         (rc = dev_alloc(&B.bnd, 8 * cn + 8)) || (rc = dev_alloc(&B.ball, cn)) ||
-        (rc = dev_alloc(&B.gent, 2 * cn)))
+        (rc = dev_alloc(&B.gent, 2 * cn)) || (rc = dev_alloc(&B.amag, cn)) ||
+        (rc = dev_alloc(&B.gamin, cn)))
       return rc;
     const int64_t hist = 2 * radix_hist_entries(cn);
     if ((rc = dev_alloc(&B.hist, hist))) return rc;
@@ -214,7 +218,8 @@ static int ensure(gothic_ctx *c, int64_t n, int nsys, int64_t want_nodes, int64_
     if ((rc = dev_alloc(&B.first, nodes)) || (rc = dev_alloc(&B.count, nodes)) ||
         (rc = dev_alloc(&B.child_first, nodes)) || (rc = dev_alloc(&B.parent, nodes)) ||
         (rc = dev_alloc(&B.n_child, nodes)) || (rc = dev_alloc(&B.level, nodes)) ||
-        (rc = dev_alloc(&B.nrec, 2 * nodes)) || (rc = dev_alloc(&B.quad, 2 * nodes)))
+        (rc = dev_alloc(&B.nrec, 2 * nodes)) || (rc = dev_alloc(&B.quad, 2 * nodes)) ||
+        (rc = dev_alloc(&B.mcrit, nodes)))
       return rc;
     c->cap_nodes = nodes;
     ++c->generation;
@@ -286,8 +291,8 @@ static void enqueue_make(gothic_ctx *c, const Systems &sy, const float4 *xyzm, h
 }
 
 static void enqueue_post(gothic_ctx *c, const Systems &sy, const float4 *xyzm,
-                         const uint8_t *active, hipStream_t s) {
-  launch_permute(c, xyzm, active, sy.n, s);
+                         const uint8_t *active, const float4 *acc_old, hipStream_t s) {
+  launch_permute(c, xyzm, active, c->prm.mac == 1 ? acc_old : nullptr, sy.n, s);
   launch_moments(c, sy.n, sy.nsys, s);
   launch_groups(c, sy.n, s);
 }
@@ -306,8 +311,8 @@ static void enqueue_walk(gothic_ctx *c, int64_t n, float4 *out, hipStream_t s, b
 // with the current positions.  The construction is timed when the rebuild
 // models are being fed.
 static int enqueue_forces(gothic_ctx *c, const Systems &sy, const float4 *xyzm,
-                          const uint8_t *active, float4 *out, hipStream_t s, float r_crit,
-                          bool rebuild) {
+                          const uint8_t *active, const float4 *acc_old, float4 *out,
+                          hipStream_t s, float r_crit, bool rebuild) {
   enqueue_begin(c, !rebuild, r_crit, s);
   enqueue_upload(c, sy, s);
   if (rebuild) {
@@ -316,7 +321,7 @@ static int enqueue_forces(gothic_ctx *c, const Systems &sy, const float4 *xyzm,
     enqueue_make(c, sy, xyzm, s);
     if (tm) (void)hipEventRecord(c->tree.mk1, s);
   }
-  enqueue_post(c, sy, xyzm, active, s);
+  enqueue_post(c, sy, xyzm, active, acc_old, s);
   enqueue_walk(c, sy.n, out, s, true);
   return hip_check(hipGetLastError(), "kernel launch");
 }
@@ -517,9 +522,12 @@ static void meter_mark(gothic_ctx *c, int k, bool rebuilt, bool tuned) {
 }
 
 static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const uint8_t *active,
-                      float4 *o4, hipStream_t s, float r_crit, int meter_class = 0,
-                      bool tuned = false, int kmax = 0) {
+                      const float4 *acc_old, float4 *o4, hipStream_t s, float r_crit,
+                      int meter_class = 0, bool tuned = false, int kmax = 0) {
   const int64_t n = sy.n;
+  if (c->prm.mac == 1 && !acc_old)
+    return set_error(GOTHIC_EINVAL,
+                     "the acceleration MAC needs the previous accelerations (gothic_tree_forces_ex)");
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(s, &cap);
   const bool capturing = cap != hipStreamCaptureStatusNone;
@@ -543,7 +551,7 @@ static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const 
   constexpr int kAttempts = 6;
   for (int attempt = 0; attempt < kAttempts; ++attempt) {
     c->tune.recording = meter;
-    rc = enqueue_forces(c, sy, x4, active, o4, s, r_crit, rebuild);
+    rc = enqueue_forces(c, sy, x4, active, acc_old, o4, s, r_crit, rebuild);
     c->tune.recording = false;
     if (rc) return rc;
     tree_used(c, sy, rebuild);
@@ -603,6 +611,8 @@ void gothic_default_params(gothic_params *p) {
   p->graph = 0;
   p->autotune = 0;
   p->rebuild_interval = 1;
+  p->mac = 0;
+  p->mac_delta = 0.0078125f;  // 2^-7
   p->node_capacity = 0;
 }
 
@@ -660,8 +670,8 @@ int gothic_set_params(gothic_ctx *c, const gothic_params *p) {
   const gothic_params &a = c->prm, &b = *p;
   if (a.key_kind != b.key_kind || a.n_leaf != b.n_leaf || a.multipole != b.multipole ||
       a.group_size != b.group_size || a.list_depth != b.list_depth ||
-      a.compensated != b.compensated || a.graph != b.graph ||
-      a.node_capacity != b.node_capacity)
+      a.compensated != b.compensated || a.graph != b.graph || a.mac != b.mac ||
+      a.mac_delta != b.mac_delta || a.node_capacity != b.node_capacity)
     ++c->generation;
   c->prm = *p;
   return GOTHIC_OK;
@@ -688,7 +698,7 @@ int gothic_tree_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, f
   Systems sy;
   int rc = make_systems(1, off, &eps, &theta, false, &sy);
   if (rc) return rc;
-  return run_forces(c, sy, reinterpret_cast<const float4 *>(xyzm), active,
+  return run_forces(c, sy, reinterpret_cast<const float4 *>(xyzm), active, nullptr,
                     reinterpret_cast<float4 *>(acc_pot), reinterpret_cast<hipStream_t>(stream),
                     c->prm.r_crit);
 }
@@ -705,9 +715,26 @@ int gothic_tree_forces_batched(gothic_ctx *c, int nsys, const int64_t *offsets, 
   if ((const void *)xyzm == (const void *)acc_pot)
     return set_error(GOTHIC_EINVAL, "xyzm and acc_pot must not overlap");
   DeviceGuard guard(c->device);
-  return run_forces(c, sy, reinterpret_cast<const float4 *>(xyzm), active,
+  return run_forces(c, sy, reinterpret_cast<const float4 *>(xyzm), active, nullptr,
                     reinterpret_cast<float4 *>(acc_pot), reinterpret_cast<hipStream_t>(stream),
                     c->prm.r_crit);
+}
+
+int gothic_tree_forces_ex(gothic_ctx *c, int nsys, const int64_t *offsets, const float *xyzm,
+                          const float *eps, const float *theta, const uint8_t *active,
+                          const float *acc_old, float *acc_pot, void *stream) {
+  if (!c) return set_error(GOTHIC_EINVAL, "context is NULL");
+  Systems sy;
+  int rc = make_systems(nsys, offsets, eps, theta, true, &sy);
+  if (rc) return rc;
+  if (sy.n == 0) return GOTHIC_OK;
+  if (!xyzm || !acc_pot) return set_error(GOTHIC_EINVAL, "xyzm and acc_pot must not be NULL");
+  if ((const void *)xyzm == (const void *)acc_pot || (const void *)acc_old == (const void *)acc_pot)
+    return set_error(GOTHIC_EINVAL, "acc_pot must not overlap xyzm or acc_old");
+  DeviceGuard guard(c->device);
+  return run_forces(c, sy, reinterpret_cast<const float4 *>(xyzm), active,
+                    reinterpret_cast<const float4 *>(acc_old), reinterpret_cast<float4 *>(acc_pot),
+                    reinterpret_cast<hipStream_t>(stream), c->prm.r_crit);
 }
 
 int gothic_get_stats(gothic_ctx *c, gothic_stats *out) {
@@ -910,11 +937,13 @@ static int sim_bind_impl(gothic_ctx *c, const Systems &sy, double *pos, double *
   sim_launch_reset(c, s);
   sim_launch_shadow(c, s);
   if ((rc = hip_check(hipGetLastError(), "kernel launch"))) return rc;
-  // t = 0 forces on every particle (synchronous, checked)
-  const int saved = c->prm.check;
+  // t = 0 forces on every particle (synchronous, checked; the acceleration
+  // MAC has no a_old yet and uses the opening angle here)
+  const gothic_params saved = c->prm;
   c->prm.check = 1;
-  rc = run_forces(c, sy, S.shadow, nullptr, S.anew, s, c->prm.r_crit);
-  c->prm.check = saved;
+  if (c->prm.mac == 1) c->prm.mac = 0;
+  rc = run_forces(c, sy, S.shadow, nullptr, nullptr, S.anew, s, c->prm.r_crit);
+  c->prm = saved;
   if (rc) return rc;
   sim_launch_init(c, s);
   sim_launch_reset(c, s);
@@ -987,7 +1016,7 @@ static int capture_step(gothic_ctx *c) {
         enqueue_upload(c, sy, G.cap_stream);
         break;
       case 1: enqueue_make(c, sy, S.shadow, G.cap_stream); break;
-      case 2: enqueue_post(c, sy, S.shadow, S.act, G.cap_stream); break;
+      case 2: enqueue_post(c, sy, S.shadow, S.act, S.aold, G.cap_stream); break;
       case 3: enqueue_walk(c, sy.n, S.anew, G.cap_stream, false); break;
       default: sim_launch_correct(c, G.cap_stream); break;
     }
@@ -1062,7 +1091,7 @@ int gothic_sim_step(gothic_ctx *c, void *stream) {
     if (meter) meter_mark(c, cls, rebuild, c->prm.autotune != 0);
   } else {
     sim_launch_predict(c, s);
-    rc = run_forces(c, sim_systems(S), S.shadow, S.act, S.anew, s, r_crit, cls,
+    rc = run_forces(c, sim_systems(S), S.shadow, S.act, S.aold, S.anew, s, r_crit, cls,
                     c->prm.autotune != 0, S.kmax);
     if (rc) return rc;
     if (c->tree.since == 1) ++S.builds;
@@ -1096,7 +1125,7 @@ static int timed_eval(gothic_ctx *c, const Systems &sy, const float4 *x4, const 
   if ((rc = ensure(c, sy.n, sy.nsys, nodes_wanted(c, sy.n, sy.nsys), c->spill_per_wave)))
     return rc;
   (void)hipEventRecord(T.ev0, s);
-  if ((rc = enqueue_forces(c, sy, x4, act, o4, s, r_crit, true))) return rc;
+  if ((rc = enqueue_forces(c, sy, x4, act, nullptr, o4, s, r_crit, true))) return rc;
   (void)hipEventRecord(T.ev1, s);
   tree_used(c, sy, true);
   if ((rc = hip_check(hipMemcpyAsync(c->b.ctl_host, c->b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
@@ -1120,7 +1149,7 @@ static int autotune_impl(gothic_ctx *c, const Systems &sy, const float4 *x4, con
   // scratch and counts the active particles
   c->prm.autotune = 0;
   c->prm.rebuild_interval = 1;
-  rc = run_forces(c, sy, x4, act, o4, s, saved.r_crit);
+  rc = run_forces(c, sy, x4, act, nullptr, o4, s, saved.r_crit);
   c->prm = saved;
   if (rc) return rc;
   const int64_t na = c->b.ctl_host->n_active;
@@ -1205,7 +1234,7 @@ static int autotune_impl(gothic_ctx *c, const Systems &sy, const float4 *x4, con
   c->prm.check = 1;
   c->prm.autotune = 0;
   c->prm.rebuild_interval = 1;
-  rc = run_forces(c, sy, x4, act, o4, s, c->prm.r_crit);
+  rc = run_forces(c, sy, x4, act, nullptr, o4, s, c->prm.r_crit);
   c->prm.check = chosen.check;
   c->prm.autotune = chosen.autotune;
   c->prm.rebuild_interval = chosen.rebuild_interval;

@@ -83,6 +83,9 @@ struct Buffers {
   uint32_t *bnd = nullptr;        // per level-node child boundaries, 8 each (8 n)
   float4 *nrec = nullptr;         // walk record, 2 per node: (x,y,z,M), (b_J, a, b, leaf)
   float4 *quad = nullptr;         // 2 per node: (xx,yy,zz,xy), (xz,yz,tr,0)
+  float *mcrit = nullptr;         // per node: critical distance of the multipole MAC
+  float *amag = nullptr;          // |a_old| of each key-ordered particle (acceleration MAC)
+  float *gamin = nullptr;         // smallest |a_old| of each group
   // groups (capacity cap_groups)
   float4 *ball = nullptr;
   uint32_t *gent = nullptr;       // 2 per group: node entries, particle entries
@@ -231,8 +234,8 @@ void launch_radix_sort(gothic_ctx *c, int64_t n, int nsys, hipStream_t s);
 bool keys_to_B(int nsys);  // the key kernel writes keyB / idxB (odd pass count)
 int64_t radix_hist_entries(int64_t n);
 // tree.hip
-void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active, int64_t n,
-                    hipStream_t s);
+void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active,
+                    const float4 *acc_old, int64_t n, hipStream_t s);
 void launch_build(gothic_ctx *c, int64_t n, int nsys, hipStream_t s);
 // moments.hip
 void launch_moments(gothic_ctx *c, int64_t n, int nsys, hipStream_t s);

@@ -107,7 +107,8 @@ group_first_k(Ctl *__restrict__ ctl, const uint32_t *__restrict__ gflag,
 __global__ void __launch_bounds__(256)
 group_ball_k(int64_t n, const Ctl *__restrict__ ctl, const uint32_t *__restrict__ alist,
              const uint32_t *__restrict__ gfirst, const float4 *__restrict__ pos,
-             float4 *__restrict__ ball) {
+             float4 *__restrict__ ball, const float *__restrict__ amag,
+             float *__restrict__ gamin) {
   const unsigned ng = ctl->n_groups, na = ctl->n_active;
   const int lane = lane_id();
   const int64_t wid = __builtin_amdgcn_readfirstlane(
@@ -126,6 +127,10 @@ group_ball_k(int64_t n, const Ctl *__restrict__ ctl, const uint32_t *__restrict_
     const float dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
     const float r = wave_max(sqrtf(dx * dx + dy * dy + dz * dz));
     ball[g] = make_float4(cx, cy, cz, r * (1.0f + 4.0f * 1.1920929e-7f));  // same from all lanes
+    if (amag) {  // acceleration MAC: the group's smallest |a_old|
+      const float am = wave_min(amag[ai < n ? ai : 0]);
+      gamin[g] = am;
+    }
   }
 }
 
@@ -149,8 +154,9 @@ void launch_groups(gothic_ctx *c, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(group_first_k, dim3(g), dim3(256), 0, s, B.ctl, B.gB, B.flag, B.gfirst);
   int64_t wb = (n + 3) / 4;
   int gb = (int)(wb > 8192 ? 8192 : (wb < 1 ? 1 : wb));
+  const bool acc_mac = c->prm.mac == 1;
   hipLaunchKernelGGL(group_ball_k, dim3(gb), dim3(256), 0, s, n, B.ctl, B.alist, B.gfirst, B.pos,
-                     B.ball);
+                     B.ball, acc_mac ? B.amag : nullptr, B.gamin);
 }
 
 }  // namespace gothic

@@ -235,9 +235,26 @@ radius_k(Ctl *__restrict__ ctl, int64_t n, const float4 *__restrict__ pos,
   }
 }
 
+// Critical distance of the multipole MAC of Warren & Salmon (Section 2.2) for
+// every node: b_J/2 + sqrt(b_J^2/4 + sqrt(3 B2 / delta)), B2 = trace of the
+// second moments (sum m |r - r_J|^2), once b_J is final.
+__global__ void __launch_bounds__(256)
+mac_crit_k(const Ctl *__restrict__ ctl, float delta, const float4 *__restrict__ nrec,
+           const float4 *__restrict__ quad, float *__restrict__ mcrit) {
+  if (ctl->flags & kFlagNodeOverflow) return;
+  const int64_t nn = ctl->n_nodes;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nn;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const float b = nrec[2 * k + 1].x;
+    const float B2 = quad[2 * k + 1].z;
+    mcrit[k] = 0.5f * b + sqrtf(0.25f * b * b + sqrtf(3.0f * B2 / delta));
+  }
+}
+
 void launch_moments(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
   Buffers &B = c->b;
-  const int wq = c->prm.multipole == 2 ? 1 : 0;
+  // second moments for quadrupole terms and for the B2 of the multipole MAC
+  const int wq = (c->prm.multipole == 2 || c->prm.mac == 2) ? 1 : 0;
   int64_t nb = (c->cap_nodes + 255) / 256;
   int g = (int)(nb > 8192 ? 8192 : (nb < 1 ? 1 : nb));
   hipLaunchKernelGGL(leaf_moments_k, dim3(g), dim3(256), 0, s, B.ctl, n, B.first, B.count,
@@ -256,6 +273,9 @@ void launch_moments(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
   int gp = (int)(pb > 16384 ? 16384 : (pb < 1 ? 1 : pb));
   hipLaunchKernelGGL(radius_k, dim3(gp), dim3(256), 0, s, B.ctl, n, B.pos, B.leaf_of, B.parent,
                      B.level, B.nrec);
+  if (c->prm.mac == 2)
+    hipLaunchKernelGGL(mac_crit_k, dim3(g), dim3(256), 0, s, B.ctl, c->prm.mac_delta, B.nrec,
+                       B.quad, B.mcrit);
 }
 
 }  // namespace gothic

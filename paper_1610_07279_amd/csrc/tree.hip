@@ -20,9 +20,12 @@ namespace gothic {
 constexpr int kBuildThreads = 256;
 constexpr unsigned kNone = 0xffffffffu;
 
+// Key order: positions and masses, active flags and (acceleration MAC) the
+// magnitudes of the previous accelerations.
 __global__ void __launch_bounds__(256)
-permute_k(const float4 *__restrict__ xyzm, const uint8_t *__restrict__ active, int64_t n,
-          const uint32_t *__restrict__ perm, float4 *__restrict__ pos, uint32_t *__restrict__ flag,
+permute_k(const float4 *__restrict__ xyzm, const uint8_t *__restrict__ active,
+          const float4 *__restrict__ acc_old, int64_t n, const uint32_t *__restrict__ perm,
+          float4 *__restrict__ pos, uint32_t *__restrict__ flag, float *__restrict__ amag,
           Ctl *ctl) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * blockDim.x) {
@@ -31,20 +34,26 @@ permute_k(const float4 *__restrict__ xyzm, const uint8_t *__restrict__ active, i
       atomicOr(&ctl->flags, kFlagBadIndex);
       i = 0;
     }
-    pos[k] = xyzm[i];
+    const float4 p = xyzm[i];
+    if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w)))
+      atomicOr(&ctl->flags, kFlagNonFinite);  // (a reused tree skips the key pass)
+    pos[k] = p;
     flag[k] = active ? (active[i] != 0 ? 1u : 0u) : 1u;
+    if (acc_old) {
+      const float4 a = acc_old[i];
+      amag[k] = sqrtf(a.x * a.x + a.y * a.y + a.z * a.z);
+    }
   }
 }
 
-void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active, int64_t n,
-                    hipStream_t s) {
+void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active,
+                    const float4 *acc_old, int64_t n, hipStream_t s) {
   int64_t nb = (n + 255) / 256;
   int g = (int)(nb > 8192 ? 8192 : (nb < 1 ? 1 : nb));
-  hipLaunchKernelGGL(permute_k, dim3(g), dim3(256), 0, s, xyzm, active, n, c->b.idxA, c->b.pos,
-                     c->b.flag, c->b.ctl);
+  hipLaunchKernelGGL(permute_k, dim3(g), dim3(256), 0, s, xyzm, active, acc_old, n, c->b.idxA,
+                     c->b.pos, c->b.flag, c->b.amag, c->b.ctl);
 }
 
-// level 0 holds one root per system: node s covers the system's index range
 __global__ void __launch_bounds__(256)
 build_init_k(Ctl *ctl, int nsys, const uint32_t *__restrict__ soff, uint32_t *first,
              uint32_t *count, uint32_t *parent, uint8_t *level) {

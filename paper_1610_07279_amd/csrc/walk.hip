@@ -8,7 +8,8 @@
 // represented by its pseudo i-particle (r_I, b_I); a candidate pseudo
 // j-particle J is at distance d = lambda r_JI with lambda = 1 - b_I / r_JI
 // (0 when b_I >= r_JI), and is accepted when b_J <= theta d (the opening-angle
-// MAC of Barnes & Hut written without the division).  Up to 64 pending
+// MAC of Barnes & Hut written without the division), or by the acceleration
+// or multipole MAC of Section 2.2 (params.mac).  Up to 64 pending
 // nodes are tested at once, one per lane, and ballot/prefix-sum compaction
 // routes
 //   accepted nodes        -> the LDS interaction list (pseudo particles),
@@ -60,6 +61,10 @@ struct WalkArgs {
   int64_t spill_cap;
   const SysRec *sys;
   const uint32_t *soff;
+  const float *gamin;   // acceleration MAC: smallest |a_old| per group
+  const float *mcrit;   // multipole MAC: critical distance per node
+  float mac_delta;
+  int mac;              // 0 opening angle, 1 acceleration, 2 multipole (Warren-Salmon)
   int G, logG, D, DQ;
   int wave_bytes;
   int compensated;
@@ -208,6 +213,8 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     const unsigned sy = __builtin_amdgcn_readfirstlane(
         sys_of(a.soff, nsys, k_first < a.n ? k_first : 0u));
     const float eps2 = a.sys[sy].eps2, theta = a.sys[sy].theta, inv_eps = a.sys[sy].inv_eps;
+    // acceleration MAC: accept when m b^2 <= (delta |a_old|_min) d^4
+    const float dfac = a.mac == 1 ? a.mac_delta * a.gamin[g] : 0.f;
     Acc acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int np = 0, nq = 0;
     // LDS ring holds stack entries [qb, qt) (ring positions mod kQueueCap);
@@ -245,7 +252,22 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       const float dx = r0.x - bl.x, dy = r0.y - bl.y, dz = r0.z - bl.z;
       const float rji = sqrtf(dx * dx + dy * dy + dz * dz);
       const float dist = fmaxf(rji - bl.w, 0.f);
-      const bool accept = has && qv < nn && (r1.x <= theta * dist);
+      // multipole acceptance (Section 2.2); with the acceleration and
+      // multipole MACs a node of positive size that may hold a member of the
+      // group (b_J >= d) is never accepted
+      bool mac_ok;
+      if (a.mac == 0) {
+        mac_ok = r1.x <= theta * dist;
+      } else {
+        const bool outside = !(r1.x > 0.f && r1.x >= dist);
+        if (a.mac == 1) {
+          const float d2 = dist * dist;
+          mac_ok = outside && (r0.w * r1.x * r1.x <= dfac * (d2 * d2));
+        } else {
+          mac_ok = outside && (a.mcrit[node] <= dist);
+        }
+      }
+      const bool accept = has && qv < nn && mac_ok;
       const bool leaf = __float_as_uint(r1.w) != 0u;
       const bool open_leaf = has && qv < nn && !accept && leaf;
       const bool open_int = has && qv < nn && !accept && !leaf;
@@ -444,6 +466,10 @@ void launch_walk(gothic_ctx *c, int64_t n, float4 *acc_pot, hipStream_t s) {
   a.spill_cap = c->spill_per_wave;
   a.sys = B.sys;
   a.soff = B.soff;
+  a.gamin = B.gamin;
+  a.mcrit = B.mcrit;
+  a.mac_delta = c->prm.mac_delta;
+  a.mac = c->prm.mac;
   a.G = c->prm.group_size;
   int lg = 0;
   while ((1 << lg) < a.G) ++lg;

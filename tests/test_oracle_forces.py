@@ -167,3 +167,60 @@ def test_inactive_rows_untouched_and_active_subset():
     assert np.isnan(a[act == 0]).all() and np.isfinite(a[act == 1]).all()
     d = oracle.direct(xyzm, 1.0 / 64, idx=np.flatnonzero(act))
     assert _rel_rms(a[act == 1], d) < 1e-13
+
+
+# ---------------------------------------------------------------- other MACs (Section 2.2)
+@pytest.mark.parametrize("mac", [1, 2])
+def test_mac_tiny_delta_is_the_direct_sum(mac):
+    x = ics.plummer(2000, seed=41)
+    d = oracle.direct(x, 1 / 64)
+    r = oracle.tree_forces(x, 1 / 64, 0.5, mac=mac, delta=1e-14, acc_old=d)
+    assert np.abs(r["acc_pot"] - d).max() <= 1e-12 * np.abs(d).max()
+
+
+@pytest.mark.parametrize("mac", [1, 2])
+def test_mac_huge_delta_is_the_unit_opening_angle(mac):
+    # with Delta -> infinity only the guard (b_J = 0 or b_J < d) is left: the
+    # opening-angle MAC just below theta = 1, list for list (Warren-Salmon:
+    # b/2 + sqrt(b^2/4) is b only to rounding, so nodes with d within an ulp
+    # of b may differ)
+    x = ics.nfw(3000, seed=42)
+    d = oracle.direct(x, 1 / 128)
+    r = oracle.tree_forces(x, 1 / 128, 0.5, mac=mac, delta=1e30, acc_old=d)
+    r1 = oracle.tree_forces(x, 1 / 128, float(np.nextafter(1.0, 0.0)), mac=0)
+    same = (r["counts"][:, :2] == r1["counts"][:, :2]).all(1)
+    if mac == 1:
+        assert same.all()
+        assert np.array_equal(r["acc_pot"], r1["acc_pot"])
+    else:
+        assert same.mean() >= 0.99
+        a, b = r["acc_pot"], r1["acc_pot"]
+        assert np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()) < 1e-4
+
+
+def test_acceleration_mac_error_scales_with_delta():
+    # each accepted node's monopole error is at most about Delta |a_old| (Springel's
+    # criterion); the median relative error is below Delta and falls with it
+    x = ics.plummer(3000, seed=43)
+    d = oracle.direct(x, 1 / 64)
+    prev = np.inf
+    for delta in (1e-1, 1e-2, 1e-3, 1e-4):
+        a = oracle.tree_forces(x, 1 / 64, 0.5, mac=1, delta=delta, acc_old=d)["acc_pot"]
+        err = np.linalg.norm(a[:, :3] - d[:, :3], axis=1) / np.linalg.norm(d[:, :3], axis=1)
+        assert np.median(err) <= delta
+        assert np.median(err) < prev
+        prev = np.median(err)
+
+
+def test_multipole_mac_error_scales_with_delta():
+    # Warren-Salmon bound each node's truncation error by about Delta (an
+    # absolute acceleration): the median absolute error stays below Delta
+    x = ics.plummer(3000, seed=44)
+    d = oracle.direct(x, 1 / 64)
+    prev = np.inf
+    for delta in (1e-1, 1e-2, 1e-3, 1e-4):
+        a = oracle.tree_forces(x, 1 / 64, 0.5, mac=2, delta=delta)["acc_pot"]
+        err = np.linalg.norm(a[:, :3] - d[:, :3], axis=1)
+        assert np.median(err) <= delta
+        assert np.median(err) < prev
+        prev = np.median(err)

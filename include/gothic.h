@@ -127,6 +127,12 @@ typedef struct {
                          member of the group) */
   float mac_delta;    /* accuracy of mac 1 (dimensionless) and mac 2 (an
                          acceleration); > 0 (default 2^-7) */
+  int ball;           /* enclosing ball of each group's pseudo i-particle
+                         (Appendix B): 0 GEO, centred on the bounding box
+                         (default); 1 SEB, the smallest enclosing ball; 2 EBS,
+                         Ritter's sphere; 3 COM, centred on the centre of mass;
+                         4 CMP, the smaller of GEO and COM.  The radius is the
+                         largest member distance from the centre */
   int64_t node_capacity; /* initial size of the node arrays in nodes; 0 = from
                          n and n_leaf (about n + 8 n / n_leaf).  Trees that do
                          not fit are abandoned on the device, the arrays grow

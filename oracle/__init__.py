@@ -49,7 +49,8 @@ def _load():
     lib.orc_build.argtypes = [i64, P, i32, i64, P, P, P, P, P]
     lib.orc_moments.argtypes = [i64, P, P, P, P, P, P]
     lib.orc_groups.restype = i64
-    lib.orc_groups.argtypes = [i64, P, P, i32, f64, P, P, P, P]
+    lib.orc_groups.argtypes = [i64, P, P, i32, f64, P, P, P, P, i32]
+    lib.orc_seb.argtypes = [i32, P, P]
     lib.orc_walk.argtypes = [i64, P, P, P, P, P, P, P, P, P, i64, P, P, P,
                              f64, f64, i32, f64, f64, P, i64, P, P, P, i32, f64, P]
     _lib = lib
@@ -130,21 +131,34 @@ def moments(tree, ps: np.ndarray):
     return com, b, S
 
 
-def groups(act_sorted: np.ndarray, ps: np.ndarray, G: int, r_crit: float = 0.0):
+BALL_GEO, BALL_SEB, BALL_EBS, BALL_COM, BALL_CMP = 0, 1, 2, 3, 4
+
+
+def groups(act_sorted: np.ndarray, ps: np.ndarray, G: int, r_crit: float = 0.0,
+           ball: int = BALL_GEO):
     """r_crit: critical separation (Section 2.4); pass the float32 value the
-    library uses, e.g. float(np.float32(r)); <= 0 disables the gap split."""
+    library uses, e.g. float(np.float32(r)); <= 0 disables the gap split.
+    ball: the enclosing-ball kind of the pseudo i-particles (Appendix B)."""
     n = act_sorted.size
     act_sorted = np.ascontiguousarray(act_sorted, dtype=np.uint8)
     alist = np.zeros(max(n, 1), np.uint32)
     gmax = max(1, n)
     gfirst = np.zeros(gmax, np.uint32)
     gcount = np.zeros(gmax, np.uint32)
-    ball = np.zeros((gmax, 4), np.float64)
+    balls = np.zeros((gmax, 4), np.float64)
     ng = _load().orc_groups(n, _p(act_sorted), _p(ps), G, float(r_crit), _p(alist), _p(gfirst),
-                            _p(gcount), _p(ball))
+                            _p(gcount), _p(balls), int(ball))
     na = int(act_sorted.sum())
     return dict(alist=alist[:na].copy(), first=gfirst[:ng].copy(), count=gcount[:ng].copy(),
-                ball=ball[:ng].copy())
+                ball=balls[:ng].copy())
+
+
+def seb(pts: np.ndarray):
+    """Smallest enclosing ball of pts [n,3] (Welzl): (centre [3], radius)."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    out = np.zeros(4, np.float64)
+    _load().orc_seb(pts.shape[0], _p(pts), _p(out))
+    return out[:3], float(out[3])
 
 
 def walk(tree, mom, ps, grp, eps, theta, multipole=1, tie_rel=1e-5, tie_abs=0.0,
@@ -174,7 +188,7 @@ def walk(tree, mom, ps, grp, eps, theta, multipole=1, tie_rel=1e-5, tie_abs=0.0,
 
 def tree_forces(xyzm, eps, theta, active=None, n_leaf=16, group_size=32, multipole=1,
                 key_kind=0, tie_rel=1e-5, tie_abs=0.0, gsel=None, r_crit=-0.0625, mac=0,
-                delta=0.0, acc_old=None):
+                delta=0.0, acc_old=None, ball=BALL_GEO):
     """All steps of the method in float64; acc_pot is [n,4] in the caller's
     order (NaN rows for inactive particles).  r_crit < 0 is a fraction of the
     key-cube side (the library's convention); 0 disables the gap split.
@@ -191,7 +205,7 @@ def tree_forces(xyzm, eps, theta, active=None, n_leaf=16, group_size=32, multipo
     rc = float(np.float32(r_crit))
     if rc < 0:
         rc = -rc * float(cb[3])
-    grp = groups(act[perm], ps, group_size, rc)
+    grp = groups(act[perm], ps, group_size, rc, ball)
     amag = None
     if mac == 1:
         a3 = np.asarray(acc_old, np.float64)[:, :3]

@@ -294,20 +294,206 @@ void orc_moments(int64_t nn, const uint32_t *first, const uint32_t *count,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Enclosing balls of a group (pseudo i-particles, Appendix B).  Each kind
+ * picks a centre; the radius is then the largest member distance from it.
+ *   0 GEO  centre of the bounding box
+ *   1 SEB  smallest enclosing ball (unique): Welzl's recursion
+ *   2 EBS  Ritter's bounding sphere: diameter of two far points (the one
+ *          farthest from the first member, and the one farthest from that),
+ *          grown in member order to take in every member outside it
+ *   3 COM  centre of mass
+ *   4 CMP  the smaller of GEO and COM (COM only if its radius is smaller by
+ *          more than a relative 1e-5, so the choice is robust to rounding)  */
+typedef struct { double c[3]; double r2; } OBall;
+
+static double dist2(const double *a, const double *b) {
+  const double x = a[0] - b[0], y = a[1] - b[1], z = a[2] - b[2];
+  return x * x + y * y + z * z;
+}
+
+static int ob_in(const OBall *B, const double *p) {
+  return B->r2 >= 0 && dist2(p, B->c) <= B->r2 * (1.0 + 1e-12);
+}
+
+static OBall ob_two(const double *a, const double *b) {
+  OBall B;
+  for (int k = 0; k < 3; ++k) B.c[k] = 0.5 * (a[k] + b[k]);
+  B.r2 = 0.25 * dist2(a, b);
+  return B;
+}
+
+/* smallest ball with a, b, c on its boundary (the circumcircle in their
+ * plane); for (nearly) collinear points the ball of the farthest pair */
+static OBall ob_three(const double *a, const double *b, const double *c) {
+  double u[3], v[3], w[3];
+  for (int k = 0; k < 3; ++k) { u[k] = b[k] - a[k]; v[k] = c[k] - a[k]; }
+  w[0] = u[1] * v[2] - u[2] * v[1];
+  w[1] = u[2] * v[0] - u[0] * v[2];
+  w[2] = u[0] * v[1] - u[1] * v[0];
+  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const double ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  if (ww <= 1e-24 * uu * vv) {
+    const double dab = dist2(a, b), dac = dist2(a, c), dbc = dist2(b, c);
+    if (dab >= dac && dab >= dbc) return ob_two(a, b);
+    return dac >= dbc ? ob_two(a, c) : ob_two(b, c);
+  }
+  /* centre = a + ((uu v - vv u) x w) / (2 ww) */
+  double t[3];
+  for (int k = 0; k < 3; ++k) t[k] = uu * v[k] - vv * u[k];
+  OBall B;
+  B.c[0] = a[0] + (t[1] * w[2] - t[2] * w[1]) / (2 * ww);
+  B.c[1] = a[1] + (t[2] * w[0] - t[0] * w[2]) / (2 * ww);
+  B.c[2] = a[2] + (t[0] * w[1] - t[1] * w[0]) / (2 * ww);
+  B.r2 = dist2(a, B.c);
+  return B;
+}
+
+/* the sphere through a, b, c, d; for (nearly) coplanar points the smallest
+ * of the balls of three or two of them that holds all four */
+static OBall ob_four(const double *a, const double *b, const double *c, const double *d) {
+  double u[3], v[3], t[3];
+  for (int k = 0; k < 3; ++k) { u[k] = b[k] - a[k]; v[k] = c[k] - a[k]; t[k] = d[k] - a[k]; }
+  const double det = u[0] * (v[1] * t[2] - v[2] * t[1]) - u[1] * (v[0] * t[2] - v[2] * t[0]) +
+                     u[2] * (v[0] * t[1] - v[1] * t[0]);
+  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+  if (fabs(det) <= 1e-12 * sqrt(uu * vv * tt)) {
+    const double *P[4] = {a, b, c, d};
+    OBall best;
+    best.r2 = -1;
+    for (int i = 0; i < 4; ++i)
+      for (int j = i + 1; j < 4; ++j) {
+        OBall cand[3];
+        int nc = 0;
+        cand[nc++] = ob_two(P[i], P[j]);
+        for (int k = j + 1; k < 4; ++k) cand[nc++] = ob_three(P[i], P[j], P[k]);
+        for (int q = 0; q < nc; ++q) {
+          int ok = 1;
+          for (int m = 0; m < 4; ++m) ok &= ob_in(&cand[q], P[m]);
+          if (ok && (best.r2 < 0 || cand[q].r2 < best.r2)) best = cand[q];
+        }
+      }
+    return best;
+  }
+  /* solve 2 [u; v; t] x = [uu; vv; tt] for the centre offset x (Cramer) */
+  const double r0 = 0.5 * uu, r1 = 0.5 * vv, r2 = 0.5 * tt;
+  OBall B;
+  double x[3];
+  x[0] = (r0 * (v[1] * t[2] - v[2] * t[1]) - u[1] * (r1 * t[2] - v[2] * r2) +
+          u[2] * (r1 * t[1] - v[1] * r2)) / det;
+  x[1] = (u[0] * (r1 * t[2] - v[2] * r2) - r0 * (v[0] * t[2] - v[2] * t[0]) +
+          u[2] * (v[0] * r2 - r1 * t[0])) / det;
+  x[2] = (u[0] * (v[1] * r2 - r1 * t[1]) - u[1] * (v[0] * r2 - r1 * t[0]) +
+          r0 * (v[0] * t[1] - v[1] * t[0])) / det;
+  for (int k = 0; k < 3; ++k) B.c[k] = a[k] + x[k];
+  B.r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  return B;
+}
+
+static OBall ob_support(const double **R, int nr) {
+  OBall B;
+  switch (nr) {
+    case 0: B.c[0] = B.c[1] = B.c[2] = 0; B.r2 = -1; return B;
+    case 1: for (int k = 0; k < 3; ++k) B.c[k] = R[0][k]; B.r2 = 0; return B;
+    case 2: return ob_two(R[0], R[1]);
+    case 3: return ob_three(R[0], R[1], R[2]);
+    default: return ob_four(R[0], R[1], R[2], R[3]);
+  }
+}
+
+/* Welzl: the smallest ball holding P[0..n) with R[0..nr) on its boundary */
+static OBall ob_welzl(const double **P, int n, const double **R, int nr) {
+  if (n == 0 || nr == 4) return ob_support(R, nr);
+  OBall B = ob_welzl(P, n - 1, R, nr);
+  if (ob_in(&B, P[n - 1])) return B;
+  const double *R2[4];
+  for (int k = 0; k < nr; ++k) R2[k] = R[k];
+  R2[nr] = P[n - 1];
+  return ob_welzl(P, n - 1, R2, nr + 1);
+}
+
+static double ob_radius(const double *const *P, int n, const double c[3]) {
+  double r = 0;
+  for (int q = 0; q < n; ++q) {
+    const double d = sqrt(dist2(P[q], c));
+    if (d > r) r = d;
+  }
+  return r;
+}
+
+static void group_ball(const double **P, int n, const double *mass, int kind, double out[4]) {
+  double c[3];
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) lo[a] = hi[a] = P[0][a];
+  for (int q = 0; q < n; ++q)
+    for (int a = 0; a < 3; ++a) {
+      if (P[q][a] < lo[a]) lo[a] = P[q][a];
+      if (P[q][a] > hi[a]) hi[a] = P[q][a];
+    }
+  double geo[3];
+  for (int a = 0; a < 3; ++a) geo[a] = 0.5 * (lo[a] + hi[a]);
+  if (kind == 1) {
+    const double *R[4];
+    OBall B = ob_welzl(P, n, R, 0);
+    for (int a = 0; a < 3; ++a) c[a] = B.c[a];
+  } else if (kind == 2) {
+    int y = 0, z = 0;
+    for (int q = 0; q < n; ++q) if (dist2(P[q], P[0]) > dist2(P[y], P[0])) y = q;
+    for (int q = 0; q < n; ++q) if (dist2(P[q], P[y]) > dist2(P[z], P[y])) z = q;
+    double r = 0.5 * sqrt(dist2(P[y], P[z]));
+    for (int a = 0; a < 3; ++a) c[a] = 0.5 * (P[y][a] + P[z][a]);
+    for (int q = 0; q < n; ++q) {
+      const double d = sqrt(dist2(P[q], c));
+      if (d > r) {  /* grow: the new ball holds the old one and P[q] */
+        const double rn = 0.5 * (r + d);
+        for (int a = 0; a < 3; ++a) c[a] += (P[q][a] - c[a]) * (rn - r) / d;
+        r = rn;
+      }
+    }
+  } else if (kind == 3 || kind == 4) {
+    double M = 0, s[3] = {0, 0, 0};
+    for (int q = 0; q < n; ++q) {
+      M += mass[q];
+      for (int a = 0; a < 3; ++a) s[a] += mass[q] * P[q][a];
+    }
+    for (int a = 0; a < 3; ++a) c[a] = M > 0 ? s[a] / M : geo[a];
+    if (kind == 4 && !(ob_radius(P, n, c) < ob_radius(P, n, geo) * (1.0 - 1e-5)))
+      for (int a = 0; a < 3; ++a) c[a] = geo[a];
+  } else {
+    for (int a = 0; a < 3; ++a) c[a] = geo[a];
+  }
+  for (int a = 0; a < 3; ++a) out[a] = c[a];
+  out[3] = ob_radius(P, n, c);
+}
+
+/* plain smallest enclosing ball of points pts[n][3] (for tests) */
+void orc_seb(int n, const double *pts, double out[4]) {
+  const double **P = (const double **)malloc(sizeof(double *) * (size_t)(n > 0 ? n : 1));
+  for (int q = 0; q < n; ++q) P[q] = pts + 3 * q;
+  const double *R[4];
+  OBall B = ob_welzl(P, n, R, 0);
+  for (int a = 0; a < 3; ++a) out[a] = B.c[a];
+  out[3] = ob_radius(P, n, B.c);
+  free(P);
+}
+
+/* ---------------------------------------------------------------------- */
 /* Groups (Sections 2.3-2.4): the active particles in key order.  Following
  * Section 2.4, two consecutive active particles farther apart than the
  * critical separation r_crit are never put in the same group (r_crit <= 0:
  * no such split); each run between such gaps is cut into groups of at most G
  * consecutive particles.  The gap test compares the float64 squared distance
  * of the (float32) positions with r_crit^2.  Each group gets a pseudo
- * i-particle: the geometric centre of its bounding box r_I and the radius
- * b_I = max |r_i - r_I| (GEO ball, Appendix B).
+ * i-particle (r_I, b_I): an enclosing ball of the kind `ball_kind` (see
+ * group_ball; GEO by default).
  * act_sorted[k] = active flag of sorted particle k.  Outputs: alist (sorted
  * indices of active particles), gfirst/gcount into alist, ball[4g..] = r_I, b_I.
  * Returns the number of groups.                                              */
 int64_t orc_groups(int64_t n, const uint8_t *act_sorted, const double *ps, int G,
                    double r_crit, uint32_t *alist, uint32_t *gfirst, uint32_t *gcount,
-                   double *ball) {
+                   double *ball, int ball_kind) {
   int64_t na = 0;
   for (int64_t k = 0; k < n; ++k)
     if (act_sorted[k]) alist[na++] = (uint32_t)k;
@@ -324,26 +510,17 @@ int64_t orc_groups(int64_t n, const uint8_t *act_sorted, const double *ps, int G
   }
   for (int64_t g = 0; g < ng; ++g)
     gcount[g] = (uint32_t)((g + 1 < ng ? gfirst[g + 1] : na) - gfirst[g]);
+#pragma omp parallel for schedule(dynamic, 16)
   for (int64_t g = 0; g < ng; ++g) {
-    const int64_t s = gfirst[g], e = s + gcount[g];
-    double lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = ps[4 * (int64_t)alist[s] + a];
-    for (int64_t q = s; q < e; ++q)
-      for (int a = 0; a < 3; ++a) {
-        const double v = ps[4 * (int64_t)alist[q] + a];
-        if (v < lo[a]) lo[a] = v;
-        if (v > hi[a]) hi[a] = v;
-      }
-    double c[3];
-    for (int a = 0; a < 3; ++a) c[a] = 0.5 * (lo[a] + hi[a]);
-    double bI = 0;
-    for (int64_t q = s; q < e; ++q) {
-      const double *p = ps + 4 * (int64_t)alist[q];
-      const double d = sqrt((p[0] - c[0]) * (p[0] - c[0]) + (p[1] - c[1]) * (p[1] - c[1]) +
-                            (p[2] - c[2]) * (p[2] - c[2]));
-      if (d > bI) bI = d;
+    const int64_t s = gfirst[g];
+    const int cnt = (int)gcount[g];
+    const double *P[64];
+    double m[64];
+    for (int q = 0; q < cnt && q < 64; ++q) {
+      P[q] = ps + 4 * (int64_t)alist[s + q];
+      m[q] = ps[4 * (int64_t)alist[s + q] + 3];
     }
-    ball[4 * g] = c[0]; ball[4 * g + 1] = c[1]; ball[4 * g + 2] = c[2]; ball[4 * g + 3] = bI;
+    group_ball(P, cnt < 64 ? cnt : 64, m, ball_kind, ball + 4 * g);
   }
   return ng;
 }

@@ -34,7 +34,8 @@ class Params(C.Structure):
                 ("group_size", C.c_int), ("list_depth", C.c_int), ("compensated", C.c_int),
                 ("check", C.c_int), ("timing", C.c_int), ("r_crit", C.c_float),
                 ("graph", C.c_int), ("autotune", C.c_int), ("rebuild_interval", C.c_int),
-                ("mac", C.c_int), ("mac_delta", C.c_float), ("node_capacity", C.c_int64)]
+                ("mac", C.c_int), ("mac_delta", C.c_float), ("ball", C.c_int),
+                ("node_capacity", C.c_int64)]
 
 
 class TuneResult(C.Structure):

@@ -165,6 +165,7 @@ static int validate_params(const gothic_params *p) {
   if (p->mac < 0 || p->mac > 2) return set_error(GOTHIC_EINVAL, "mac must be 0, 1 or 2");
   if (!(p->mac_delta > 0.f) || !std::isfinite(p->mac_delta))
     return set_error(GOTHIC_EINVAL, "mac_delta must be finite and > 0");
+  if (p->ball < 0 || p->ball > 4) return set_error(GOTHIC_EINVAL, "ball must be in 0..4");
   return GOTHIC_OK;
 }
 
@@ -613,6 +614,7 @@ void gothic_default_params(gothic_params *p) {
   p->rebuild_interval = 1;
   p->mac = 0;
   p->mac_delta = 0.0078125f;  // 2^-7
+  p->ball = 0;
   p->node_capacity = 0;
 }
 
@@ -671,7 +673,7 @@ int gothic_set_params(gothic_ctx *c, const gothic_params *p) {
   if (a.key_kind != b.key_kind || a.n_leaf != b.n_leaf || a.multipole != b.multipole ||
       a.group_size != b.group_size || a.list_depth != b.list_depth ||
       a.compensated != b.compensated || a.graph != b.graph || a.mac != b.mac ||
-      a.mac_delta != b.mac_delta || a.node_capacity != b.node_capacity)
+      a.mac_delta != b.mac_delta || a.ball != b.ball || a.node_capacity != b.node_capacity)
     ++c->generation;
   c->prm = *p;
   return GOTHIC_OK;

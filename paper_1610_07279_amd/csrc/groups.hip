@@ -5,10 +5,9 @@
 // between replays of a captured step) start a new group (the squared gap is compared with
 // r_crit^2 in float64 without fused operations, so the bounds are exact and
 // reproducible); every run between such gaps is cut into groups of at most G.
-// Each group gets its pseudo i-particle: the geometric centre r_I of the
-// group's bounding box and the radius b_I of the sphere about r_I that holds
-// every member (the GEO ball of Appendix B).  b_I is computed in FP32 and
-// widened by a few ulp so the sphere provably holds the members.
+// Each group gets its pseudo i-particle (r_I, b_I): an enclosing ball of the
+// kind params.ball selects (Appendix B; the geometric centre of the bounding
+// box by default), see group_ball_k.
 #include "common.h"
 #include "primitives.h"
 
@@ -102,31 +101,242 @@ group_first_k(Ctl *__restrict__ ctl, const uint32_t *__restrict__ gflag,
     if (gflag[a]) gfirst[gidx[a]] = (uint32_t)a;
 }
 
+// ---------------------------------------------------------------- balls
+// Enclosing balls of a group (pseudo i-particles, Appendix B): a centre of
+// the chosen kind, and the largest member distance from it as the radius
+// (float32, widened by 4 ulp so the sphere provably holds the members).
+//   GEO bounding-box centre; SEB smallest enclosing ball; EBS Ritter's
+//   sphere; COM centre of mass; CMP the smaller of GEO and COM.
+// One wave per group, member q in lane q (G <= 64).  SEB and EBS centres are
+// computed in float64 with wave-uniform control: ballots find the next
+// member outside the current ball.
+struct DBall {
+  double x, y, z, r2;
+};
+
+__device__ __forceinline__ double d2of(double ax, double ay, double az, double bx, double by,
+                                       double bz) {
+  const double x = ax - bx, y = ay - by, z = az - bz;
+  return x * x + y * y + z * z;
+}
+
+__device__ __forceinline__ bool in_ball(const DBall &B, double x, double y, double z) {
+  return d2of(x, y, z, B.x, B.y, B.z) <= B.r2 * (1.0 + 1e-12);
+}
+
+__device__ DBall dball2(double ax, double ay, double az, double bx, double by, double bz) {
+  return DBall{0.5 * (ax + bx), 0.5 * (ay + by), 0.5 * (az + bz), 0.25 * d2of(ax, ay, az, bx, by, bz)};
+}
+
+// smallest ball with the three points on its boundary (their circumcircle);
+// nearly collinear points: the ball of the farthest pair
+__device__ DBall dball3(const double *a, const double *b, const double *c) {
+  const double ux = b[0] - a[0], uy = b[1] - a[1], uz = b[2] - a[2];
+  const double vx = c[0] - a[0], vy = c[1] - a[1], vz = c[2] - a[2];
+  const double wx = uy * vz - uz * vy, wy = uz * vx - ux * vz, wz = ux * vy - uy * vx;
+  const double uu = ux * ux + uy * uy + uz * uz, vv = vx * vx + vy * vy + vz * vz;
+  const double ww = wx * wx + wy * wy + wz * wz;
+  if (ww <= 1e-24 * uu * vv) {
+    const double dab = uu, dac = vv, dbc = d2of(b[0], b[1], b[2], c[0], c[1], c[2]);
+    if (dab >= dac && dab >= dbc) return dball2(a[0], a[1], a[2], b[0], b[1], b[2]);
+    if (dac >= dbc) return dball2(a[0], a[1], a[2], c[0], c[1], c[2]);
+    return dball2(b[0], b[1], b[2], c[0], c[1], c[2]);
+  }
+  const double tx = uu * vx - vv * ux, ty = uu * vy - vv * uy, tz = uu * vz - vv * uz;
+  const double h = 0.5 / ww;
+  DBall B;
+  B.x = a[0] + (ty * wz - tz * wy) * h;
+  B.y = a[1] + (tz * wx - tx * wz) * h;
+  B.z = a[2] + (tx * wy - ty * wx) * h;
+  B.r2 = d2of(a[0], a[1], a[2], B.x, B.y, B.z);
+  return B;
+}
+
+// the sphere through four points; nearly coplanar: the smallest ball of
+// two or three of them that holds all four
+__device__ DBall dball4(const double *a, const double *b, const double *c, const double *d) {
+  const double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+  const double v[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+  const double t[3] = {d[0] - a[0], d[1] - a[1], d[2] - a[2]};
+  const double c0 = v[1] * t[2] - v[2] * t[1], c1 = v[0] * t[2] - v[2] * t[0],
+               c2 = v[0] * t[1] - v[1] * t[0];
+  const double det = u[0] * c0 - u[1] * c1 + u[2] * c2;
+  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+  if (fabs(det) <= 1e-12 * sqrt(uu * vv * tt)) {
+    const double *P[4] = {a, b, c, d};
+    DBall best{0, 0, 0, -1.0};
+    for (int i = 0; i < 4; ++i)
+      for (int j = i + 1; j < 4; ++j)
+        for (int k = j; k < 4; ++k) {  // k == j: the pair ball
+          const DBall cand = (k == j) ? dball2(P[i][0], P[i][1], P[i][2], P[j][0], P[j][1], P[j][2])
+                                      : dball3(P[i], P[j], P[k]);
+          bool ok = true;
+          for (int m = 0; m < 4; ++m) ok = ok && in_ball(cand, P[m][0], P[m][1], P[m][2]);
+          if (ok && (best.r2 < 0 || cand.r2 < best.r2)) best = cand;
+        }
+    return best;
+  }
+  const double r0 = 0.5 * uu, r1 = 0.5 * vv, r2 = 0.5 * tt;
+  const double x0 = (r0 * c0 - u[1] * (r1 * t[2] - v[2] * r2) + u[2] * (r1 * t[1] - v[1] * r2)) / det;
+  const double x1 = (u[0] * (r1 * t[2] - v[2] * r2) - r0 * c1 + u[2] * (v[0] * r2 - r1 * t[0])) / det;
+  const double x2 = (u[0] * (v[1] * r2 - r1 * t[1]) - u[1] * (v[0] * r2 - r1 * t[0]) + r0 * c2) / det;
+  return DBall{a[0] + x0, a[1] + x1, a[2] + x2, x0 * x0 + x1 * x1 + x2 * x2};
+}
+
+__device__ __forceinline__ int first_lane(unsigned long long m) {
+  return __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1);
+}
+
+// smallest enclosing ball: the incremental algorithm with up to four
+// boundary points; every loop index only grows, so it ends
+__device__ DBall seb_wave(double px, double py, double pz, int cnt) {
+  const int lane = lane_id();
+  const double P0[3] = {__shfl(px, 0, 64), __shfl(py, 0, 64), __shfl(pz, 0, 64)};
+  DBall B{P0[0], P0[1], P0[2], 0.0};
+  int i = 0;
+  for (;;) {
+    const unsigned long long mi = __ballot(lane > i && lane < cnt && !in_ball(B, px, py, pz));
+    if (!mi) break;
+    i = first_lane(mi);
+    const double Pi[3] = {__shfl(px, i, 64), __shfl(py, i, 64), __shfl(pz, i, 64)};
+    B = DBall{Pi[0], Pi[1], Pi[2], 0.0};
+    int j = -1;
+    for (;;) {
+      const unsigned long long mj = __ballot(lane > j && lane < i && !in_ball(B, px, py, pz));
+      if (!mj) break;
+      j = first_lane(mj);
+      const double Pj[3] = {__shfl(px, j, 64), __shfl(py, j, 64), __shfl(pz, j, 64)};
+      B = dball2(Pi[0], Pi[1], Pi[2], Pj[0], Pj[1], Pj[2]);
+      int k = -1;
+      for (;;) {
+        const unsigned long long mk = __ballot(lane > k && lane < j && !in_ball(B, px, py, pz));
+        if (!mk) break;
+        k = first_lane(mk);
+        const double Pk[3] = {__shfl(px, k, 64), __shfl(py, k, 64), __shfl(pz, k, 64)};
+        B = dball3(Pi, Pj, Pk);
+        int l = -1;
+        for (;;) {
+          const unsigned long long ml = __ballot(lane > l && lane < k && !in_ball(B, px, py, pz));
+          if (!ml) break;
+          l = first_lane(ml);
+          const double Pl[3] = {__shfl(px, l, 64), __shfl(py, l, 64), __shfl(pz, l, 64)};
+          B = dball4(Pi, Pj, Pk, Pl);
+        }
+      }
+    }
+  }
+  return B;
+}
+
+// Ritter's sphere: the diameter of two far members, grown in member order
+__device__ void ebs_wave(double px, double py, double pz, int cnt, double &cx, double &cy,
+                         double &cz) {
+  const int lane = lane_id();
+  const bool v = lane < cnt;
+  const double x0 = __shfl(px, 0, 64), y0 = __shfl(py, 0, 64), z0 = __shfl(pz, 0, 64);
+  // farthest member from member 0 (first one on ties), then farthest from it
+  double d = v ? d2of(px, py, pz, x0, y0, z0) : -1.0;
+  double dm = d;
+  for (int o = 32; o >= 1; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+  const int y = first_lane(__ballot(v && d == dm));
+  const double yx = __shfl(px, y, 64), yy = __shfl(py, y, 64), yz = __shfl(pz, y, 64);
+  d = v ? d2of(px, py, pz, yx, yy, yz) : -1.0;
+  dm = d;
+  for (int o = 32; o >= 1; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+  const int z = first_lane(__ballot(v && d == dm));
+  const double zx = __shfl(px, z, 64), zy = __shfl(py, z, 64), zz = __shfl(pz, z, 64);
+  cx = 0.5 * (yx + zx);
+  cy = 0.5 * (yy + zy);
+  cz = 0.5 * (yz + zz);
+  double r = 0.5 * sqrt(d2of(yx, yy, yz, zx, zy, zz));
+  // members are visited in order; the ball only grows, so a member inside it
+  // stays inside and the next member outside is the next one to take in
+  int q = -1;
+  for (;;) {
+    const double dq = sqrt(d2of(px, py, pz, cx, cy, cz));
+    const unsigned long long m = __ballot(v && lane > q && dq > r);
+    if (!m) break;
+    q = first_lane(m);
+    const double dd = __shfl(dq, q, 64);
+    const double qx = __shfl(px, q, 64), qy = __shfl(py, q, 64), qz = __shfl(pz, q, 64);
+    const double rn = 0.5 * (r + dd);
+    const double f = (rn - r) / dd;
+    cx += (qx - cx) * f;
+    cy += (qy - cy) * f;
+    cz += (qz - cz) * f;
+    r = rn;
+  }
+}
+
+__device__ __forceinline__ float ball_radius(float4 p, float cx, float cy, float cz) {
+  const float dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
+  return wave_max(sqrtf(dx * dx + dy * dy + dz * dz));
+}
+
 // one wave per group; loop control is wave-uniform and the member load is
 // predicated (lanes past the group's end re-read its first member)
 __global__ void __launch_bounds__(256)
-group_ball_k(int64_t n, const Ctl *__restrict__ ctl, const uint32_t *__restrict__ alist,
+group_ball_k(int64_t n, int kind, const Ctl *__restrict__ ctl, const uint32_t *__restrict__ alist,
              const uint32_t *__restrict__ gfirst, const float4 *__restrict__ pos,
              float4 *__restrict__ ball, const float *__restrict__ amag,
              float *__restrict__ gamin) {
-  const unsigned ng = ctl->n_groups, na = ctl->n_active;
+  const unsigned ng = ctl->n_groups;
   const int lane = lane_id();
   const int64_t wid = __builtin_amdgcn_readfirstlane(
       (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  constexpr float kWiden = 1.0f + 4.0f * 1.1920929e-7f;
   for (int64_t g = wid; g < ng; g += nw) {
     const int64_t s = gfirst[g];
     const int64_t e = gfirst[g + 1];
     const int cnt = (int)(e - s < 64 ? (e > s ? e - s : 1) : 64);
-    (void)na;
-    const uint32_t ai = alist[s + (lane < cnt ? lane : 0)];
+    // SEB visits the members in a fixed pseudo-random order (lane q holds
+    // member (97 q + 13) mod cnt), which keeps its expected work linear
+    const int mem = (kind == 1) ? (int)((97u * (unsigned)lane + 13u) % (unsigned)cnt)
+                                : (lane < cnt ? lane : 0);
+    const uint32_t ai = alist[s + (lane < cnt ? mem : 0)];
     const float4 p = pos[ai < n ? ai : 0];
+    float cx, cy, cz;
+    // GEO (also the fallback half of CMP)
     const float lx = wave_min(p.x), ly = wave_min(p.y), lz = wave_min(p.z);
     const float hx = wave_max(p.x), hy = wave_max(p.y), hz = wave_max(p.z);
-    const float cx = 0.5f * (lx + hx), cy = 0.5f * (ly + hy), cz = 0.5f * (lz + hz);
-    const float dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
-    const float r = wave_max(sqrtf(dx * dx + dy * dy + dz * dz));
-    ball[g] = make_float4(cx, cy, cz, r * (1.0f + 4.0f * 1.1920929e-7f));  // same from all lanes
+    cx = 0.5f * (lx + hx);
+    cy = 0.5f * (ly + hy);
+    cz = 0.5f * (lz + hz);
+    if (kind == 1 || kind == 2) {
+      double dx, dy, dz;
+      if (kind == 1) {
+        const DBall B = seb_wave((double)p.x, (double)p.y, (double)p.z, cnt);
+        dx = B.x; dy = B.y; dz = B.z;
+      } else {
+        ebs_wave((double)p.x, (double)p.y, (double)p.z, cnt, dx, dy, dz);
+      }
+      cx = (float)dx; cy = (float)dy; cz = (float)dz;
+    } else if (kind == 3 || kind == 4) {
+      const double m = lane < cnt ? (double)p.w : 0.0;
+      double M = m, sx = m * p.x, sy = m * p.y, sz = m * p.z;
+      for (int o = 32; o >= 1; o >>= 1) {
+        M += __shfl_xor(M, o, 64);
+        sx += __shfl_xor(sx, o, 64);
+        sy += __shfl_xor(sy, o, 64);
+        sz += __shfl_xor(sz, o, 64);
+      }
+      if (M > 0.0) {
+        const float mx = (float)(sx / M), my = (float)(sy / M), mz = (float)(sz / M);
+        if (kind == 3) {
+          cx = mx; cy = my; cz = mz;
+        } else {  // CMP: COM only if clearly smaller than GEO
+          const float rg = ball_radius(p, cx, cy, cz), rm = ball_radius(p, mx, my, mz);
+          if (rm < rg * (1.0f - 1e-5f)) {
+            cx = mx; cy = my; cz = mz;
+          }
+        }
+      }
+    }
+    const float r = ball_radius(p, cx, cy, cz);
+    ball[g] = make_float4(cx, cy, cz, r * kWiden);  // same from all lanes
     if (amag) {  // acceleration MAC: the group's smallest |a_old|
       const float am = wave_min(amag[ai < n ? ai : 0]);
       gamin[g] = am;
@@ -155,8 +365,8 @@ void launch_groups(gothic_ctx *c, int64_t n, hipStream_t s) {
   int64_t wb = (n + 3) / 4;
   int gb = (int)(wb > 8192 ? 8192 : (wb < 1 ? 1 : wb));
   const bool acc_mac = c->prm.mac == 1;
-  hipLaunchKernelGGL(group_ball_k, dim3(gb), dim3(256), 0, s, n, B.ctl, B.alist, B.gfirst, B.pos,
-                     B.ball, acc_mac ? B.amag : nullptr, B.gamin);
+  hipLaunchKernelGGL(group_ball_k, dim3(gb), dim3(256), 0, s, n, c->prm.ball, B.ctl, B.alist,
+                     B.gfirst, B.pos, B.ball, acc_mac ? B.amag : nullptr, B.gamin);
 }
 
 }  // namespace gothic

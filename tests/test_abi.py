@@ -30,8 +30,8 @@ def test_defaults_and_cpu_only_errors():
     import paper_1610_07279_amd as g
     p = g.default_params()
     assert (p.key_kind, p.n_leaf, p.multipole, p.group_size, p.list_depth, p.compensated,
-            p.check, p.timing, p.graph, p.autotune, p.rebuild_interval, p.mac,
-            p.node_capacity) == (0, 16, 1, 32, 384, 1, 1, 0, 0, 0, 1, 0, 0)
+            p.check, p.timing, p.graph, p.autotune, p.rebuild_interval, p.mac, p.ball,
+            p.node_capacity) == (0, 16, 1, 32, 384, 1, 1, 0, 0, 0, 1, 0, 0, 0)
     assert p.mac_delta == 2.0 ** -7
     assert p.r_crit == -0.0625
     # a NULL context is rejected before any device call

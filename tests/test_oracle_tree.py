@@ -184,3 +184,102 @@ def test_groups_chunks_and_geo_ball():
         c = 0.5 * (mem.min(0) + mem.max(0))
         assert np.array_equal(g["ball"][q, :3], c)
         assert np.isclose(g["ball"][q, 3], np.linalg.norm(mem - c, axis=1).max(), rtol=1e-15)
+
+
+# ---------------------------------------------------------------- enclosing balls (Appendix B)
+def _brute_seb(P):
+    """Smallest enclosing ball by enumerating every ball through 1-4 points."""
+    import itertools
+    best = None
+    for k in (1, 2, 3, 4):
+        for S in itertools.combinations(range(len(P)), k):
+            pts = P[list(S)]
+            if k == 1:
+                c = pts[0]
+            elif k == 2:
+                c = pts.mean(0)
+            elif k == 3:
+                a, b, cc = pts
+                u, v = b - a, cc - a
+                w = np.cross(u, v)
+                if w @ w < 1e-20:
+                    continue
+                c = a + np.cross((u @ u) * v - (v @ v) * u, w) / (2 * (w @ w))
+            else:
+                M = 2 * (pts[1:] - pts[0])
+                if abs(np.linalg.det(M)) < 1e-14:
+                    continue
+                c = np.linalg.solve(M, (pts[1:] ** 2).sum(1) - pts[0] @ pts[0])
+            r = np.sqrt(((P - c) ** 2).sum(1).max())
+            if best is None or r < best[1]:
+                best = (c, r)
+    return best
+
+
+def test_smallest_enclosing_ball_is_the_brute_force_minimum():
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        n = int(rng.integers(1, 9))
+        P = rng.normal(size=(n, 3)) * rng.uniform(0.01, 10)
+        c, r = oracle.seb(P)
+        cb, rb = _brute_seb(P)
+        assert abs(r - rb) <= 1e-9 * max(rb, 1e-300)
+        assert np.all(np.sqrt(((P - c) ** 2).sum(1)) <= r * (1 + 1e-12))
+
+
+def test_smallest_enclosing_ball_special_cases():
+    # regular tetrahedron: the circumsphere; square: its circumcircle; a
+    # segment with interior points: half its length; repeated points
+    tet = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float)
+    c, r = oracle.seb(tet)
+    assert np.allclose(c, 0, atol=1e-12) and abs(r - np.sqrt(3)) < 1e-12
+    sq = np.array([[1, 0, 5], [0, 1, 5], [-1, 0, 5], [0, -1, 5], [0.2, 0.1, 5]], float)
+    c, r = oracle.seb(sq)
+    assert np.allclose(c, [0, 0, 5], atol=1e-12) and abs(r - 1) < 1e-12
+    seg = np.array([[0, 0, 0], [0.3, 0, 0], [2, 0, 0], [1.1, 0, 0]], float)
+    c, r = oracle.seb(seg)
+    assert np.allclose(c, [1, 0, 0], atol=1e-12) and abs(r - 1) < 1e-12
+    rep = np.array([[0.5, 0.5, 0.5]] * 5 + [[1.5, 0.5, 0.5]], float)
+    c, r = oracle.seb(rep)
+    assert abs(r - 0.5) < 1e-12
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4])
+def test_group_balls_contain_their_members(kind):
+    x = ics.nfw(6000, seed=12)
+    k, _ = oracle.keys(x)
+    ks, perm = oracle.sort(k)
+    ps = x[perm].astype(np.float64)
+    act = ics.random_active(6000, 0.5, seed=13)[perm]
+    grp = oracle.groups(act, ps, 32, 0.0, kind)
+    seb_r = []
+    for q in range(grp["first"].size):
+        mem = ps[grp["alist"][grp["first"][q]:grp["first"][q] + grp["count"][q]], :3]
+        c, r = grp["ball"][q, :3], grp["ball"][q, 3]
+        dist = np.sqrt(((mem - c) ** 2).sum(1))
+        assert r == dist.max()  # the radius is the largest member distance
+        _, rs = oracle.seb(mem)
+        seb_r.append((r, rs))
+        if kind == 1:
+            assert abs(r - rs) <= 1e-12 * rs
+    ratio = np.array([r / rs for r, rs in seb_r if rs > 0])
+    assert np.all(ratio >= 1 - 1e-12)
+    if kind == 2:   # Ritter: a few per cent above the minimum
+        assert np.median(ratio) < 1.05 and ratio.max() < 1.3
+    if kind == 0:   # bounding-box centre: at most sqrt(3) x the minimum
+        assert ratio.max() <= np.sqrt(3) + 1e-12
+
+
+def test_cmp_ball_is_the_smaller_of_geo_and_com():
+    x = ics.plummer(5000, seed=14)
+    k, _ = oracle.keys(x)
+    ks, perm = oracle.sort(k)
+    ps = x[perm].astype(np.float64)
+    act = np.ones(5000, np.uint8)
+    geo = oracle.groups(act, ps, 16, 0.0, 0)["ball"]
+    com = oracle.groups(act, ps, 16, 0.0, 3)["ball"]
+    cmp_ = oracle.groups(act, ps, 16, 0.0, 4)["ball"]
+    use_com = com[:, 3] < geo[:, 3] * (1 - 1e-5)
+    assert np.array_equal(cmp_[use_com], com[use_com])
+    assert np.array_equal(cmp_[~use_com], geo[~use_com])
+    assert 0 < use_com.mean() < 1

@@ -225,10 +225,14 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 24)
     ap.add_argument("--group-size", type=int, default=32)
     ap.add_argument("--list-depth", type=int, default=384)
-    ap.add_argument("--r-crit", type=float, default=0.5,
+    ap.add_argument("--r-crit", type=float, default=0.25,
                     help="critical separation splitting groups (Section 2.4)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-shared", action="store_true", help="skip the shared-step run")
+    ap.add_argument("--autotune", type=int, default=0, choices=(0, 1),
+                    help="tune r_crit online during the block steps (Section 2.4)")
+    ap.add_argument("--ball", type=int, default=2, choices=range(5),
+                    help="enclosing ball of the groups (Appendix B): 0 GEO, 1 SEB, 2 EBS, 3 COM, 4 CMP")
     ap.add_argument("--rebuild-interval", type=int, default=0,
                     help="tree reuse: 0 = automatic (the growth models of Section 2.6), "
                          "1 = new tree every sub-step, k = every k sub-steps")
@@ -289,7 +293,8 @@ def main():
     mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).to(dev)
     ctx = g.Context(device=0, multipole=multipole, group_size=args.group_size,
                     list_depth=args.list_depth, r_crit=args.r_crit, timing=1, graph=args.graph,
-                    rebuild_interval=args.rebuild_interval)
+                    rebuild_interval=args.rebuild_interval, ball=args.ball,
+                    autotune=args.autotune)
 
     log(f"bench: block steps (warmup {args.warmup}, timed {args.steps})")
     blk = run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, False, args.steps, args.warmup)
@@ -325,7 +330,8 @@ def main():
                                f"block steps kmax=8 (eta=0.1), finest sub-steps",
                    "n": n, "group_size": args.group_size, "list_depth": args.list_depth,
                    "r_crit": args.r_crit, "graph": args.graph,
-                   "rebuild_interval": args.rebuild_interval,
+                   "rebuild_interval": args.rebuild_interval, "ball": args.ball,
+                   "autotune": args.autotune,
                    "parallelism": "single GPU"},
         "block": {"s_per_step": blk["seconds"] / args.steps,
                   "interactions_per_s": inter / blk["seconds"],

@@ -130,12 +130,12 @@ static void free_all(gothic_ctx *c) {
                   B.gA, B.gB, B.gfirst,
                   B.first, B.count, B.child_first, B.parent, B.n_child, B.level, B.nch, B.bnd,
                   B.nrec, B.quad, B.ball, B.gent, B.hist, B.part, B.bbox_part, B.spill, B.sys,
-                  B.soff, B.rcrit, B.mcrit, B.amag, B.gamin, B.ctl};
+                  B.soff, B.rcrit, B.mcrit, B.amag, B.gamin, B.anc, B.leaflev, B.ctl};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (B.ctl_host) (void)hipHostFree(B.ctl_host);
   B = Buffers();
-  c->cap_n = c->cap_nodes = c->cap_groups = c->cap_hist = c->cap_sys = 0;
+  c->cap_n = c->cap_nodes = c->cap_groups = c->cap_hist = c->cap_sys = c->cap_anc = 0;
   ++c->generation;
   ++c->buffers;
 }
@@ -226,6 +226,14 @@ static int ensure(gothic_ctx *c, int64_t n, int nsys, int64_t want_nodes, int64_
     ++c->generation;
     ++c->buffers;
   }
+  if (c->cap_anc < c->cap_n) {
+    if ((rc = dev_alloc(&B.anc, (int64_t)kMaxLevels * c->cap_n)) ||
+        (rc = dev_alloc(&B.leaflev, c->cap_n)))
+      return rc;
+    c->cap_anc = c->cap_n;
+    ++c->generation;
+    ++c->buffers;
+  }
   const int slots = walk_slots(c);
   const int64_t spill = std::max<int64_t>(want_spill, 16384);
   if (slots != c->walk_waves || spill > c->spill_per_wave || !B.spill) {
@@ -289,6 +297,7 @@ static void enqueue_make(gothic_ctx *c, const Systems &sy, const float4 *xyzm, h
   launch_bbox_keys(c, xyzm, sy.n, sy.nsys, sy.max_n, s);
   launch_radix_sort(c, sy.n, sy.nsys, s);
   launch_build(c, sy.n, sy.nsys, s);
+  launch_ancestors(c, sy.n, s);
 }
 
 static void enqueue_post(gothic_ctx *c, const Systems &sy, const float4 *xyzm,

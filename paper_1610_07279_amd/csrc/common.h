@@ -86,6 +86,10 @@ struct Buffers {
   float *mcrit = nullptr;         // per node: critical distance of the multipole MAC
   float *amag = nullptr;          // |a_old| of each key-ordered particle (acceleration MAC)
   float *gamin = nullptr;         // smallest |a_old| of each group
+  // ancestors (capacity cap_anc particles): anc[l * n + k] is the level-l
+  // ancestor of key-ordered particle k, for l < leaflev[k] (its leaf's level)
+  uint32_t *anc = nullptr;
+  uint8_t *leaflev = nullptr;
   // groups (capacity cap_groups)
   float4 *ball = nullptr;
   uint32_t *gent = nullptr;       // 2 per group: node entries, particle entries
@@ -191,7 +195,7 @@ struct gothic_ctx {
   int device = 0;
   int num_cus = 256;
   gothic_params prm{};
-  int64_t cap_n = 0, cap_nodes = 0, cap_groups = 0, cap_hist = 0, cap_sys = 0;
+  int64_t cap_n = 0, cap_nodes = 0, cap_groups = 0, cap_hist = 0, cap_sys = 0, cap_anc = 0;
   int64_t spill_per_wave = 0;
   int walk_waves = 0;             // persistent walk waves (slots)
   gothic::Buffers b;
@@ -237,6 +241,8 @@ int64_t radix_hist_entries(int64_t n);
 void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active,
                     const float4 *acc_old, int64_t n, hipStream_t s);
 void launch_build(gothic_ctx *c, int64_t n, int nsys, hipStream_t s);
+// moments.hip: the ancestor table of a new tree
+void launch_ancestors(gothic_ctx *c, int64_t n, hipStream_t s);
 // moments.hip
 void launch_moments(gothic_ctx *c, int64_t n, int nsys, hipStream_t s);
 // groups.hip

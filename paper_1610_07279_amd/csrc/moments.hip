@@ -7,10 +7,10 @@
 //              r_J = r exactly and b_J = 0);
 //   internal:  bottom-up one level at a time from the children (masses and
 //              centres add; second moments by the parallel-axis rule);
-//   b_J:       particle-parallel: each particle walks up its ancestor chain
-//              one level per step; lanes of a wave that share an ancestor
-//              (always a contiguous run in key order) max-reduce their
-//              distances and one lane per run issues an atomic max.
+//   b_J:       particle-parallel over the ancestor table written with the
+//              tree: lanes of a wave that share an ancestor (always a
+//              contiguous run in key order) max-reduce their distances; whole
+//              nodes are stored, nodes shared between waves take an atomic max.
 // The node record read by the walk is written here: (x, y, z, M) and
 // (b_J, first|child_first, count|n_child, is_leaf).
 #include "common.h"
@@ -121,32 +121,145 @@ internal_moments_k(int l, Ctl *__restrict__ ctl, const uint32_t *__restrict__ ch
   }
 }
 
-// Each wave takes a contiguous chunk of key-ordered particles, in tiles of
-// 64.  A node's particles are contiguous, so at every level the ancestors of
-// a tile form runs; runs that end inside the tile are complete and issue one
-// atomic max each, the last run of a tile is carried to the next tile as a
-// per-level running (node, max) in LDS.  Upper-level nodes thus receive one
-// atomic per wave chunk instead of one per 64 particles.
+// ---------------------------------------------------------------- b_J
+// Every particle's ancestors are written once per tree into a level-major
+// table (anc[l * n + k] = the level-l ancestor of key-ordered particle k, for
+// l below its leaf's level).  The radius pass then works on contiguous chunks
+// of particles, one wave per chunk, in tiles of 64: a node's particles are
+// contiguous, so at every level the ancestors of a tile form runs.  A run
+// that starts and ends inside the wave's chunk is a whole node and its
+// maximum is stored; runs that may reach past either end of the chunk are
+// combined across waves with an atomic max.  The last run of every level is
+// carried from tile to tile in LDS.
+__global__ void __launch_bounds__(256)
+leaf_map_k(const Ctl *__restrict__ ctl, int64_t n, const uint32_t *__restrict__ first,
+           const uint32_t *__restrict__ count, const uint8_t *__restrict__ n_child,
+           uint32_t *__restrict__ leaf_of) {
+  if (ctl->flags & kFlagNodeOverflow) return;
+  const int64_t nn = ctl->n_nodes;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nn;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    if (n_child[k] != 0) continue;
+    const uint32_t f = first[k], c = count[k];
+    if ((int64_t)f + c > n) continue;
+    for (uint32_t j = f; j < f + c; ++j) leaf_of[j] = (uint32_t)k;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+ancestors_k(Ctl *__restrict__ ctl, int64_t n, const uint32_t *__restrict__ leaf_of,
+            const uint32_t *__restrict__ parent, const uint8_t *__restrict__ level,
+            uint32_t *__restrict__ anc, uint8_t *__restrict__ leaflev) {
+  if (ctl->flags & kFlagNodeOverflow) return;
+  const unsigned nn = ctl->n_nodes;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t node = leaf_of[k];
+    if (node >= nn) {
+      atomicOr(&ctl->flags, kFlagBadIndex);
+      leaflev[k] = 0;
+      continue;
+    }
+    const int L = level[node];
+    leaflev[k] = (uint8_t)L;
+    for (int l = L - 1; l >= 0; --l) {
+      const uint32_t up = parent[node];
+      node = up < nn ? up : 0u;
+      anc[(int64_t)l * n + k] = node;
+    }
+  }
+}
+
 constexpr int kRadiusWaves = 4;  // waves per workgroup
 
-__device__ __forceinline__ void flush_b(float4 *nrec, unsigned node, float v) {
-  // every lane passes the same (node, v): the atomic is combined per wave
-  atomicMax(reinterpret_cast<unsigned *>(&nrec[2 * (size_t)node + 1].x), __float_as_uint(v));
+// per wave and level: the run carried from tile to tile
+struct RadiusCarry {
+  unsigned node[kRadiusWaves][kMaxLevels];
+  float max[kRadiusWaves][kMaxLevels];
+  unsigned open[kRadiusWaves][kMaxLevels];  // the run may hold particles before the chunk
+};
+
+// the radius of a node seen by one wave: stored if the wave saw all of the
+// node's particles, else an atomic max (radii are >= 0, so their bit
+// patterns order like the values); one lane writes
+__device__ __forceinline__ void put_b(float4 *nrec, unsigned node, float v, bool shared_node) {
+  if (lane_id() == 0) {
+    float *dst = &nrec[2 * (size_t)node + 1].x;
+    if (shared_node) atomicMax(reinterpret_cast<unsigned *>(dst), __float_as_uint(v));
+    else *dst = v;
+  }
+}
+
+// one level of one tile: lane holds (key = node or kNone, dist); at_start:
+// the tile is the first of the chunk
+__device__ __forceinline__ void radius_level(float4 *nrec, RadiusCarry &rc, int w, int l,
+                                             unsigned key, float dist, bool at_start) {
+  const int lane = lane_id();
+  const bool part = key != kNone;
+  // segmented max over contiguous runs of equal key: the first lane of each
+  // run ends up with the run's maximum
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const float od = __shfl_down(dist, d, 64);
+    const unsigned ok = __shfl_down(key, d, 64);
+    dist = (lane + d < 64 && ok == key) ? fmaxf(dist, od) : dist;
+  }
+  const unsigned prev = __shfl_up(key, 1, 64);
+  const bool lead = part && (lane == 0 || prev != key);
+  const unsigned long long lm = __ballot(lead);
+  if (!lm) return;
+  const int fl = __builtin_amdgcn_readfirstlane(__ffsll((long long)lm) - 1);
+  const int ll = __builtin_amdgcn_readfirstlane(63 - __clzll((long long)lm));
+  const unsigned fnode = __builtin_amdgcn_readfirstlane(__shfl(key, fl, 64));
+  const unsigned lnode = __builtin_amdgcn_readfirstlane(__shfl(key, ll, 64));
+  const float fmx = __shfl(dist, fl, 64);
+  const float lmx = __shfl(dist, ll, 64);
+  unsigned rn = __builtin_amdgcn_readfirstlane(rc.node[w][l]);
+  float rm = rc.max[w][l];
+  bool ropen = __builtin_amdgcn_readfirstlane(rc.open[w][l]) != 0u;
+  // runs strictly inside the tile are whole nodes
+  if (lead && lane != fl && lane != ll) nrec[2 * (size_t)key + 1].x = dist;
+  const bool first_open = at_start && fl == 0;  // may continue from the previous chunk
+  if (fl == ll) {
+    if (fnode == rn) {
+      rm = fmaxf(rm, fmx);
+    } else {
+      if (rn != kNone) put_b(nrec, rn, rm, ropen);
+      rn = fnode;
+      rm = fmx;
+      ropen = first_open;
+    }
+  } else {
+    if (fnode == rn) {
+      put_b(nrec, rn, fmaxf(rm, fmx), ropen);
+    } else {
+      if (rn != kNone) put_b(nrec, rn, rm, ropen);
+      put_b(nrec, fnode, fmx, first_open);
+    }
+    rn = lnode;
+    rm = lmx;
+    ropen = false;
+  }
+  rc.node[w][l] = rn;  // same value from every lane
+  rc.max[w][l] = rm;
+  rc.open[w][l] = ropen ? 1u : 0u;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 __global__ void __launch_bounds__(256)
 radius_k(Ctl *__restrict__ ctl, int64_t n, const float4 *__restrict__ pos,
-         const uint32_t *__restrict__ leaf_of, const uint32_t *__restrict__ parent,
-         const uint8_t *__restrict__ level, float4 *__restrict__ nrec) {
+         const uint32_t *__restrict__ anc, const uint8_t *__restrict__ leaflev,
+         float4 *__restrict__ nrec) {
   if (ctl->flags & kFlagNodeOverflow) return;
   const unsigned nn = ctl->n_nodes;
-  __shared__ unsigned s_node[kRadiusWaves][kMaxLevels];
-  __shared__ float s_max[kRadiusWaves][kMaxLevels];
+  __shared__ RadiusCarry rc;
   const int w = threadIdx.x >> 6;
   const int lane = lane_id();
   if (lane < kMaxLevels) {
-    s_node[w][lane] = kNone;
-    s_max[w][lane] = 0.f;
+    rc.node[w][lane] = kNone;
+    rc.max[w][lane] = 0.f;
+    rc.open[w][lane] = 0u;
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -160,79 +273,52 @@ radius_k(Ctl *__restrict__ ctl, int64_t n, const float4 *__restrict__ pos,
     const bool inr = i < c1;
     const int64_t ic = inr ? i : c1 - 1;
     const float4 p = pos[ic];
-    const unsigned lf = leaf_of[ic];
-    const unsigned par = lf < nn ? parent[lf] : kNone;
-    unsigned node = (inr && (par < nn)) ? par : kNone;
-    int lv = (node != kNone) ? (int)level[node != kNone ? node : 0] : -1;
-    int top = lv;
+    const int L = inr ? (int)leaflev[ic] : 0;  // ancestors at levels 0 .. L-1
+    int top = L - 1;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) top = max(top, __shfl_xor(top, d, 64));
     top = __builtin_amdgcn_readfirstlane(top);
-    for (int l = top; l >= 0; --l) {
-      const bool part = (node != kNone) && (lv == l);
-      const unsigned key = part ? node : kNone;
-      const unsigned ns = part ? node : 0u;
-      const float4 r = nrec[2 * (size_t)ns];
-      // a parent is one level up (breadth-first levels): only the parent
-      // index is needed for the next level, loaded together with the record
-      const unsigned up0 = parent[ns];
-      const float dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z;
-      float dist = (part && r.w > 0.f) ? sqrtf(dx * dx + dy * dy + dz * dz) : 0.f;
-      // segmented max over contiguous runs of equal key: the first lane of
-      // each run ends up with the run's maximum
+    // the nodes of four levels are loaded before they are reduced
+    for (int l0 = top; l0 >= 0; l0 -= 4) {
+      unsigned nd[4];
+      float4 rr[4];
 #pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const float od = __shfl_down(dist, d, 64);
-        const unsigned ok = __shfl_down(key, d, 64);
-        dist = (lane + d < 64 && ok == key) ? fmaxf(dist, od) : dist;
+      for (int u = 0; u < 4; ++u) {
+        const int l = l0 - u;
+        const bool part = l >= 0 && l < L;
+        const unsigned a = part ? anc[(int64_t)l * n + ic] : kNone;
+        nd[u] = (part && a < nn) ? a : kNone;
       }
-      const unsigned prev = __shfl_up(key, 1, 64);
-      const bool lead = part && (lane == 0 || prev != key);
-      const unsigned long long lm = __ballot(lead);
-      if (lm) {
-        const int fl = __builtin_amdgcn_readfirstlane(__ffsll((long long)lm) - 1);
-        const int ll = __builtin_amdgcn_readfirstlane(63 - __clzll((long long)lm));
-        const unsigned fnode = __builtin_amdgcn_readfirstlane(__shfl(key, fl, 64));
-        const unsigned lnode = __builtin_amdgcn_readfirstlane(__shfl(key, ll, 64));
-        const float fmx = __shfl(dist, fl, 64);
-        const float lmx = __shfl(dist, ll, 64);
-        unsigned rn = __builtin_amdgcn_readfirstlane(s_node[w][l]);
-        float rm = s_max[w][l];
-        // runs strictly inside the tile are complete
-        if (lead && lane != fl && lane != ll) flush_b(nrec, node, dist);
-        if (fl == ll) {
-          if (fnode == rn) {
-            rm = fmaxf(rm, fmx);
-          } else {
-            if (rn != kNone) flush_b(nrec, rn, rm);
-            rn = fnode;
-            rm = fmx;
-          }
-        } else {
-          if (fnode == rn) {
-            flush_b(nrec, rn, fmaxf(rm, fmx));
-          } else {
-            if (rn != kNone) flush_b(nrec, rn, rm);
-            flush_b(nrec, fnode, fmx);
-          }
-          rn = lnode;
-          rm = lmx;
-        }
-        s_node[w][l] = rn;  // same value from every lane
-        s_max[w][l] = rm;
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) rr[u] = nrec[2 * (size_t)(nd[u] != kNone ? nd[u] : 0u)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int l = l0 - u;
+        if (l < 0) break;  // uniform
+        const float4 r = rr[u];
+        const float dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z;
+        const float dist = (nd[u] != kNone && r.w > 0.f) ? sqrtf(dx * dx + dy * dy + dz * dz) : 0.f;
+        radius_level(nrec, rc, w, l, nd[u], dist, base == c0);
       }
-      const unsigned up = up0 < nn ? up0 : kNone;  // the root's parent is kNone
-      node = part ? up : node;
-      lv = part ? (up != kNone ? lv - 1 : -1) : lv;
     }
   }
-  // carried runs of the last tile
+  // the carried runs may continue in the next chunk
   for (int l = 0; l < kMaxLevels; ++l) {
-    const unsigned rn = __builtin_amdgcn_readfirstlane(s_node[w][l]);
-    if (rn != kNone) flush_b(nrec, rn, s_max[w][l]);
+    const unsigned rn = __builtin_amdgcn_readfirstlane(rc.node[w][l]);
+    if (rn != kNone) put_b(nrec, rn, rc.max[w][l], true);
   }
+}
+
+void launch_ancestors(gothic_ctx *c, int64_t n, hipStream_t s) {
+  Buffers &B = c->b;
+  int64_t nb = (c->cap_nodes + 255) / 256;
+  int g = (int)(nb > 8192 ? 8192 : (nb < 1 ? 1 : nb));
+  hipLaunchKernelGGL(leaf_map_k, dim3(g), dim3(256), 0, s, B.ctl, n, B.first, B.count, B.n_child,
+                     B.leaf_of);
+  int64_t pb = (n + 255) / 256;
+  int gp = (int)(pb > 8192 ? 8192 : (pb < 1 ? 1 : pb));
+  hipLaunchKernelGGL(ancestors_k, dim3(gp), dim3(256), 0, s, B.ctl, n, B.leaf_of, B.parent,
+                     B.level, B.anc, B.leaflev);
 }
 
 // Critical distance of the multipole MAC of Warren & Salmon (Section 2.2) for
@@ -271,8 +357,8 @@ void launch_moments(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
   // about 1024 particles per wave chunk (more waves only for small n)
   int64_t pb = (n + 4095) / 4096;
   int gp = (int)(pb > 16384 ? 16384 : (pb < 1 ? 1 : pb));
-  hipLaunchKernelGGL(radius_k, dim3(gp), dim3(256), 0, s, B.ctl, n, B.pos, B.leaf_of, B.parent,
-                     B.level, B.nrec);
+  hipLaunchKernelGGL(radius_k, dim3(gp), dim3(256), 0, s, B.ctl, n, B.pos, B.anc, B.leaflev,
+                     B.nrec);
   if (c->prm.mac == 2)
     hipLaunchKernelGGL(mac_crit_k, dim3(g), dim3(256), 0, s, B.ctl, c->prm.mac_delta, B.nrec,
                        B.quad, B.mcrit);

@@ -37,7 +37,7 @@ def _oracle_on_old_tree(x_old, x_new, eps, theta, act, multipole, G=32, r_crit=-
     clean = cnt[:, 2] == 0
     rows = np.concatenate([grp["alist"][grp["first"][q]:grp["first"][q] + grp["count"][q]]
                            for q in np.flatnonzero(clean)])
-    return out, perm, rows, ks, tree
+    return out, perm, rows, ks, tree, mom
 
 
 @pytest.mark.parametrize("multipole", [1, 2])
@@ -61,11 +61,15 @@ def test_reused_tree_matches_the_oracle(multipole):
         ks, perm, _ = ctx.keys()
         keys.append(ks.copy())
         built_from = xs[0] if i < 3 else xs[3]
-        ref, perm_o, rows, ks_o, tree_o = _oracle_on_old_tree(built_from, x, eps, theta, act,
-                                                               multipole)
+        ref, perm_o, rows, ks_o, tree_o, mom_o = _oracle_on_old_tree(built_from, x, eps, theta,
+                                                                      act, multipole)
         assert np.array_equal(ks, ks_o) and np.array_equal(perm, perm_o), i
         t = ctx.tree()
         assert np.array_equal(t["first"], tree_o["first"]), i
+        # node radii of the (reused) tree at the current positions
+        _, b, _ = ctx.nodes()
+        scale = np.abs(mom_o[0][:, :3]).sum(1) + mom_o[1]
+        assert np.all(np.abs(b - mom_o[1]) <= 1e-5 * mom_o[1] + 2e-6 * scale), i
         e = rel_rms(o[perm_o[rows]], ref[rows])
         say(f"  evaluation {i} ({'new' if i in (0, 3) else 'reused'} tree): rms {e:.2e}")
         assert e <= 1e-5

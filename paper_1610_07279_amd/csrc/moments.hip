@@ -190,36 +190,67 @@ __device__ __forceinline__ void put_b(float4 *nrec, unsigned node, float v, bool
   }
 }
 
+// DPP lane moves within the wave (gfx9 encodings): row_shr:1,2,4,8 shift
+// inside each row of 16 lanes, row_bcast:15 / row_bcast:31 carry the last
+// lane of a row into the next row(s), wave_shr:1 shifts the whole wave by
+// one lane.  Lanes without a source read `old`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned dpp_move(unsigned v, unsigned old) {
+  return (unsigned)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+// inclusive max scan from lane 0 upward, restarted at lanes with head set:
+// the last lane of each run of lanes ends up with the run's maximum.
+// Values are non-negative floats, whose bit patterns order like the values.
+__device__ __forceinline__ unsigned seg_max_scan(unsigned v, unsigned head) {
+#define GOTHIC_SEG_STEP(ctrl, rows)                   \
+  {                                                   \
+    const unsigned ov = dpp_move<ctrl, rows>(v, 0u);  \
+    const unsigned oh = dpp_move<ctrl, rows>(head, 0u); \
+    v = head ? v : max(v, ov);                        \
+    head |= oh;                                       \
+  }
+  GOTHIC_SEG_STEP(0x111, 0xf)
+  GOTHIC_SEG_STEP(0x112, 0xf)
+  GOTHIC_SEG_STEP(0x114, 0xf)
+  GOTHIC_SEG_STEP(0x118, 0xf)
+  GOTHIC_SEG_STEP(0x142, 0xa)
+  GOTHIC_SEG_STEP(0x143, 0xc)
+#undef GOTHIC_SEG_STEP
+  return v;
+}
+
 // one level of one tile: lane holds (key = node or kNone, dist); at_start:
 // the tile is the first of the chunk
 __device__ __forceinline__ void radius_level(float4 *nrec, RadiusCarry &rc, int w, int l,
                                              unsigned key, float dist, bool at_start) {
   const int lane = lane_id();
   const bool part = key != kNone;
-  // segmented max over contiguous runs of equal key: the first lane of each
-  // run ends up with the run's maximum
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const float od = __shfl_down(dist, d, 64);
-    const unsigned ok = __shfl_down(key, d, 64);
-    dist = (lane + d < 64 && ok == key) ? fmaxf(dist, od) : dist;
-  }
-  const unsigned prev = __shfl_up(key, 1, 64);
-  const bool lead = part && (lane == 0 || prev != key);
-  const unsigned long long lm = __ballot(lead);
-  if (!lm) return;
-  const int fl = __builtin_amdgcn_readfirstlane(__ffsll((long long)lm) - 1);
-  const int ll = __builtin_amdgcn_readfirstlane(63 - __clzll((long long)lm));
-  const unsigned fnode = __builtin_amdgcn_readfirstlane(__shfl(key, fl, 64));
-  const unsigned lnode = __builtin_amdgcn_readfirstlane(__shfl(key, ll, 64));
-  const float fmx = __shfl(dist, fl, 64);
-  const float lmx = __shfl(dist, ll, 64);
+  // runs of equal key: heads from the previous lane's key, the run maximum
+  // at each run's last lane
+  const unsigned prev = dpp_move<0x138, 0xf>(key, ~key);
+  const unsigned next = __shfl_down(key, 1, 64);
+  const unsigned head = (lane == 0 || prev != key) ? 1u : 0u;
+  const float run_max = __uint_as_float(seg_max_scan(__float_as_uint(dist), head));
+  const bool tail = part && (lane == 63 || next != key);
+  const unsigned long long tm = __ballot(tail);
+  if (!tm) return;
+  const int fl = __builtin_amdgcn_readfirstlane(__ffsll((long long)tm) - 1);
+  const int ll = __builtin_amdgcn_readfirstlane(63 - __clzll((long long)tm));
+  const unsigned fnode = (unsigned)__builtin_amdgcn_readlane((int)key, fl);
+  const unsigned lnode = (unsigned)__builtin_amdgcn_readlane((int)key, ll);
+  const float fmx = __uint_as_float((unsigned)__builtin_amdgcn_readlane(
+      (int)__float_as_uint(run_max), fl));
+  const float lmx = __uint_as_float((unsigned)__builtin_amdgcn_readlane(
+      (int)__float_as_uint(run_max), ll));
+  // the first run reaches back to lane 0 iff lane 0 holds a particle of it
+  const bool first_open =
+      at_start && (unsigned)__builtin_amdgcn_readfirstlane((int)key) == fnode;
   unsigned rn = __builtin_amdgcn_readfirstlane(rc.node[w][l]);
   float rm = rc.max[w][l];
   bool ropen = __builtin_amdgcn_readfirstlane(rc.open[w][l]) != 0u;
   // runs strictly inside the tile are whole nodes
-  if (lead && lane != fl && lane != ll) nrec[2 * (size_t)key + 1].x = dist;
-  const bool first_open = at_start && fl == 0;  // may continue from the previous chunk
+  if (tail && lane != fl && lane != ll) nrec[2 * (size_t)key + 1].x = run_max;
   if (fl == ll) {
     if (fnode == rn) {
       rm = fmaxf(rm, fmx);

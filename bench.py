@@ -217,6 +217,168 @@ def cpu_baseline(x, eps, theta, multipole, group_size, n_leaf, r_crit, target_s=
                        f"tree preparation ({prep:.1f} s) not timed")
 
 
+def rel_error(tree, ref):
+    """|a_tree - a_direct| / |a_direct| per target (acceleration as a vector)."""
+    num = np.linalg.norm(tree[:, :3].astype(np.float64) - ref[:, :3], axis=1)
+    return num / np.linalg.norm(ref[:, :3], axis=1)
+
+
+def mac_sweep(args):
+    """Time per step against force accuracy for the three MACs (Fig. 3 of
+    Section 3.2): NFW sphere (r_s = 1, truncated at 5 r_s, seed 503), eps =
+    r_s/64, quadrupole nodes.  Accuracy: the relative error of the acceleration
+    vector of a random sample of particles (seed 504) against the float64 direct
+    sum of the library, 50th and 99th percentiles, at t = 0 with every particle
+    active (the acceleration MAC reads the accelerations of one opening-angle
+    evaluation, theta = 0.5, as the previous step's).  Time: seconds per finest
+    sub-step of the block and the shared scheme, as in the headline run.
+    Parameters: theta = 0.9 ... 0.1 and Delta = 2^-2 ... 2^-18 (even powers)
+    for the acceleration and the multipole MAC.  One JSON line per point."""
+    import torch
+
+    import ics
+    import paper_1610_07279_amd as g
+
+    n, eps, eta, kmax = args.n, 1.0 / 64, 0.1, 8
+    log(f"mac sweep: NFW N={n}, truncated at 5 r_s (seed 503), eps 1/64")
+    x, v = ics.nfw(n, seed=503, c=5.0, with_vel=True)
+    dev = torch.device("cuda", 0)
+    xd = torch.from_numpy(x).to(dev)
+    rng = np.random.default_rng(504)
+    idx = np.sort(rng.choice(n, size=min(args.sweep_sample, n), replace=False)).astype(np.int64)
+    it = torch.from_numpy(idx).to(dev)
+    t0 = time.perf_counter()
+    ref = g.Context(device=0).direct_forces(xd, eps, idx=it).cpu().numpy()
+    log(f"mac sweep: direct sum for {idx.size} targets in {time.perf_counter() - t0:.1f} s")
+    base = dict(multipole=2, group_size=args.group_size, list_depth=args.list_depth,
+                r_crit=args.r_crit, ball=args.ball, rebuild_interval=args.rebuild_interval)
+    prev = g.Context(device=0, **base).tree_forces(xd, eps, 0.5)
+    pos0 = torch.from_numpy(x[:, :3].astype(np.float64)).to(dev)
+    vel0 = torch.from_numpy(v).to(dev)
+    mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).to(dev)
+    points = [(0, 0.1 * k) for k in range(9, 0, -1)]
+    points += [(m, 2.0 ** -e) for m in (1, 2) for e in range(2, 19, 2)]
+    name = {0: "opening angle", 1: "acceleration", 2: "multipole"}
+    for mac, val in points:
+        theta = val if mac == 0 else 0.5
+        ctx = g.Context(device=0, mac=mac, mac_delta=val if mac else 2.0 ** -7, timing=1,
+                        graph=args.graph, **base)
+        acc = ctx.tree_forces(xd, eps, theta, acc_old=prev if mac == 1 else None)
+        e = rel_error(acc[it].cpu().numpy(), ref)
+        inter = ctx.stats()["interactions"]
+        blk = run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, False, args.steps,
+                      args.warmup)
+        shd = run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, True, args.steps,
+                      args.warmup)
+        row = {"mac": name[mac], "param": val, "err50": float(np.percentile(e, 50)),
+               "err99": float(np.percentile(e, 99)), "interactions_all_active": inter,
+               "block_s_per_step": blk["seconds"] / args.steps,
+               "shared_s_per_step": shd["seconds"] / args.steps,
+               "n": n, "sample": int(idx.size), "steps": args.steps}
+        log(f"mac sweep: {name[mac]:13s} {val:.3g}: err50 {row['err50']:.2e} err99 "
+            f"{row['err99']:.2e}  block {row['block_s_per_step'] * 1e3:.2f} ms  shared "
+            f"{row['shared_s_per_step'] * 1e3:.2f} ms")
+        print(json.dumps(row), flush=True)
+        del ctx
+        torch.cuda.empty_cache()
+
+
+def ball_sweep(args):
+    """The five enclosing balls of the pseudo i-particles (Appendix B, Fig. 10
+    and Table 3) on two particle distributions of N = 2^23 with every particle
+    active: the NFW sphere of the headline run (eps 1/512) and the
+    three-component galaxy (NFW halo, Hernquist bulge, exponential disk; a
+    stand-in for the M31 model, eps 1/512).  The groups do not depend on the
+    ball, so each group's radius is compared with its smallest enclosing ball
+    (SEB): percentiles of r_ball / r_SEB; plus the interactions and the walk
+    time of an evaluation with each ball.  The cost of each ball kernel is the
+    group_ball_k<kind> line of a kernel trace of this run.  One JSON line per
+    (model, ball)."""
+    import torch
+
+    import ics
+    import paper_1610_07279_amd as g
+
+    n, eps, theta = args.n, 1.0 / 512, 0.5
+    names = ["GEO", "SEB", "EBS", "COM", "CMP"]
+    models = [("NFW", lambda: ics.nfw(n, seed=501)), ("galaxy", lambda: ics.galaxy(n))]
+    for model, make in models:
+        log(f"ball sweep: {model} N={n}")
+        xd = torch.from_numpy(make()).to(torch.device("cuda", 0))
+        radii, firsts = {}, {}
+        for kind in (1, 0, 2, 3, 4):  # SEB first: the reference radius
+            ctx = g.Context(device=0, multipole=2, group_size=args.group_size,
+                            list_depth=args.list_depth, r_crit=args.r_crit, ball=kind, timing=1)
+            out = ctx.tree_forces(xd, eps, theta)
+            ctx.set_params(check=0)
+            ctx.walk_time()
+            for _ in range(args.steps):
+                ctx.tree_forces(xd, eps, theta, out=out)
+            torch.cuda.synchronize()
+            ms, k = ctx.walk_time()
+            st = ctx.stats()
+            grp = ctx.groups()
+            radii[kind], firsts[kind] = grp["ball"][:, 3].astype(np.float64), grp["first"]
+            if not np.array_equal(firsts[kind], firsts[1]):
+                raise RuntimeError("the groups changed with the ball kind")
+            seb = radii[1]
+            ok = seb > 0
+            q = radii[kind][ok] / seb[ok]
+            row = {"model": model, "ball": names[kind], "n": n, "groups": int(st["n_groups"]),
+                   "ratio_p50": float(np.percentile(q, 50)), "ratio_p90": float(np.percentile(q, 90)),
+                   "ratio_p99": float(np.percentile(q, 99)), "ratio_max": float(q.max()),
+                   "interactions": st["interactions"], "walk_ms": ms / max(k, 1)}
+            log(f"ball sweep: {model:6s} {names[kind]}: r/r_SEB p50 {row['ratio_p50']:.4f} p99 "
+                f"{row['ratio_p99']:.4f} max {row['ratio_max']:.4f}, interactions "
+                f"{row['interactions']:.4e}, walk {row['walk_ms']:.2f} ms")
+            print(json.dumps(row), flush=True)
+            del ctx
+        del xd
+        torch.cuda.empty_cache()
+
+
+def n_sweep(args):
+    """Time per step against the number of particles (Fig. 8 of Section 3.4):
+    the NFW sphere of the headline run (c = 10, seed 501; the paper shows the
+    M31 model and quotes the NFW sphere at 2^23 and 2^24), eps 1/512, the
+    acceleration MAC with Delta = 2^-7, quadrupole nodes, block
+    steps on 8 levels, at N = 2^10, 2^12, ..., 2^24 (or the one N of --n);
+    seconds per finest sub-step of the block and the shared scheme and the part
+    spent in the walk kernel (HIP events).  The split over the other functions
+    comes from a kernel trace of a run at one N.  One JSON line per N."""
+    import torch
+
+    import ics
+    import paper_1610_07279_amd as g
+
+    eps, eta, kmax = 1.0 / 512, 0.1, 8
+    dev = torch.device("cuda", 0)
+    sizes = [args.n] if "--n" in sys.argv else [1 << lg for lg in range(10, 25, 2)]
+    for n in sizes:
+        x, v = ics.nfw(n, seed=501, with_vel=True)
+        pos0 = torch.from_numpy(x[:, :3].astype(np.float64)).to(dev)
+        vel0 = torch.from_numpy(v).to(dev)
+        mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).to(dev)
+        ctx = g.Context(device=0, multipole=2, group_size=args.group_size,
+                        list_depth=args.list_depth, r_crit=args.r_crit, timing=1,
+                        graph=args.graph, rebuild_interval=args.rebuild_interval, ball=args.ball,
+                        mac=1, mac_delta=2.0 ** -7)
+        row = {"n": n, "steps": args.steps, "model": "NFW", "mac": "acceleration 2^-7"}
+        for mode, shared in (("block", False), ("shared", True)):
+            r = run_sim(ctx, pos0, vel0, mass, eps, 0.5, eta, kmax, shared, args.steps,
+                        args.warmup)
+            row[f"{mode}_s_per_step"] = r["seconds"] / args.steps
+            row[f"{mode}_walk_s_per_step"] = r["walk_ms"] / 1e3 / args.steps
+            row[f"{mode}_interactions_per_s"] = r["info"]["interactions_total"] / r["seconds"]
+            row[f"{mode}_tree_builds"] = r["info"]["tree_builds"]
+        log(f"n sweep: N={n}: block {row['block_s_per_step'] * 1e3:.3f} ms (walk "
+            f"{row['block_walk_s_per_step'] * 1e3:.3f}), shared {row['shared_s_per_step'] * 1e3:.3f}"
+            f" ms (walk {row['shared_walk_s_per_step'] * 1e3:.3f})")
+        print(json.dumps(row), flush=True)
+        del ctx, pos0, vel0, mass
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,7 +408,18 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profile to bytes) and exit")
+    ap.add_argument("--sweep", choices=("mac", "ball", "n"), default=None,
+                    help="mac: time per step against force accuracy for the three MACs; "
+                         "ball: the five enclosing balls (both at N = 2^23 unless --n is "
+                         "given); n: time per step for N = 2^10 ... 2^24; then exit")
+    ap.add_argument("--sweep-sample", type=int, default=1 << 14,
+                    help="particles whose force error a sweep measures")
     args = ap.parse_args()
+    if args.sweep:
+        if "--n" not in sys.argv:
+            args.n = 1 << 23
+        {"mac": mac_sweep, "ball": ball_sweep, "n": n_sweep}[args.sweep](args)
+        return
     if args.copy_calibration:
         import torch
         nb = args.copy_calibration

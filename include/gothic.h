@@ -98,7 +98,9 @@ typedef struct {
                          its best point (the perturbation that follows a
                          drifting optimum).  One search per class of
                          sub-steps with the same due levels.  Synchronises on
-                         the previous sub-step's walk (default 0) */
+                         the previous sub-step's walk.  2: as 1, after first
+                         picking the group size of each class by timing
+                         (gothic_sim_set_group_sizes) (default 0) */
   int rebuild_interval; /* tree reuse (Section 2.6): 1 = build a new tree for
                          every evaluation (default); k > 1 = build one every
                          k evaluations and walk the last one in between, with
@@ -234,6 +236,29 @@ typedef struct {
 } gothic_tune_result;
 
 /*
+ * Softened direct summation in float64 (Section 1: the Plummer-softened
+ * acceleration and potential with G = 1, as the tree force approximates
+ * them), the reference that the accuracy of the tree force is measured
+ * against (Section 3.2, Fig. 3).  Independent of the tree: every pair is summed.
+ *   n        particles, 1 <= n < 2^31 (with ni = 0 any n in [0, 2^31))
+ *   xyzm     [n][4] float DEVICE: x, y, z, m of every j-particle
+ *   eps      Plummer softening length, finite and > 0
+ *   ni       targets, 0 <= ni < 2^31
+ *   idx      [ni] int64 DEVICE: the particle of each target; NULL = targets
+ *            0 .. ni-1 (then ni <= n).  An index outside [0, n) gives a NaN row.
+ *   acc_pot  [ni][4] double DEVICE out: ax, ay, az, phi of each target; the
+ *            pair j = idx[k] is left out (another particle at the same
+ *            position adds no force and -m/eps to phi)
+ * Every target costs n pair terms; the j-particles are split into chunks whose
+ * float64 partials are added in a fixed order, so the result is the same on
+ * every call.  The partials live in context scratch of (chunks x ni) x 32
+ * bytes, grown on demand (ECAPTURE when it would grow inside stream capture).
+ * Returns GOTHIC_OK, EINVAL, ENOMEM or EDEVICE.
+ */
+int gothic_direct_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, int64_t ni,
+                         const int64_t *idx, double *acc_pot, void *stream);
+
+/*
  * Timed search for the fastest tunables of one workload (Section 2.4 tunes
  * r_crit by Brent's method on the measured time; here the group size G and
  * the list budget are searched as well): every G in {8, 16, 32, 64} with
@@ -313,12 +338,23 @@ int gothic_sim_get_state(gothic_ctx *c, float *acc_pot, uint8_t *levels, int64_t
 /* dt_fine and dt_max of every bound system: HOST double arrays of nsys
  * entries (gothic_sim_info reports system 0).  Synchronises. */
 int gothic_sim_get_steps(gothic_ctx *c, int nsys, double *dt_fine, double *dt_max);
-/* Online r_crit tuning (params.autotune): for each sub-step class c =
- * 0..nclass-1 (class c = sub-steps whose index has its lowest set bit at c,
- * capped at kmax), the best r_crit of the last finished search (0 if none
- * finished yet) and the number of finished searches.  HOST arrays; either
- * may be NULL. */
-int gothic_sim_get_tuning(gothic_ctx *c, int nclass, float *r_crit_best, int *searches);
+/* Online tuning (params.autotune): for each sub-step class c = 0..nclass-1
+ * (class c = sub-steps whose index has its lowest set bit at c, capped at
+ * kmax), the best r_crit of the last finished search (0 if none finished
+ * yet), the number of finished searches, and the group size the class walks
+ * with now (params.group_size until a size is fixed or picked).  HOST
+ * arrays; any may be NULL.  0 <= nclass <= 32. */
+int gothic_sim_get_tuning(gothic_ctx *c, int nclass, float *r_crit_best, int *searches,
+                          int *group_size);
+/* Group size per sub-step class (Section 4 names choosing the number of
+ * threads per i-particle, S, for each step as future work; a wave holds G
+ * i-particles with S = 64 / G lanes each, so this chooses S per class).
+ * group_size: HOST int [nclass], each 0 (params.group_size) or a power of
+ * two in 1..64; classes >= nclass keep their setting.  params.autotune = 2
+ * picks the size of each class whose entry is 0 by timing G = 8, 16, 32, 64
+ * on its first sub-steps.  The binding of a system (gothic_sim_bind*) clears
+ * the table.  Returns EINVAL for a bad size (nothing is changed). */
+int gothic_sim_set_group_sizes(gothic_ctx *c, int nclass, const int *group_size);
 
 /* Counts of the last evaluation; synchronises the stream of that call. */
 int gothic_get_stats(gothic_ctx *c, gothic_stats *out);

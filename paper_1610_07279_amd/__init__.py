@@ -86,6 +86,7 @@ def _load():
     lib.gothic_tree_forces.argtypes = [P, i64, P, f32, f32, P, P, P]
     lib.gothic_tree_forces_batched.argtypes = [P, i32, P, P, P, P, P, P, P]
     lib.gothic_tree_forces_ex.argtypes = [P, i32, P, P, P, P, P, P, P, P]
+    lib.gothic_direct_forces.argtypes = [P, i64, P, f32, i64, P, P, P]
     lib.gothic_get_stats.argtypes = [P, C.POINTER(Stats)]
     lib.gothic_get_keys.argtypes = [P, P, P, P]
     lib.gothic_get_tree.argtypes = [P, P, P, P, P, P]
@@ -95,7 +96,8 @@ def _load():
     lib.gothic_sim_bind.argtypes = [P, i64, P, P, P, f32, f32, C.c_double, i32, i32, P]
     lib.gothic_sim_bind_batched.argtypes = [P, i32, P, P, P, P, P, P, C.c_double, i32, i32, P]
     lib.gothic_sim_get_steps.argtypes = [P, i32, P, P]
-    lib.gothic_sim_get_tuning.argtypes = [P, i32, P, P]
+    lib.gothic_sim_get_tuning.argtypes = [P, i32, P, P, P]
+    lib.gothic_sim_set_group_sizes.argtypes = [P, i32, P]
     lib.gothic_autotune.argtypes = [P, i32, P, P, P, P, P, P, C.POINTER(TuneResult), P]
     lib.gothic_sim_step.argtypes = [P, P]
     lib.gothic_sim_reset_counters.argtypes = [P, P]
@@ -226,6 +228,30 @@ class Context:
                                             stream=stream, acc_old=acc_old)
         return out
 
+    def direct_forces(self, xyzm, eps: float, idx=None, out=None, stream=None):
+        """float64 [ni,4] (ax, ay, az, phi) by direct summation over all of
+        xyzm for the targets idx (int64 GPU tensor; None = every particle)."""
+        import torch
+        if xyzm.dtype != torch.float32 or xyzm.dim() != 2 or xyzm.shape[1] != 4:
+            raise ValueError("xyzm must be a float32 [n,4] tensor")
+        if not xyzm.is_cuda or not xyzm.is_contiguous():
+            raise ValueError("xyzm must be a contiguous GPU tensor")
+        n = xyzm.shape[0]
+        if idx is not None:
+            if idx.dtype != torch.int64 or idx.dim() != 1 or not idx.is_cuda \
+                    or not idx.is_contiguous():
+                raise ValueError("idx must be a contiguous int64 [ni] GPU tensor")
+        ni = n if idx is None else idx.shape[0]
+        if out is None:
+            out = torch.empty((ni, 4), dtype=torch.float64, device=xyzm.device)
+        elif out.dtype != torch.float64 or out.shape != (ni, 4) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 [ni,4] tensor")
+        s = _stream_of(xyzm, stream)
+        self._last_stream = s
+        _check(lib.gothic_direct_forces(self._h, n, _ptr(xyzm), float(eps), ni, _ptr(idx),
+                                        _ptr(out), s))
+        return out
+
     @staticmethod
     def _systems(offsets, eps, theta):
         import numpy as np
@@ -344,15 +370,23 @@ class Context:
                                         m.ctypes.data_as(C.c_void_p)))
         return f, m
 
-    def sim_tuning(self, nclass: int = 32):
-        """(best r_crit per sub-step class [nclass] float32, finished searches [nclass])
-        of the online tuner (params.autotune)."""
+    def sim_tuning(self, nclass: int = 32, with_groups: bool = False):
+        """(best r_crit per sub-step class [nclass] float32, finished searches [nclass]
+        [, group size per class [nclass]]) of the online tuner (params.autotune)."""
         import numpy as np
         r = np.zeros(nclass, np.float32)
         k = np.zeros(nclass, np.int32)
+        gs = np.zeros(nclass, np.int32)
         _check(lib.gothic_sim_get_tuning(self._h, nclass, r.ctypes.data_as(C.c_void_p),
-                                         k.ctypes.data_as(C.c_void_p)))
-        return r, k
+                                         k.ctypes.data_as(C.c_void_p),
+                                         gs.ctypes.data_as(C.c_void_p)))
+        return (r, k, gs) if with_groups else (r, k)
+
+    def sim_set_group_sizes(self, sizes):
+        """Group size per sub-step class (0 = params.group_size)."""
+        import numpy as np
+        g = np.ascontiguousarray(sizes, dtype=np.int32)
+        _check(lib.gothic_sim_set_group_sizes(self._h, g.size, g.ctypes.data_as(C.c_void_p)))
 
     def sim_step(self, nsteps: int = 1, stream=None):
         s = _stream_of(self._sim_keep[0], stream)

@@ -158,8 +158,8 @@ static int validate_params(const gothic_params *p) {
   if (p->timing != 0 && p->timing != 1) return set_error(GOTHIC_EINVAL, "timing must be 0 or 1");
   if (!std::isfinite(p->r_crit)) return set_error(GOTHIC_EINVAL, "r_crit must be finite");
   if (p->graph != 0 && p->graph != 1) return set_error(GOTHIC_EINVAL, "graph must be 0 or 1");
-  if (p->autotune != 0 && p->autotune != 1)
-    return set_error(GOTHIC_EINVAL, "autotune must be 0 or 1");
+  if (p->autotune < 0 || p->autotune > 2)
+    return set_error(GOTHIC_EINVAL, "autotune must be 0, 1 or 2");
   if (p->rebuild_interval < 0 || p->rebuild_interval > (1 << 20))
     return set_error(GOTHIC_EINVAL, "rebuild_interval must be in 0..2^20");
   if (p->mac < 0 || p->mac > 2) return set_error(GOTHIC_EINVAL, "mac must be 0, 1 or 2");
@@ -400,6 +400,12 @@ static void free_graphs(gothic_ctx *c) {
       (void)hipGraphExecDestroy(e);
       e = nullptr;
     }
+  for (auto &pair : G.exec_g)
+    for (auto &e : pair)
+      if (e) {
+        (void)hipGraphExecDestroy(e);
+        e = nullptr;
+      }
   G.valid = false;
 }
 
@@ -473,6 +479,7 @@ static int meter_prepare(gothic_ctx *c) {
   if (!R.mk1 && (rc = hip_check(hipEventCreate(&R.mk1), "hipEventCreate"))) return rc;
   if (!T.ready) {
     for (auto &t : T.cls) t.init(-12.0, 0.0, 0.25, 20);
+    for (auto &g : T.pick) g.init(2);
     T.ready = true;
     T.pending = -1;
   }
@@ -494,7 +501,12 @@ static int meter_collect(gothic_ctx *c, int kmax) {
   if ((rc = hip_check(hipEventSynchronize(T.ev1), "hipEventSynchronize"))) return rc;
   float walk = 0.f;
   if ((rc = hip_check(hipEventElapsedTime(&walk, T.ev0, T.ev1), "hipEventElapsedTime"))) return rc;
-  if (T.pending_tuned) T.cls[k].observe((double)walk);
+  if (T.pending_pick) {
+    T.pick[k].observe((double)walk);
+    if (T.pick[k].decided()) T.class_G[k] = T.pick[k].current();
+  } else if (T.pending_tuned) {
+    T.cls[k].observe((double)walk);
+  }
   if (c->prm.rebuild_interval == 0) {
     if (T.pending_rebuilt) {
       float make = 0.f;
@@ -524,17 +536,20 @@ static int meter_collect(gothic_ctx *c, int kmax) {
 }
 
 // note the evaluation just enqueued for the next collection
-static void meter_mark(gothic_ctx *c, int k, bool rebuilt, bool tuned) {
+static void meter_mark(gothic_ctx *c, int k, bool rebuilt, bool tuned, bool picked) {
   TuneState &T = c->tune;
   T.pending = k;
   T.pending_rebuilt = rebuilt;
   T.pending_tuned = tuned;
+  T.pending_pick = picked;
 }
 
 static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const uint8_t *active,
                       const float4 *acc_old, float4 *o4, hipStream_t s, float r_crit,
-                      int meter_class = 0, bool tuned = false, int kmax = 0) {
+                      int meter_class = 0, bool tuned = false, int kmax = 0, int group_G = 0,
+                      bool picked = false) {
   const int64_t n = sy.n;
+  c->cur_G = group_G > 0 ? group_G : c->prm.group_size;
   if (c->prm.mac == 1 && !acc_old)
     return set_error(GOTHIC_EINVAL,
                      "the acceleration MAC needs the previous accelerations (gothic_tree_forces_ex)");
@@ -597,7 +612,7 @@ static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const 
     if ((rc = ensure(c, n, sy.nsys, nodes, spill))) return rc;
     rebuild = true;  // the grown buffers hold no tree
   }
-  if (meter) meter_mark(c, meter_class, rebuild, tuned);
+  if (meter) meter_mark(c, meter_class, rebuild, tuned, picked);
   return GOTHIC_OK;
 }
 
@@ -667,6 +682,7 @@ int gothic_destroy(gothic_ctx *c) {
     free_sim(c);
     free_events(c);
     free_all(c);
+    if (c->direct_part) (void)hipFree(c->direct_part);
   }
   delete c;
   return GOTHIC_OK;
@@ -746,6 +762,40 @@ int gothic_tree_forces_ex(gothic_ctx *c, int nsys, const int64_t *offsets, const
   return run_forces(c, sy, reinterpret_cast<const float4 *>(xyzm), active,
                     reinterpret_cast<const float4 *>(acc_old), reinterpret_cast<float4 *>(acc_pot),
                     reinterpret_cast<hipStream_t>(stream), c->prm.r_crit);
+}
+
+int gothic_direct_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, int64_t ni,
+                         const int64_t *idx, double *acc_pot, void *stream) {
+  if (!c) return set_error(GOTHIC_EINVAL, "context is NULL");
+  if (n < 0 || n >= (int64_t)1 << 31) return set_error(GOTHIC_EINVAL, "n must be in [0, 2^31)");
+  if (!(eps > 0.f) || !std::isfinite(eps)) return set_error(GOTHIC_EINVAL, "eps must be finite and > 0");
+  if (ni < 0 || ni >= (int64_t)1 << 31) return set_error(GOTHIC_EINVAL, "ni must be in [0, 2^31)");
+  if (ni == 0) return GOTHIC_OK;
+  if (n == 0) return set_error(GOTHIC_EINVAL, "targets need particles (n = 0)");
+  if (!idx && ni > n) return set_error(GOTHIC_EINVAL, "without idx, ni must be <= n");
+  if (!xyzm || !acc_pot) return set_error(GOTHIC_EINVAL, "xyzm and acc_pot must not be NULL");
+  DeviceGuard guard(c->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int nchunk;
+  int64_t chunk;
+  direct_plan(n, ni, &nchunk, &chunk);
+  const int64_t want = (int64_t)nchunk * ni;
+  int rc;
+  if (want > c->cap_direct) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    (void)hipStreamIsCapturing(s, &cap);
+    if (cap != hipStreamCaptureStatusNone)
+      return set_error(GOTHIC_ECAPTURE, "direct-sum scratch must grow; call once uncaptured first");
+    if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
+    if ((rc = dev_alloc(&c->direct_part, want))) {
+      c->cap_direct = 0;
+      return rc;
+    }
+    c->cap_direct = want;
+  }
+  launch_direct(n, reinterpret_cast<const float4 *>(xyzm), (double)eps, ni, idx, c->direct_part,
+                acc_pot, s);
+  return hip_check(hipGetLastError(), "direct-sum launch");
 }
 
 int gothic_get_stats(gothic_ctx *c, gothic_stats *out) {
@@ -922,6 +972,7 @@ static int sim_bind_impl(gothic_ctx *c, const Systems &sy, double *pos, double *
   S.kmax = kmax;
   c->tune.ready = false;
   c->tune.pending = -1;
+  for (int &g : c->tune.class_G) g = 0;
   {  // a new system: no tree to reuse, no growth history (the events stay)
     hipEvent_t m0 = c->tree.mk0, m1 = c->tree.mk1;
     c->tree = TreeState();
@@ -1003,6 +1054,39 @@ static Systems sim_systems(const SimState &S) {
 
 // Capture the segments of a sub-step on the context's own stream; buffers
 // are already sized by the bind.
+// capture one segment of a sub-step on the context's capture stream
+static int capture_segment(gothic_ctx *c, int seg, hipGraphExec_t *out) {
+  SimGraphs &G = c->graphs;
+  SimState &S = c->sim;
+  const Systems sy = sim_systems(S);
+  hipGraph_t g = nullptr;
+  int rc;
+  if ((rc = hip_check(hipStreamBeginCapture(G.cap_stream, hipStreamCaptureModeThreadLocal),
+                      "hipStreamBeginCapture")))
+    return rc;
+  switch (seg) {
+    case 0:
+      sim_launch_predict(c, G.cap_stream);
+      enqueue_upload(c, sy, G.cap_stream);
+      break;
+    case 1: enqueue_make(c, sy, S.shadow, G.cap_stream); break;
+    case 2: enqueue_post(c, sy, S.shadow, S.act, S.aold, G.cap_stream); break;
+    case 3: enqueue_walk(c, sy.n, S.anew, G.cap_stream, false); break;
+    default: sim_launch_correct(c, G.cap_stream); break;
+  }
+  const int lrc = hip_check(hipGetLastError(), "kernel launch");
+  rc = hip_check(hipStreamEndCapture(G.cap_stream, &g), "hipStreamEndCapture");
+  if (lrc || rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return lrc ? lrc : rc;
+  }
+  rc = hip_check(hipGraphInstantiate(out, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+  (void)hipGraphDestroy(g);
+  return rc;
+}
+
+// the segments that do not depend on the group size (predict, tree, correct);
+// those that do are captured per group size by capture_groups
 static int capture_step(gothic_ctx *c) {
   SimGraphs &G = c->graphs;
   SimState &S = c->sim;
@@ -1016,31 +1100,8 @@ static int capture_step(gothic_ctx *c) {
   if (sy.n > c->cap_n || sy.nsys > c->cap_sys || nodes_wanted(c, sy.n, sy.nsys) > c->cap_nodes ||
       walk_slots(c) != c->walk_waves)
     return set_error(GOTHIC_ECAPTURE, "scratch is not sized for this system; bind again");
-  for (int seg = 0; seg < kSegments; ++seg) {
-    hipGraph_t g = nullptr;
-    if ((rc = hip_check(hipStreamBeginCapture(G.cap_stream, hipStreamCaptureModeThreadLocal),
-                        "hipStreamBeginCapture")))
-      return rc;
-    switch (seg) {
-      case 0:
-        sim_launch_predict(c, G.cap_stream);
-        enqueue_upload(c, sy, G.cap_stream);
-        break;
-      case 1: enqueue_make(c, sy, S.shadow, G.cap_stream); break;
-      case 2: enqueue_post(c, sy, S.shadow, S.act, S.aold, G.cap_stream); break;
-      case 3: enqueue_walk(c, sy.n, S.anew, G.cap_stream, false); break;
-      default: sim_launch_correct(c, G.cap_stream); break;
-    }
-    const int lrc = hip_check(hipGetLastError(), "kernel launch");
-    rc = hip_check(hipStreamEndCapture(G.cap_stream, &g), "hipStreamEndCapture");
-    if (lrc || rc) {
-      if (g) (void)hipGraphDestroy(g);
-      free_graphs(c);
-      return lrc ? lrc : rc;
-    }
-    rc = hip_check(hipGraphInstantiate(&G.exec[seg], g, nullptr, nullptr, 0), "hipGraphInstantiate");
-    (void)hipGraphDestroy(g);
-    if (rc) {
+  for (int seg : {0, 1, 4}) {
+    if ((rc = capture_segment(c, seg, &G.exec[seg]))) {
       free_graphs(c);
       return rc;
     }
@@ -1048,6 +1109,25 @@ static int capture_step(gothic_ctx *c) {
   G.generation = c->generation;
   G.valid = true;
   return GOTHIC_OK;
+}
+
+// groups + moments and walk segments for group size G = 2^lg
+static int capture_groups(gothic_ctx *c, int lg) {
+  SimGraphs &G = c->graphs;
+  c->cur_G = 1 << lg;
+  int rc;
+  for (int k = 0; k < 2; ++k)
+    if ((rc = capture_segment(c, 2 + k, &G.exec_g[lg][k]))) {
+      free_graphs(c);
+      return rc;
+    }
+  return GOTHIC_OK;
+}
+
+static int log2_of(int G) {
+  int lg = 0;
+  while ((1 << lg) < G) ++lg;
+  return lg;
 }
 
 int gothic_sim_step(gothic_ctx *c, void *stream) {
@@ -1063,14 +1143,25 @@ int gothic_sim_step(gothic_ctx *c, void *stream) {
   int cls = __builtin_ctzll(snext);
   if (cls > S.kmax) cls = S.kmax;
   float r_crit = c->prm.r_crit;
-  if (c->prm.autotune) {
-    if ((rc = meter_prepare(c))) return rc;
-    r_crit = -(float)std::exp2(T.cls[cls].current());
+  // group size of the class: fixed by gothic_sim_set_group_sizes or a
+  // finished pick, else (autotune = 2) the candidate being timed
+  int gsize = c->prm.group_size;
+  bool picking = false;
+  if (c->prm.autotune && (rc = meter_prepare(c))) return rc;
+  if (T.class_G[cls] > 0) {
+    gsize = T.class_G[cls];
+  } else if (c->prm.autotune == 2) {
+    gsize = T.pick[cls].current();
+    picking = true;
   }
+  const bool tuning = c->prm.autotune != 0 && !picking;
+  if (tuning) r_crit = -(float)std::exp2(T.cls[cls].current());
   if (c->prm.graph && !c->prm.check) {
     if ((rc = ensure_events(c))) return rc;
     if (!c->graphs.valid || c->graphs.generation != c->generation)
       if ((rc = capture_step(c))) return rc;
+    const int lg = log2_of(gsize);
+    if (!c->graphs.exec_g[lg][0] && (rc = capture_groups(c, lg))) return rc;
     const Systems sy = sim_systems(S);
     const bool meter = metering(c);
     if (meter && ((rc = meter_prepare(c)) || (rc = meter_collect(c, S.kmax)))) return rc;
@@ -1089,21 +1180,21 @@ int gothic_sim_step(gothic_ctx *c, void *stream) {
       if ((rc = hip_check(hipGraphLaunch(G.exec[1], s), "hipGraphLaunch"))) return rc;
       if (meter) (void)hipEventRecord(c->tree.mk1, s);
     }
-    if ((rc = hip_check(hipGraphLaunch(G.exec[2], s), "hipGraphLaunch"))) return rc;
+    if ((rc = hip_check(hipGraphLaunch(G.exec_g[lg][0], s), "hipGraphLaunch"))) return rc;
     const bool timed = c->prm.timing && c->ev_used < (int)c->ev_start.size();
     if (meter) (void)hipEventRecord(T.ev0, s);
     if (timed) (void)hipEventRecord(c->ev_start[c->ev_used], s);
-    if ((rc = hip_check(hipGraphLaunch(G.exec[3], s), "hipGraphLaunch"))) return rc;
+    if ((rc = hip_check(hipGraphLaunch(G.exec_g[lg][1], s), "hipGraphLaunch"))) return rc;
     if (timed) (void)hipEventRecord(c->ev_stop[c->ev_used++], s);
     if (meter) (void)hipEventRecord(T.ev1, s);
     if ((rc = hip_check(hipGraphLaunch(G.exec[4], s), "hipGraphLaunch"))) return rc;
     tree_used(c, sy, rebuild);
     if (rebuild) ++S.builds;
-    if (meter) meter_mark(c, cls, rebuild, c->prm.autotune != 0);
+    if (meter) meter_mark(c, cls, rebuild, tuning, picking);
   } else {
     sim_launch_predict(c, s);
-    rc = run_forces(c, sim_systems(S), S.shadow, S.act, S.aold, S.anew, s, r_crit, cls,
-                    c->prm.autotune != 0, S.kmax);
+    rc = run_forces(c, sim_systems(S), S.shadow, S.act, S.aold, S.anew, s, r_crit, cls, tuning,
+                    S.kmax, gsize, picking);
     if (rc) return rc;
     if (c->tree.since == 1) ++S.builds;
     sim_launch_correct(c, s);
@@ -1113,7 +1204,8 @@ int gothic_sim_step(gothic_ctx *c, void *stream) {
   return GOTHIC_OK;
 }
 
-int gothic_sim_get_tuning(gothic_ctx *c, int nclass, float *r_crit_best, int *searches) {
+int gothic_sim_get_tuning(gothic_ctx *c, int nclass, float *r_crit_best, int *searches,
+                          int *group_size) {
   if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
   if (nclass < 0 || nclass > kTuneClasses)
     return set_error(GOTHIC_EINVAL, "nclass must be in 0..32");
@@ -1122,7 +1214,22 @@ int gothic_sim_get_tuning(gothic_ctx *c, int nclass, float *r_crit_best, int *se
     const bool have = T.ready && T.cls[k].have_best;
     if (r_crit_best) r_crit_best[k] = have ? -(float)std::exp2(T.cls[k].best) : 0.f;
     if (searches) searches[k] = T.ready ? T.cls[k].searches : 0;
+    if (group_size) group_size[k] = T.class_G[k] > 0 ? T.class_G[k] : c->prm.group_size;
   }
+  return GOTHIC_OK;
+}
+
+int gothic_sim_set_group_sizes(gothic_ctx *c, int nclass, const int *group_size) {
+  if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
+  if (nclass < 0 || nclass > kTuneClasses)
+    return set_error(GOTHIC_EINVAL, "nclass must be in 0..32");
+  if (nclass > 0 && !group_size) return set_error(GOTHIC_EINVAL, "group_size must not be NULL");
+  for (int k = 0; k < nclass; ++k) {
+    const int G = group_size[k];
+    if (G != 0 && (G < 1 || G > 64 || (G & (G - 1))))
+      return set_error(GOTHIC_EINVAL, "group sizes must be 0 or a power of two in 1..64");
+  }
+  for (int k = 0; k < nclass; ++k) c->tune.class_G[k] = group_size[k];
   return GOTHIC_OK;
 }
 
@@ -1135,6 +1242,7 @@ static int timed_eval(gothic_ctx *c, const Systems &sy, const float4 *x4, const 
   int rc;
   if ((rc = ensure(c, sy.n, sy.nsys, nodes_wanted(c, sy.n, sy.nsys), c->spill_per_wave)))
     return rc;
+  c->cur_G = c->prm.group_size;
   (void)hipEventRecord(T.ev0, s);
   if ((rc = enqueue_forces(c, sy, x4, act, nullptr, o4, s, r_crit, true))) return rc;
   (void)hipEventRecord(T.ev1, s);

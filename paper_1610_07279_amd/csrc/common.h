@@ -150,8 +150,12 @@ struct SimState {
 // them (control block, r_crit) and the events timing the construction and
 // the walk are launched outside.
 constexpr int kSegments = 5;
+constexpr int kGroupSizes = 7;  // G = 1, 2, 4, ..., 64
 struct SimGraphs {
+  // segments 0 (predict), 1 (tree) and 4 (correct); 2 and 3 (groups, walk)
+  // depend on the group size and live in exec_g[log2 G], captured on demand
   hipGraphExec_t exec[kSegments] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t exec_g[kGroupSizes][2] = {};
   hipStream_t cap_stream = nullptr;
   uint64_t generation = 0;
   bool valid = false;
@@ -184,6 +188,9 @@ struct TuneState {
   int pending = -1;                          // its class, or -1
   bool pending_rebuilt = false;              // ... whether it built its tree
   bool pending_tuned = false;                // ... whether its r_crit came from cls[]
+  bool pending_pick = false;                 // ... whether its G came from pick[]
+  GroupPicker pick[kTuneClasses];            // params.autotune = 2: G per class
+  int class_G[kTuneClasses] = {};            // group size per class (0: params.group_size)
   bool recording = false;                    // record ev0 / ev1 around the next walk
   // gothic_autotune results by (batched, log2 n, log2 of n / n_active, multipole)
   std::map<std::tuple<int, int, int, int>, gothic_tune_result> cache;
@@ -197,7 +204,10 @@ struct gothic_ctx {
   gothic_params prm{};
   int64_t cap_n = 0, cap_nodes = 0, cap_groups = 0, cap_hist = 0, cap_sys = 0, cap_anc = 0;
   int64_t spill_per_wave = 0;
-  int walk_waves = 0;             // persistent walk waves (slots)
+  int walk_waves = 0;             // persistent walk waves (slots), the most any G launches
+  int slots_g[gothic::kGroupSizes] = {};  // walk waves per log2 G for slots_multi / slots_D
+  int slots_multi = 0, slots_D = 0;
+  int cur_G = 32;                 // group size of the evaluation being enqueued
   gothic::Buffers b;
   uint64_t generation = 1;        // bumped whenever a device buffer or a parameter changes
   uint64_t buffers = 1;           // bumped whenever a device buffer is (re)allocated
@@ -213,6 +223,9 @@ struct gothic_ctx {
   gothic::SimGraphs graphs;
   gothic::TuneState tune;
   gothic::TreeState tree;
+  // float64 partials of the direct summation (gothic_direct_forces)
+  double4 *direct_part = nullptr;
+  int64_t cap_direct = 0;
 };
 
 namespace gothic {
@@ -228,6 +241,11 @@ void scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n_host, const uns
                     const unsigned *lo_dev, int64_t n_max, unsigned *total_dev, uint32_t *part,
                     hipStream_t s);
 int scan_blocks();
+
+// direct.hip: float64 direct sum for ni targets; part holds nchunk * ni partials
+void direct_plan(int64_t n, int64_t ni, int *nchunk, int64_t *chunk);
+void launch_direct(int64_t n, const float4 *xyzm, double eps, int64_t ni, const int64_t *idx,
+                   double4 *part, double *out, hipStream_t s);
 
 // keys.hip (nsys systems, the largest holding max_n particles)
 void launch_bbox_keys(gothic_ctx *c, const float4 *xyzm, int64_t n, int nsys, int64_t max_n,

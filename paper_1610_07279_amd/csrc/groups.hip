@@ -277,8 +277,10 @@ __device__ __forceinline__ float ball_radius(float4 p, float cx, float cy, float
 
 // one wave per group; loop control is wave-uniform and the member load is
 // predicated (lanes past the group's end re-read its first member)
+// (one instantiation per ball kind, so that a kernel trace times each kind)
+template <int kind>
 __global__ void __launch_bounds__(256)
-group_ball_k(int64_t n, int kind, const Ctl *__restrict__ ctl, const uint32_t *__restrict__ alist,
+group_ball_k(int64_t n, const Ctl *__restrict__ ctl, const uint32_t *__restrict__ alist,
              const uint32_t *__restrict__ gfirst, const float4 *__restrict__ pos,
              float4 *__restrict__ ball, const float *__restrict__ amag,
              float *__restrict__ gamin) {
@@ -350,7 +352,7 @@ void launch_groups(gothic_ctx *c, int64_t n, hipStream_t s) {
   scan_exclusive(B.flag, B.flag2, n, nullptr, nullptr, n, &B.ctl->scan_total, B.part, s);
   int64_t nb = (n + 255) / 256;
   int g = (int)(nb > 8192 ? 8192 : (nb < 1 ? 1 : nb));
-  hipLaunchKernelGGL(compact_k, dim3(g), dim3(256), 0, s, n, c->prm.group_size, B.flag, B.flag2,
+  hipLaunchKernelGGL(compact_k, dim3(g), dim3(256), 0, s, n, c->cur_G, B.flag, B.flag2,
                      B.alist, B.ctl);
   // runs between gaps > r_crit (flag: run breaks, flag2: run index, gA: run starts)
   hipLaunchKernelGGL(group_breaks_k, dim3(g), dim3(256), 0, s, n, B.rcrit, B.ctl, B.soff,
@@ -358,15 +360,23 @@ void launch_groups(gothic_ctx *c, int64_t n, hipStream_t s) {
   scan_exclusive(B.flag, B.flag2, 0, na_dev, nullptr, n, &B.ctl->scan_total, B.part, s);
   hipLaunchKernelGGL(group_runs_k, dim3(g), dim3(256), 0, s, B.ctl, B.flag, B.flag2, B.gA);
   // groups: every G-th particle of a run starts one (gB: starts, flag: group index)
-  hipLaunchKernelGGL(group_starts_k, dim3(g), dim3(256), 0, s, c->prm.group_size, B.ctl, B.flag,
+  hipLaunchKernelGGL(group_starts_k, dim3(g), dim3(256), 0, s, c->cur_G, B.ctl, B.flag,
                      B.flag2, B.gA, B.gB);
   scan_exclusive(B.gB, B.flag, 0, na_dev, nullptr, n, &B.ctl->scan_total, B.part, s);
   hipLaunchKernelGGL(group_first_k, dim3(g), dim3(256), 0, s, B.ctl, B.gB, B.flag, B.gfirst);
   int64_t wb = (n + 3) / 4;
   int gb = (int)(wb > 8192 ? 8192 : (wb < 1 ? 1 : wb));
   const bool acc_mac = c->prm.mac == 1;
-  hipLaunchKernelGGL(group_ball_k, dim3(gb), dim3(256), 0, s, n, c->prm.ball, B.ctl, B.alist,
-                     B.gfirst, B.pos, B.ball, acc_mac ? B.amag : nullptr, B.gamin);
+  decltype(&group_ball_k<0>) ball_fn;
+  switch (c->prm.ball) {
+    case 1: ball_fn = group_ball_k<1>; break;
+    case 2: ball_fn = group_ball_k<2>; break;
+    case 3: ball_fn = group_ball_k<3>; break;
+    case 4: ball_fn = group_ball_k<4>; break;
+    default: ball_fn = group_ball_k<0>; break;
+  }
+  hipLaunchKernelGGL(ball_fn, dim3(gb), dim3(256), 0, s, n, B.ctl, B.alist, B.gfirst, B.pos,
+                     B.ball, acc_mac ? B.amag : nullptr, B.gamin);
 }
 
 }  // namespace gothic

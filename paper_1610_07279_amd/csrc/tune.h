@@ -148,6 +148,52 @@ struct OnlineTuner {
   }
 };
 
+// Group size per sub-step class.  A block time step changes the number of
+// i-particles from step to step by orders of magnitude, and the best number
+// of threads sharing one i-particle (S) depends on it (Section 3.4, Fig. 7);
+// the paper fixes S and names choosing it per step as future work (Section
+// 4).  Here a wave holds one group of G i-particles with S = 64 / G lanes
+// each, so choosing S is choosing G.  The candidates are timed round-robin,
+// `rounds` walks each (interleaved, so a tree that ages between rebuilds
+// weighs on every candidate alike), and the smallest mean walk time wins.
+struct GroupPicker {
+  static constexpr int kCand = 4;
+  static constexpr int kSizes[kCand] = {8, 16, 32, 64};
+  int rounds = 2;
+  double sum[kCand] = {0, 0, 0, 0};
+  int count[kCand] = {0, 0, 0, 0};
+  int next = 0;     // candidate timed next
+  int chosen = -1;  // index of the winner once every candidate is timed
+
+  void init(int rounds_) {
+    rounds = rounds_ < 1 ? 1 : rounds_;
+    for (int k = 0; k < kCand; ++k) {
+      sum[k] = 0.0;
+      count[k] = 0;
+    }
+    next = 0;
+    chosen = -1;
+  }
+  bool decided() const { return chosen >= 0; }
+  int current() const { return kSizes[decided() ? chosen : next]; }
+  void choose(int G) {  // fixed from outside
+    for (int k = 0; k < kCand; ++k)
+      if (kSizes[k] == G) chosen = k;
+  }
+  void observe(double t) {
+    if (decided()) return;
+    sum[next] += t;
+    ++count[next];
+    next = (next + 1) % kCand;
+    if (next == 0 && count[kCand - 1] >= rounds) {
+      int b = 0;
+      for (int k = 1; k < kCand; ++k)
+        if (sum[k] / count[k] < sum[b] / count[b]) b = k;
+      chosen = b;
+    }
+  }
+};
+
 // Tree-rebuild interval (Section 2.6 and Appendix C of the paper).  Reusing
 // the last tree saves its construction time t_make, while the walk time
 // t_walk^(i) of the i-th step on the same tree grows as the tree drifts from

@@ -434,17 +434,33 @@ static WalkFn walk_fn(int multi, int G) {
   }
 }
 
-int walk_slots(gothic_ctx *c) {
+// resident walk waves of the kernel for each group size G = 2^lg, kept per
+// (multipole, list depth)
+static void walk_occupancy(gothic_ctx *c) {
   const int multi = c->prm.multipole;
   int D, DQ;
   list_dims(multi, c->prm.list_depth, &D, &DQ);
+  if (c->slots_multi == multi && c->slots_D == D) return;
   const int wb = wave_bytes_for(multi, D, DQ);
   const int wpb = waves_per_block(wb);
-  int per_cu = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, walk_fn(multi, c->prm.group_size), wpb * 64, wpb * wb);
-  if (e != hipSuccess || per_cu < 1) per_cu = 1;
-  return c->num_cus * per_cu * wpb;
+  for (int lg = 0; lg < kGroupSizes; ++lg) {
+    int per_cu = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, walk_fn(multi, 1 << lg), wpb * 64, wpb * wb);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    c->slots_g[lg] = c->num_cus * per_cu * wpb;
+  }
+  c->slots_multi = multi;
+  c->slots_D = D;
+}
+
+// the most persistent waves a walk of any group size launches (the spill
+// stacks are sized for it)
+int walk_slots(gothic_ctx *c) {
+  walk_occupancy(c);
+  int m = 0;
+  for (int lg = 0; lg < kGroupSizes; ++lg) m = c->slots_g[lg] > m ? c->slots_g[lg] : m;
+  return m;
 }
 
 void launch_walk(gothic_ctx *c, int64_t n, float4 *acc_pot, hipStream_t s) {
@@ -470,7 +486,7 @@ void launch_walk(gothic_ctx *c, int64_t n, float4 *acc_pot, hipStream_t s) {
   a.mcrit = B.mcrit;
   a.mac_delta = c->prm.mac_delta;
   a.mac = c->prm.mac;
-  a.G = c->prm.group_size;
+  a.G = c->cur_G;
   int lg = 0;
   while ((1 << lg) < a.G) ++lg;
   a.logG = lg;
@@ -478,7 +494,9 @@ void launch_walk(gothic_ctx *c, int64_t n, float4 *acc_pot, hipStream_t s) {
   a.wave_bytes = wave_bytes_for(multi, a.D, a.DQ);
   a.compensated = c->prm.compensated;
   const int wpb = waves_per_block(a.wave_bytes);
-  const int slots = c->walk_waves;
+  walk_occupancy(c);
+  const int own = c->slots_g[lg];
+  const int slots = own < c->walk_waves ? own : c->walk_waves;
   const int blocks = slots / wpb;
   hipLaunchKernelGGL(walk_fn(multi, a.G), dim3(blocks), dim3(wpb * 64), wpb * a.wave_bytes, s, a);
 }

@@ -124,3 +124,78 @@ def test_captured_step_reads_rcrit_from_device():
         groups.append(runs[1][0].stats()["n_groups"])
     say(f"  groups at the last sub-step of each phase {groups}")
     assert groups[1] != groups[0] and groups[2] == groups[0]
+
+
+def _bound(x, v, eps, **kw):
+    ctx = g.Context(device=0, multipole=2, **kw)
+    pos = torch.from_numpy(x[:, :3].astype(np.float64)).cuda()
+    vel = torch.from_numpy(v).cuda()
+    mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).cuda()
+    return ctx, pos, vel, mass
+
+
+def test_group_size_per_class_replays_equal_launches():
+    """A group size per sub-step class (S = 64 / G lanes per i-particle per
+    class): captured sub-steps with one groups + walk graph per size give the
+    launched sub-steps bit for bit, and the table is what the classes use."""
+    kmax = 3
+    x, v = ics.plummer(6000, seed=85, with_vel=True)
+    table = [8, 64, 16, 32]
+    say(f"[gpu] group sizes per class {table}, graph vs launched")
+    runs = []
+    for graph in (0, 1):
+        ctx, pos, vel, mass = _bound(x, v, 1 / 64, graph=graph)
+        ctx.sim_bind(pos, vel, mass, 1 / 64, 0.5, eta=0.1, kmax=kmax)
+        ctx.set_params(check=0)
+        ctx.sim_set_group_sizes(table)
+        runs.append((ctx, pos, vel))
+    _, _, gs = runs[1][0].sim_tuning(kmax + 2, with_groups=True)
+    assert gs.tolist() == table + [32]
+    for step in range(3 << kmax):
+        for ctx, _, _ in runs:
+            ctx.sim_step()
+        torch.cuda.synchronize()
+        (c0, p0, v0), (c1, p1, v1) = runs
+        assert torch.equal(p0, p1) and torch.equal(v0, v1), step
+        assert c0.stats()["n_groups"] == c1.stats()["n_groups"], step
+    assert runs[1][0].stats()["flags"] == 0
+    # the last sub-step of a cycle (every particle due) walks groups of the
+    # size its class is given
+    n_groups = []
+    for size in (8, 64):
+        ctx, pos, vel, mass = _bound(x, v, 1 / 64, graph=1)
+        ctx.sim_bind(pos, vel, mass, 1 / 64, 0.5, eta=0.1, kmax=kmax)
+        ctx.set_params(check=0)
+        ctx.sim_set_group_sizes([size] * (kmax + 1))
+        ctx.sim_step(1 << kmax)
+        st = ctx.stats()
+        n_groups.append((st["n_groups"], st["n_active"]))
+    say(f"  all-active sub-step with G = 8 / 64: (groups, active) {n_groups}")
+    (g8, a8), (g64, a64) = n_groups
+    assert a8 == a64 == x.shape[0] and g8 >= a8 // 8 and g64 < g8
+    with pytest.raises(g.GothicError):
+        runs[0][0].sim_set_group_sizes([12])
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_autotune_picks_group_size_per_class(graph):
+    kmax = 3
+    x, v = ics.nfw(20000, seed=86, with_vel=True)
+    say(f"[gpu] autotune = 2 (group size per class, then r_crit), graph={graph}")
+    runs = []
+    for tune in (0, 2):
+        ctx, pos, vel, mass = _bound(x, v, 1 / 128, graph=graph, autotune=tune)
+        ctx.sim_bind(pos, vel, mass, 1 / 128, 0.5, eta=0.1, kmax=kmax)
+        ctx.set_params(check=0)
+        ctx.sim_step(16 << kmax)
+        torch.cuda.synchronize()
+        assert ctx.stats()["flags"] == 0
+        runs.append((ctx, pos.cpu().numpy()))
+    (c0, p0), (c1, p1) = runs
+    r, k, gs = c1.sim_tuning(kmax + 1, with_groups=True)
+    say(f"  group size per class {gs.tolist()}, r_crit searches {k.tolist()}")
+    assert set(gs.tolist()) <= {8, 16, 32, 64}
+    assert k[0] >= 1 and np.all(r[k > 0] < 0)
+    dx = np.abs(p1 - p0).max(1) / (np.abs(p0).max(1) + 1e-3)
+    say(f"  position difference to the untuned run: p99 {np.percentile(dx, 99):.2e}")
+    assert np.percentile(dx, 99) < 1e-3

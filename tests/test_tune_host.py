@@ -18,7 +18,13 @@ WRAP = r'''
 using gothic::BrentMin;
 using gothic::OnlineTuner;
 using gothic::RebuildModels;
+using gothic::GroupPicker;
 extern "C" {
+void *gp_new(int rounds) { auto *g = new GroupPicker(); g->init(rounds); return g; }
+int gp_current(void *p) { return static_cast<GroupPicker *>(p)->current(); }
+int gp_decided(void *p) { return static_cast<GroupPicker *>(p)->decided(); }
+void gp_observe(void *p, double t) { static_cast<GroupPicker *>(p)->observe(t); }
+void gp_choose(void *p, int G) { static_cast<GroupPicker *>(p)->choose(G); }
 void *rm_new(double n_max) { auto *r = new RebuildModels(); r->n_max = n_max; return r; }
 void rm_rebuilt(void *p, double t) { static_cast<RebuildModels *>(p)->rebuilt(t); }
 void rm_sample(void *p, double t) { static_cast<RebuildModels *>(p)->sample(t); }
@@ -82,6 +88,12 @@ def lib(tmp_path_factory):
     L.ot_best.argtypes = [P]
     L.ot_best.restype = D
     L.ot_searches.argtypes = [P]
+    L.gp_new.argtypes = [I]
+    L.gp_new.restype = P
+    L.gp_current.argtypes = [P]
+    L.gp_decided.argtypes = [P]
+    L.gp_observe.argtypes = [P, D]
+    L.gp_choose.argtypes = [P, I]
     L.rm_new.argtypes = [D]
     L.rm_new.restype = P
     L.rm_rebuilt.argtypes = [P, D]
@@ -232,3 +244,32 @@ def test_rebuild_becomes_due_at_the_optimum(lib):
             due_at = i + 1
             break
     assert due_at == 20
+
+
+def test_group_picker_times_candidates_in_turn(lib):
+    """Per-class group size (the per-step S the paper leaves as future work):
+    candidates 8, 16, 32, 64 are visited round-robin, `rounds` times each, and
+    the smallest mean time wins; a later observation changes nothing."""
+    cost = {8: 3.0, 16: 2.0, 32: 2.5, 64: 4.0}
+    g = lib.gp_new(3)
+    seen = []
+    while not lib.gp_decided(g):
+        G = lib.gp_current(g)
+        seen.append(G)
+        # an ageing tree: every later walk is slower, by more than the gap
+        # between 16 and 32 over the whole pick
+        lib.gp_observe(g, cost[G] + 0.05 * len(seen))
+    assert seen == [8, 16, 32, 64] * 3
+    assert lib.gp_current(g) == 16
+    lib.gp_observe(g, 0.0)
+    assert lib.gp_current(g) == 16
+    # noise that reverses one round does not reverse the means
+    g2 = lib.gp_new(2)
+    times = iter([3.0, 2.9, 2.5, 4.0, 3.0, 1.0, 2.5, 4.0])
+    while not lib.gp_decided(g2):
+        lib.gp_observe(g2, next(times))
+    assert lib.gp_current(g2) == 16  # means 3.0, 1.95, 2.5, 4.0
+    # a size fixed from outside
+    g3 = lib.gp_new(2)
+    lib.gp_choose(g3, 64)
+    assert lib.gp_decided(g3) and lib.gp_current(g3) == 64

@@ -345,7 +345,8 @@ def n_sweep(args):
     steps on 8 levels, at N = 2^10, 2^12, ..., 2^24 (or the one N of --n);
     seconds per finest sub-step of the block and the shared scheme and the part
     spent in the walk kernel (HIP events).  The split over the other functions
-    comes from a kernel trace of a run at one N.  One JSON line per N."""
+    comes from kernel traces of runs at one N each (--n N --no-shared).  One
+    JSON line per N."""
     import torch
 
     import ics
@@ -364,16 +365,20 @@ def n_sweep(args):
                         graph=args.graph, rebuild_interval=args.rebuild_interval, ball=args.ball,
                         mac=1, mac_delta=2.0 ** -7)
         row = {"n": n, "steps": args.steps, "model": "NFW", "mac": "acceleration 2^-7"}
-        for mode, shared in (("block", False), ("shared", True)):
+        modes = (("block", False),) if args.no_shared else (("block", False), ("shared", True))
+        for mode, shared in modes:
             r = run_sim(ctx, pos0, vel0, mass, eps, 0.5, eta, kmax, shared, args.steps,
                         args.warmup)
             row[f"{mode}_s_per_step"] = r["seconds"] / args.steps
             row[f"{mode}_walk_s_per_step"] = r["walk_ms"] / 1e3 / args.steps
             row[f"{mode}_interactions_per_s"] = r["info"]["interactions_total"] / r["seconds"]
             row[f"{mode}_tree_builds"] = r["info"]["tree_builds"]
-        log(f"n sweep: N={n}: block {row['block_s_per_step'] * 1e3:.3f} ms (walk "
-            f"{row['block_walk_s_per_step'] * 1e3:.3f}), shared {row['shared_s_per_step'] * 1e3:.3f}"
-            f" ms (walk {row['shared_walk_s_per_step'] * 1e3:.3f})")
+        msg = (f"n sweep: N={n}: block {row['block_s_per_step'] * 1e3:.3f} ms (walk "
+               f"{row['block_walk_s_per_step'] * 1e3:.3f})")
+        if not args.no_shared:
+            msg += (f", shared {row['shared_s_per_step'] * 1e3:.3f} ms (walk "
+                    f"{row['shared_walk_s_per_step'] * 1e3:.3f})")
+        log(msg)
         print(json.dumps(row), flush=True)
         del ctx, pos0, vel0, mass
         torch.cuda.empty_cache()

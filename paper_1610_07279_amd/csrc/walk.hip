@@ -176,6 +176,9 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   if (ctl->flags & kFlagNodeOverflow) return;  // no valid tree: the host repeats
   const unsigned ng = ctl->n_groups, nn = ctl->n_nodes, nsys = ctl->nsys;
   const int D = a.D, DQ = a.DQ;
+  // with fewer groups than waves the surplus waves have nothing to claim:
+  // they leave before touching the shared counters
+  if (slot >= (int64_t)ng) return;
 
   unsigned long long t_node = 0, t_part = 0, t_int = 0, t_nint = 0, t_mac = 0;
   // XCD-aware work distribution: the groups (key order, hence spatially
@@ -379,7 +382,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     t_nint += (unsigned long long)gc * e_node;
     t_mac += n_mac;
   }
-  if (lane == 0) {
+  if (lane == 0 && t_mac) {
     atomicAdd(&ctl->node_entries, t_node);
     atomicAdd(&ctl->part_entries, t_part);
     atomicAdd(&ctl->interactions, t_int);

@@ -5,8 +5,10 @@
 //   scan:    exclusive scan of the digit-major table = global start of every
 //            (digit, tile) bucket,
 //   scatter: each tile ranks its elements stably (tile order, then wave
-//            order, then lane order) with ballot-based digit matching and
-//            writes them to their bucket.
+//            order, then lane order) with ballot-based digit matching,
+//            places them in LDS in digit order and writes each digit's run
+//            to its bucket with neighbouring threads on neighbouring
+//            addresses.
 // Equal keys keep the order of their indices, so the result is the
 // lexicographic (key, original index) order.  With several systems the key
 // passes are followed by passes on the digits of the system id (derived from
@@ -71,17 +73,26 @@ __global__ void __launch_bounds__(kSortThreads)
 radix_scatter_k(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ iin,
                 uint64_t *__restrict__ kout, uint32_t *__restrict__ iout, int64_t n, int shift,
                 int sys_shift, const uint32_t *__restrict__ soff, unsigned nsys, int64_t ntiles,
-                const uint32_t *__restrict__ ofs) {
+                const uint32_t *__restrict__ hist, const uint32_t *__restrict__ ofs) {
   constexpr int NW = kSortThreads / 64;
-  __shared__ unsigned gofs[kRadix];
+  static_assert(kSortThreads == kRadix, "one digit per thread in the local scan");
+  __shared__ unsigned gofs[kRadix];    // global start of (digit, this tile)
+  __shared__ unsigned lstart[kRadix];  // start of the digit inside the tile
   __shared__ unsigned run[kRadix];
   __shared__ unsigned wcnt[NW][kRadix];
-  for (int t = threadIdx.x; t < kRadix; t += kSortThreads) {
-    gofs[t] = ofs[(int64_t)t * ntiles + blockIdx.x];
-    run[t] = 0;
-  }
+  __shared__ unsigned scan_sh[NW + 1];
+  __shared__ uint64_t sk[kSortTile];   // the tile in digit order
+  __shared__ uint32_t si[kSortTile];
+  const int t0 = threadIdx.x;
+  gofs[t0] = ofs[(int64_t)t0 * ntiles + blockIdx.x];
+  run[t0] = 0;
+  unsigned total;
+  lstart[t0] = block_excl_sum<kSortThreads>(hist[(int64_t)t0 * ntiles + blockIdx.x], scan_sh,
+                                            &total);
   const int w = threadIdx.x >> 6;
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  // rank stably inside the tile (item round, then wave, then lane) and
+  // place each element at its digit's run in LDS
   for (int r = 0; r < kSortItems; ++r) {
     for (int t = threadIdx.x; t < NW * kRadix; t += kSortThreads) (&wcnt[0][0])[t] = 0;
     __syncthreads();
@@ -102,11 +113,11 @@ radix_scatter_k(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ i
     if (valid && below == cnt - 1) wcnt[w][d] = cnt;
     __syncthreads();
     if (valid) {
-      unsigned pos = gofs[d] + run[d] + below;
+      unsigned pos = lstart[d] + run[d] + below;
       for (int v = 0; v < w; ++v) pos += wcnt[v][d];
-      if (pos < n) {
-        kout[pos] = key;
-        iout[pos] = id;
+      if (pos < (unsigned)kSortTile) {
+        sk[pos] = key;
+        si[pos] = id;
       }
     }
     __syncthreads();
@@ -116,6 +127,19 @@ radix_scatter_k(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ i
       run[t] += s;
     }
     __syncthreads();
+  }
+  // write the tile out in digit order: neighbouring threads write
+  // neighbouring addresses inside each digit's bucket
+  const int64_t m_tile = n - base < kSortTile ? n - base : kSortTile;
+  for (int j = threadIdx.x; j < m_tile; j += kSortThreads) {
+    const uint64_t key = sk[j];
+    const uint32_t id = si[j];
+    const unsigned d = digit_of(key, id, shift, sys_shift, soff, nsys);
+    const unsigned pos = gofs[d] + ((unsigned)j - lstart[d]);
+    if (pos < n) {
+      kout[pos] = key;
+      iout[pos] = id;
+    }
   }
 }
 
@@ -141,7 +165,7 @@ void launch_radix_sort(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
     scan_exclusive(hist, ofs, ntiles * kRadix, nullptr, nullptr, ntiles * kRadix,
                    &c->b.ctl->scan_total, c->b.part, s);
     hipLaunchKernelGGL(radix_scatter_k, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, ka, ia,
-                       kb, ib, n, shift, sys_shift, c->b.soff, (unsigned)nsys, ntiles, ofs);
+                       kb, ib, n, shift, sys_shift, c->b.soff, (unsigned)nsys, ntiles, hist, ofs);
     uint64_t *tk = ka; ka = kb; kb = tk;
     uint32_t *ti = ia; ia = ib; ib = ti;
   }

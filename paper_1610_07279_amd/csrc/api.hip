@@ -300,9 +300,12 @@ static void enqueue_make(gothic_ctx *c, const Systems &sy, const float4 *xyzm, h
   launch_ancestors(c, sy.n, s);
 }
 
+// sign_active: the active flags are the sign bits of the masses in xyzm
+// (the block-step predictor's shadow); active is then not read
 static void enqueue_post(gothic_ctx *c, const Systems &sy, const float4 *xyzm,
-                         const uint8_t *active, const float4 *acc_old, hipStream_t s) {
-  launch_permute(c, xyzm, active, c->prm.mac == 1 ? acc_old : nullptr, sy.n, s);
+                         const uint8_t *active, const float4 *acc_old, hipStream_t s,
+                         bool sign_active = false) {
+  launch_permute(c, xyzm, active, sign_active, c->prm.mac == 1 ? acc_old : nullptr, sy.n, s);
   launch_moments(c, sy.n, sy.nsys, s);
   launch_groups(c, sy.n, s);
 }
@@ -322,7 +325,7 @@ static void enqueue_walk(gothic_ctx *c, int64_t n, float4 *out, hipStream_t s, b
 // models are being fed.
 static int enqueue_forces(gothic_ctx *c, const Systems &sy, const float4 *xyzm,
                           const uint8_t *active, const float4 *acc_old, float4 *out,
-                          hipStream_t s, float r_crit, bool rebuild) {
+                          hipStream_t s, float r_crit, bool rebuild, bool sign_active = false) {
   enqueue_begin(c, !rebuild, r_crit, s);
   enqueue_upload(c, sy, s);
   if (rebuild) {
@@ -331,7 +334,7 @@ static int enqueue_forces(gothic_ctx *c, const Systems &sy, const float4 *xyzm,
     enqueue_make(c, sy, xyzm, s);
     if (tm) (void)hipEventRecord(c->tree.mk1, s);
   }
-  enqueue_post(c, sy, xyzm, active, acc_old, s);
+  enqueue_post(c, sy, xyzm, active, acc_old, s, sign_active);
   enqueue_walk(c, sy.n, out, s, true);
   return hip_check(hipGetLastError(), "kernel launch");
 }
@@ -547,7 +550,7 @@ static void meter_mark(gothic_ctx *c, int k, bool rebuilt, bool tuned, bool pick
 static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const uint8_t *active,
                       const float4 *acc_old, float4 *o4, hipStream_t s, float r_crit,
                       int meter_class = 0, bool tuned = false, int kmax = 0, int group_G = 0,
-                      bool picked = false) {
+                      bool picked = false, bool sign_active = false) {
   const int64_t n = sy.n;
   c->cur_G = group_G > 0 ? group_G : c->prm.group_size;
   if (c->prm.mac == 1 && !acc_old)
@@ -576,7 +579,7 @@ static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const 
   constexpr int kAttempts = 6;
   for (int attempt = 0; attempt < kAttempts; ++attempt) {
     c->tune.recording = meter;
-    rc = enqueue_forces(c, sy, x4, active, acc_old, o4, s, r_crit, rebuild);
+    rc = enqueue_forces(c, sy, x4, active, acc_old, o4, s, r_crit, rebuild, sign_active);
     c->tune.recording = false;
     if (rc) return rc;
     tree_used(c, sy, rebuild);
@@ -1070,7 +1073,7 @@ static int capture_segment(gothic_ctx *c, int seg, hipGraphExec_t *out) {
       enqueue_upload(c, sy, G.cap_stream);
       break;
     case 1: enqueue_make(c, sy, S.shadow, G.cap_stream); break;
-    case 2: enqueue_post(c, sy, S.shadow, S.act, S.aold, G.cap_stream); break;
+    case 2: enqueue_post(c, sy, S.shadow, nullptr, S.aold, G.cap_stream, true); break;
     case 3: enqueue_walk(c, sy.n, S.anew, G.cap_stream, false); break;
     default: sim_launch_correct(c, G.cap_stream); break;
   }
@@ -1193,8 +1196,8 @@ int gothic_sim_step(gothic_ctx *c, void *stream) {
     if (meter) meter_mark(c, cls, rebuild, tuning, picking);
   } else {
     sim_launch_predict(c, s);
-    rc = run_forces(c, sim_systems(S), S.shadow, S.act, S.aold, S.anew, s, r_crit, cls, tuning,
-                    S.kmax, gsize, picking);
+    rc = run_forces(c, sim_systems(S), S.shadow, nullptr, S.aold, S.anew, s, r_crit, cls, tuning,
+                    S.kmax, gsize, picking, true);
     if (rc) return rc;
     if (c->tree.since == 1) ++S.builds;
     sim_launch_correct(c, s);

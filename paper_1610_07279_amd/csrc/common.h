@@ -256,7 +256,7 @@ void launch_radix_sort(gothic_ctx *c, int64_t n, int nsys, hipStream_t s);
 bool keys_to_B(int nsys);  // the key kernel writes keyB / idxB (odd pass count)
 int64_t radix_hist_entries(int64_t n);
 // tree.hip
-void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active,
+void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active, bool sign_active,
                     const float4 *acc_old, int64_t n, hipStream_t s);
 void launch_build(gothic_ctx *c, int64_t n, int nsys, hipStream_t s);
 // moments.hip: the ancestor table of a new tree

@@ -22,6 +22,33 @@ constexpr unsigned kNone = 0xffffffffu;
 
 __device__ __forceinline__ float u2f(unsigned u) { return __uint_as_float(u); }
 
+// a float moved between lanes of a row of 16 by a DPP control that gives
+// every lane a source (row rotations, quad permutations)
+template <int CTRL>
+__device__ __forceinline__ float row_dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+// sum / max over the 16 lanes of a row (lanes 16r .. 16r+15), in every lane:
+// rotate by 8 and 4 within the row, then swap lane pairs of each quad
+// (quad_perm [2,3,0,1] and [1,0,3,2])
+__device__ __forceinline__ float row_sum16(float v) {
+  v += row_dpp<0x128>(v);  // row_ror:8
+  v += row_dpp<0x124>(v);  // row_ror:4
+  v += row_dpp<0x4e>(v);
+  v += row_dpp<0xb1>(v);
+  return v;
+}
+__device__ __forceinline__ float row_max16(float v) {
+  v = fmaxf(v, row_dpp<0x128>(v));
+  v = fmaxf(v, row_dpp<0x124>(v));
+  v = fmaxf(v, row_dpp<0x4e>(v));
+  v = fmaxf(v, row_dpp<0xb1>(v));
+  return v;
+}
+
+// Leaves: 16 lanes per node, each lane taking members lane, lane + 16, ...
+// (coalesced loads), sums and maxima reduced across the row.  Rows whose
+// node is internal take no part but run the same shuffles.
 __global__ void __launch_bounds__(256)
 leaf_moments_k(Ctl *__restrict__ ctl, int64_t n, const uint32_t *__restrict__ first,
                const uint32_t *__restrict__ count, const uint8_t *__restrict__ n_child,
@@ -29,24 +56,33 @@ leaf_moments_k(Ctl *__restrict__ ctl, int64_t n, const uint32_t *__restrict__ fi
                float4 *__restrict__ nrec, float4 *__restrict__ quad, int want_quad) {
   if (ctl->flags & kFlagNodeOverflow) return;  // incomplete tree: nothing to do
   const int64_t nn = ctl->n_nodes;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nn;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    if (n_child[k] != 0) continue;
-    const uint32_t f = first[k], c = count[k];
-    if (c == 0 || (int64_t)f + c > n) {
-      atomicOr(&ctl->flags, kFlagBadIndex);
-      continue;
+  const int lane = lane_id();
+  const int rl = lane & 15;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t k0 = wave * 4; k0 < nn; k0 += nwaves * 4) {  // wave-uniform
+    const int64_t k = k0 + (lane >> 4);
+    bool leaf = k < nn && n_child[k] == 0;
+    const uint32_t f = leaf ? first[k] : 0u, c = leaf ? count[k] : 0u;
+    if (leaf && (c == 0 || (int64_t)f + c > n)) {
+      if (rl == 0) atomicOr(&ctl->flags, kFlagBadIndex);
+      leaf = false;
     }
-    const float4 p0 = pos[f];
+    const uint32_t cnt = leaf ? c : 0u;
+    const float4 p0 = pos[leaf ? f : 0u];
     float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
-    for (uint32_t j = f; j < f + c; ++j) {
-      const float4 p = pos[j];
+    for (uint32_t t = rl; t < cnt; t += 16) {
+      const float4 p = pos[f + t];
       M += p.w;
       sx += p.w * (p.x - p0.x);
       sy += p.w * (p.y - p0.y);
       sz += p.w * (p.z - p0.z);
-      leaf_of[j] = (uint32_t)k;
+      leaf_of[f + t] = (uint32_t)k;
     }
+    M = row_sum16(M);
+    sx = row_sum16(sx);
+    sy = row_sum16(sy);
+    sz = row_sum16(sz);
     float cx = p0.x, cy = p0.y, cz = p0.z;
     if (M > 0.f) {
       cx = p0.x + sx / M;
@@ -54,23 +90,41 @@ leaf_moments_k(Ctl *__restrict__ ctl, int64_t n, const uint32_t *__restrict__ fi
       cz = p0.z + sz / M;
     }
     float b2 = 0.f, xx = 0.f, yy = 0.f, zz = 0.f, xy = 0.f, xz = 0.f, yz = 0.f;
-    for (uint32_t j = f; j < f + c; ++j) {
-      const float4 p = pos[j];
+    for (uint32_t t = rl; t < cnt; t += 16) {
+      const float4 p = pos[f + t];
       const float dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
       b2 = fmaxf(b2, dx * dx + dy * dy + dz * dz);
-      if (want_quad) {
-        xx += p.w * dx * dx; yy += p.w * dy * dy; zz += p.w * dz * dz;
-        xy += p.w * dx * dy; xz += p.w * dx * dz; yz += p.w * dy * dz;
-      }
+      xx += p.w * dx * dx; yy += p.w * dy * dy; zz += p.w * dz * dz;
+      xy += p.w * dx * dy; xz += p.w * dx * dz; yz += p.w * dy * dz;
     }
-    const float b = (M > 0.f) ? sqrtf(b2) : 0.f;
-    nrec[2 * k] = make_float4(cx, cy, cz, M);
-    nrec[2 * k + 1] = make_float4(b, u2f(f), u2f(c), u2f(1u));
-    quad[2 * k] = make_float4(xx, yy, zz, xy);
-    quad[2 * k + 1] = make_float4(xz, yz, xx + yy + zz, 0.f);
+    b2 = row_max16(b2);
+    if (want_quad) {
+      xx = row_sum16(xx); yy = row_sum16(yy); zz = row_sum16(zz);
+      xy = row_sum16(xy); xz = row_sum16(xz); yz = row_sum16(yz);
+    } else {
+      xx = yy = zz = xy = xz = yz = 0.f;
+    }
+    if (leaf && rl == 0) {
+      const float b = (M > 0.f) ? sqrtf(b2) : 0.f;
+      nrec[2 * k] = make_float4(cx, cy, cz, M);
+      nrec[2 * k + 1] = make_float4(b, u2f(f), u2f(c), u2f(1u));
+      quad[2 * k] = make_float4(xx, yy, zz, xy);
+      quad[2 * k + 1] = make_float4(xz, yz, xx + yy + zz, 0.f);
+    }
   }
 }
 
+// sum over the 8 lanes of a segment (lanes 8s .. 8s+7)
+__device__ __forceinline__ float seg_sum8(float v) {
+#pragma unroll
+  for (int d = 4; d >= 1; d >>= 1) v += __shfl_xor(v, d, 8);
+  return v;
+}
+
+// Internal nodes of level l from their children: 8 lanes per node, lane q
+// reading child q (all children's records in flight at once), sums reduced
+// across the 8 lanes; second moments about the new centre by the
+// parallel-axis rule.
 __global__ void __launch_bounds__(256)
 internal_moments_k(int l, Ctl *__restrict__ ctl, const uint32_t *__restrict__ child_first,
                    const uint8_t *__restrict__ n_child, float4 *__restrict__ nrec,
@@ -80,24 +134,27 @@ internal_moments_k(int l, Ctl *__restrict__ ctl, const uint32_t *__restrict__ ch
   const int64_t lo = ctl->lvl_start[l];
   int64_t hi = ctl->lvl_start[l + 1];
   if (hi > hi_all) hi = hi_all;
-  for (int64_t k = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < hi;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const unsigned nc = n_child[k];
-    if (nc == 0) continue;
-    const uint32_t cf = child_first[k];
-    if (cf <= k || (int64_t)cf + nc > hi_all) {
-      atomicOr(&ctl->flags, kFlagBadIndex);
-      continue;
+  const int lane = lane_id();
+  const unsigned q = (unsigned)(lane & 7);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t k0 = lo + wave * 8; k0 < hi; k0 += nwaves * 8) {  // wave-uniform
+    const int64_t k = k0 + (lane >> 3);
+    const unsigned nc = k < hi ? n_child[k] : 0u;
+    const uint32_t cf = nc ? child_first[k] : 0u;
+    bool inner = nc != 0;
+    if (inner && (cf <= k || (int64_t)cf + nc > hi_all)) {
+      if (q == 0) atomicOr(&ctl->flags, kFlagBadIndex);
+      inner = false;
     }
-    const float4 r0 = nrec[2 * (size_t)cf];
-    float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
-    for (unsigned q = 0; q < nc; ++q) {
-      const float4 r = nrec[2 * (cf + q)];
-      M += r.w;
-      sx += r.w * (r.x - r0.x);
-      sy += r.w * (r.y - r0.y);
-      sz += r.w * (r.z - r0.z);
-    }
+    const bool mine = inner && q < nc;  // this lane reads child q
+    const float4 r0 = nrec[2 * (size_t)(inner ? cf : 0u)];
+    const float4 r = nrec[2 * (size_t)(mine ? cf + q : 0u)];
+    const float w = mine ? r.w : 0.f;
+    const float M = seg_sum8(w);
+    const float sx = seg_sum8(w * (r.x - r0.x));
+    const float sy = seg_sum8(w * (r.y - r0.y));
+    const float sz = seg_sum8(w * (r.z - r0.z));
     float cx = r0.x, cy = r0.y, cz = r0.z;
     if (M > 0.f) {
       cx = r0.x + sx / M;
@@ -106,18 +163,22 @@ internal_moments_k(int l, Ctl *__restrict__ ctl, const uint32_t *__restrict__ ch
     }
     float xx = 0.f, yy = 0.f, zz = 0.f, xy = 0.f, xz = 0.f, yz = 0.f;
     if (want_quad) {
-      for (unsigned q = 0; q < nc; ++q) {
-        const float4 r = nrec[2 * (cf + q)];
-        const float4 s0 = quad[2 * (cf + q)], s1 = quad[2 * (cf + q) + 1];
-        const float dx = r.x - cx, dy = r.y - cy, dz = r.z - cz;
-        xx += s0.x + r.w * dx * dx; yy += s0.y + r.w * dy * dy; zz += s0.z + r.w * dz * dz;
-        xy += s0.w + r.w * dx * dy; xz += s1.x + r.w * dx * dz; yz += s1.y + r.w * dy * dz;
-      }
+      const size_t cq = 2 * (size_t)(mine ? cf + q : 0u);
+      const float4 s0 = quad[cq], s1 = quad[cq + 1];
+      const float dx = r.x - cx, dy = r.y - cy, dz = r.z - cz;
+      xx = seg_sum8(mine ? s0.x + w * dx * dx : 0.f);
+      yy = seg_sum8(mine ? s0.y + w * dy * dy : 0.f);
+      zz = seg_sum8(mine ? s0.z + w * dz * dz : 0.f);
+      xy = seg_sum8(mine ? s0.w + w * dx * dy : 0.f);
+      xz = seg_sum8(mine ? s1.x + w * dx * dz : 0.f);
+      yz = seg_sum8(mine ? s1.y + w * dy * dz : 0.f);
     }
-    nrec[2 * k] = make_float4(cx, cy, cz, M);
-    nrec[2 * k + 1] = make_float4(0.f, u2f(cf), u2f(nc), u2f(0u));
-    quad[2 * k] = make_float4(xx, yy, zz, xy);
-    quad[2 * k + 1] = make_float4(xz, yz, xx + yy + zz, 0.f);
+    if (inner && q == 0) {
+      nrec[2 * k] = make_float4(cx, cy, cz, M);
+      nrec[2 * k + 1] = make_float4(0.f, u2f(cf), u2f(nc), u2f(0u));
+      quad[2 * k] = make_float4(xx, yy, zz, xy);
+      quad[2 * k + 1] = make_float4(xz, yz, xx + yy + zz, 0.f);
+    }
   }
 }
 
@@ -372,7 +433,7 @@ void launch_moments(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
   Buffers &B = c->b;
   // second moments for quadrupole terms and for the B2 of the multipole MAC
   const int wq = (c->prm.multipole == 2 || c->prm.mac == 2) ? 1 : 0;
-  int64_t nb = (c->cap_nodes + 255) / 256;
+  int64_t nb = (c->cap_nodes + 15) / 16;  // 16 nodes per workgroup pass
   int g = (int)(nb > 8192 ? 8192 : (nb < 1 ? 1 : nb));
   hipLaunchKernelGGL(leaf_moments_k, dim3(g), dim3(256), 0, s, B.ctl, n, B.first, B.count,
                      B.n_child, B.pos, B.leaf_of, B.nrec, B.quad, wq);
@@ -380,7 +441,7 @@ void launch_moments(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
     int64_t widest = nsys;
     for (int q = 0; q < l && widest < c->cap_nodes; ++q) widest *= 8;
     if (widest > c->cap_nodes) widest = c->cap_nodes;
-    int64_t lb = (widest + 255) / 256;
+    int64_t lb = (widest + 31) / 32;  // 32 nodes per workgroup pass
     int gl = (int)(lb > 4096 ? 4096 : (lb < 1 ? 1 : lb));
     hipLaunchKernelGGL(internal_moments_k, dim3(gl), dim3(256), 0, s, l, B.ctl, B.child_first,
                        B.n_child, B.nrec, B.quad, wq);

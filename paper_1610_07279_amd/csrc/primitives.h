@@ -14,15 +14,28 @@ __device__ __forceinline__ unsigned lanes_below(unsigned long long m) {
                                    __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-// inclusive prefix sum over the 64 lanes
+// DPP move (gfx9 encodings): lanes without a source lane read 0
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned dpp_or_zero(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+// inclusive prefix sum over the 64 lanes (all lanes active): shifts by 1, 2,
+// 4, 8 inside each row of 16 lanes, then row_bcast:15 adds row r's total to
+// rows 1 and 3 and row_bcast:31 adds row 1's total to rows 2 and 3
 __device__ __forceinline__ unsigned wave_incl_sum(unsigned v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    unsigned t = __shfl_up(v, d, 64);
-    if (l >= d) v += t;
-  }
+  v += dpp_or_zero<0x111, 0xf>(v);
+  v += dpp_or_zero<0x112, 0xf>(v);
+  v += dpp_or_zero<0x114, 0xf>(v);
+  v += dpp_or_zero<0x118, 0xf>(v);
+  v += dpp_or_zero<0x142, 0xa>(v);
+  v += dpp_or_zero<0x143, 0xc>(v);
   return v;
+}
+
+// the value of lane 63
+__device__ __forceinline__ unsigned wave_last(unsigned v) {
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {

@@ -138,8 +138,11 @@ sim_predict_k(int64_t n, unsigned nsys, const uint32_t *__restrict__ soff,
       const double x = pos[3 * i] + tau * vel[3 * i] + h * (double)a.x;
       const double y = pos[3 * i + 1] + tau * vel[3 * i + 1] + h * (double)a.y;
       const double z = pos[3 * i + 2] + tau * vel[3 * i + 2] + h * (double)a.z;
-      shadow[i] = make_float4((float)x, (float)y, (float)z, mass[i]);
       const bool due = el == ((int64_t)1 << (kmax - lev[i]));
+      // the sign of the (non-negative) mass carries the due flag to the
+      // key-order gather, which then reads one array instead of two
+      const float m = mass[i];
+      shadow[i] = make_float4((float)x, (float)y, (float)z, due ? -m : m);
       act[i] = due ? 1 : 0;
       cnt += due ? 1u : 0u;
     }

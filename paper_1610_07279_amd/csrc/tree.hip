@@ -21,9 +21,10 @@ constexpr int kBuildThreads = 256;
 constexpr unsigned kNone = 0xffffffffu;
 
 // Key order: positions and masses, active flags and (acceleration MAC) the
-// magnitudes of the previous accelerations.
+// magnitudes of the previous accelerations.  sign_active: the flag is the
+// sign bit of the mass (set by the block-step predictor), which is cleared.
 __global__ void __launch_bounds__(256)
-permute_k(const float4 *__restrict__ xyzm, const uint8_t *__restrict__ active,
+permute_k(const float4 *__restrict__ xyzm, const uint8_t *__restrict__ active, int sign_active,
           const float4 *__restrict__ acc_old, int64_t n, const uint32_t *__restrict__ perm,
           float4 *__restrict__ pos, uint32_t *__restrict__ flag, float *__restrict__ amag,
           Ctl *ctl) {
@@ -34,11 +35,18 @@ permute_k(const float4 *__restrict__ xyzm, const uint8_t *__restrict__ active,
       atomicOr(&ctl->flags, kFlagBadIndex);
       i = 0;
     }
-    const float4 p = xyzm[i];
+    float4 p = xyzm[i];
     if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w)))
       atomicOr(&ctl->flags, kFlagNonFinite);  // (a reused tree skips the key pass)
+    unsigned f = 1u;
+    if (sign_active) {
+      f = signbit(p.w) ? 1u : 0u;
+      p.w = fabsf(p.w);
+    } else if (active) {
+      f = active[i] != 0 ? 1u : 0u;
+    }
     pos[k] = p;
-    flag[k] = active ? (active[i] != 0 ? 1u : 0u) : 1u;
+    flag[k] = f;
     if (acc_old) {
       const float4 a = acc_old[i];
       amag[k] = sqrtf(a.x * a.x + a.y * a.y + a.z * a.z);
@@ -46,11 +54,12 @@ permute_k(const float4 *__restrict__ xyzm, const uint8_t *__restrict__ active,
   }
 }
 
-void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active,
+void launch_permute(gothic_ctx *c, const float4 *xyzm, const uint8_t *active, bool sign_active,
                     const float4 *acc_old, int64_t n, hipStream_t s) {
   int64_t nb = (n + 255) / 256;
   int g = (int)(nb > 8192 ? 8192 : (nb < 1 ? 1 : nb));
-  hipLaunchKernelGGL(permute_k, dim3(g), dim3(256), 0, s, xyzm, active, acc_old, n, c->b.idxA,
+  hipLaunchKernelGGL(permute_k, dim3(g), dim3(256), 0, s, xyzm, active, sign_active ? 1 : 0,
+                     acc_old, n, c->b.idxA,
                      c->b.pos, c->b.flag, c->b.amag, c->b.ctl);
 }
 

@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       const unsigned nc = open_int ? __float_as_uint(r1.z) : 0u;
       const unsigned cf = __float_as_uint(r1.y);
       const unsigned cinc = wave_incl_sum(nc);
-      const unsigned C = __builtin_amdgcn_readfirstlane(__shfl(cinc, 63, 64));
+      const unsigned C = wave_last(cinc);
       if (C) {
         const unsigned pre = cinc - nc;
         if ((qt - qb) + C > (unsigned)kQueueCap) {
@@ -335,7 +335,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       const unsigned pc = open_leaf ? __float_as_uint(r1.z) : 0u;
       const unsigned pf = __float_as_uint(r1.y);
       const unsigned pinc = wave_incl_sum(pc);
-      const unsigned P = __builtin_amdgcn_readfirstlane(__shfl(pinc, 63, 64));
+      const unsigned P = wave_last(pinc);
       if (P) {
         tpre[lane] = pinc - pc;
         tsrc[lane] = pf;

@@ -394,10 +394,18 @@ radius_k(Ctl *__restrict__ ctl, int64_t n, const float4 *__restrict__ pos,
       }
     }
   }
-  // the carried runs may continue in the next chunk
-  for (int l = 0; l < kMaxLevels; ++l) {
-    const unsigned rn = __builtin_amdgcn_readfirstlane(rc.node[w][l]);
-    if (rn != kNone) put_b(nrec, rn, rc.max[w][l], true);
+  // The carried runs may continue in the next chunk: one lane per level
+  // combines them with an atomic max.  Near the root every wave's run is the
+  // same node, so the atomic is skipped when the stored radius is already
+  // at least as large (radii only grow during the pass, so a stale read can
+  // only lead to an unneeded atomic, never to a missed one).
+  if (lane < kMaxLevels) {
+    const unsigned rn = rc.node[w][lane];
+    if (rn != kNone) {
+      unsigned *dst = reinterpret_cast<unsigned *>(&nrec[2 * (size_t)rn + 1].x);
+      const unsigned v = __float_as_uint(rc.max[w][lane]);
+      if (v > *dst) atomicMax(dst, v);
+    }
   }
 }
 

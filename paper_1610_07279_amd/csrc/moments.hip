@@ -47,7 +47,8 @@ __device__ __forceinline__ float row_max16(float v) {
 }
 
 // Leaves: 16 lanes per node, each lane taking members lane, lane + 16, ...
-// (coalesced loads), sums and maxima reduced across the row.  Rows whose
+// (coalesced loads, held in registers for both passes), sums and maxima
+// reduced across the row.  Rows whose
 // node is internal take no part but run the same shuffles.
 __global__ void __launch_bounds__(256)
 leaf_moments_k(Ctl *__restrict__ ctl, int64_t n, const uint32_t *__restrict__ first,
@@ -70,8 +71,24 @@ leaf_moments_k(Ctl *__restrict__ ctl, int64_t n, const uint32_t *__restrict__ fi
     }
     const uint32_t cnt = leaf ? c : 0u;
     const float4 p0 = pos[leaf ? f : 0u];
+    // the first 64 members (all of them unless particles share a level-21
+    // cell): up to four per lane, kept in registers for the second pass
+    float4 m[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t t = (uint32_t)rl + 16u * u;
+      m[u] = t < cnt ? pos[f + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+      if (t < cnt) leaf_of[f + t] = (uint32_t)k;
+    }
     float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
-    for (uint32_t t = rl; t < cnt; t += 16) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      M += m[u].w;
+      sx += m[u].w * (m[u].x - p0.x);
+      sy += m[u].w * (m[u].y - p0.y);
+      sz += m[u].w * (m[u].z - p0.z);
+    }
+    for (uint32_t t = (uint32_t)rl + 64u; t < cnt; t += 16) {  // members past 64
       const float4 p = pos[f + t];
       M += p.w;
       sx += p.w * (p.x - p0.x);
@@ -90,7 +107,16 @@ leaf_moments_k(Ctl *__restrict__ ctl, int64_t n, const uint32_t *__restrict__ fi
       cz = p0.z + sz / M;
     }
     float b2 = 0.f, xx = 0.f, yy = 0.f, zz = 0.f, xy = 0.f, xz = 0.f, yz = 0.f;
-    for (uint32_t t = rl; t < cnt; t += 16) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if ((uint32_t)rl + 16u * u >= cnt) continue;
+      const float4 p = m[u];
+      const float dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
+      b2 = fmaxf(b2, dx * dx + dy * dy + dz * dz);
+      xx += p.w * dx * dx; yy += p.w * dy * dy; zz += p.w * dz * dz;
+      xy += p.w * dx * dy; xz += p.w * dx * dz; yz += p.w * dy * dz;
+    }
+    for (uint32_t t = (uint32_t)rl + 64u; t < cnt; t += 16) {
       const float4 p = pos[f + t];
       const float dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
       b2 = fmaxf(b2, dx * dx + dy * dy + dz * dz);

@@ -26,6 +26,15 @@ def _coincident(n=300, seed=3):
     return x
 
 
+def _cluster(n=3000, m=130, seed=4):
+    """A Plummer sphere with m particles jittered by ~1e-7 about one point:
+    they share a level-21 cell, so a leaf holds more than 64 members."""
+    x = ics.plummer(n, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    x[:m, :3] = x[0, :3] + rng.uniform(-1e-7, 1e-7, (m, 3)).astype(np.float32)
+    return x
+
+
 def _uniform(n, seed):
     rng = np.random.default_rng(seed)
     x = np.empty((n, 4), np.float32)
@@ -39,6 +48,7 @@ SYSTEMS = {
     "nfw4097": lambda: ics.nfw(4097, seed=7),
     "uniform777": lambda: _uniform(777, 5),
     "coincident": lambda: _coincident(),
+    "cluster130": lambda: _cluster(),
     "one": lambda: ics.plummer(1, seed=1),
     "two": lambda: ics.plummer(2, seed=2),
     "allsame": lambda: np.tile(np.array([[0.25, -0.5, 1.0, 0.01]], np.float32), (70, 1)),
@@ -64,7 +74,7 @@ def test_keys_sort_tree_bitexact(name, key_kind):
             assert np.array_equal(t[f], t_o[f]), f
 
 
-@pytest.mark.parametrize("name", ["plummer8k", "nfw4097", "coincident"])
+@pytest.mark.parametrize("name", ["plummer8k", "nfw4097", "coincident", "cluster130"])
 @pytest.mark.parametrize("multipole", [1, 2])
 def test_moments_match(name, multipole):
     x = SYSTEMS[name]()
@@ -72,6 +82,8 @@ def test_moments_match(name, multipole):
     com, b, q = ctx.nodes()
     ks, perm, _ = ctx.keys()
     t = oracle.build(ks, 16)
+    if name == "cluster130":  # the case it is built for: a leaf past 64 members
+        assert (t["count"][t["n_child"] == 0]).max() > 64
     ps = x[perm].astype(np.float64)
     com_o, b_o, S_o = oracle.moments(t, ps)
     scale = np.abs(com_o[:, :3]).sum(1) + b_o

@@ -396,8 +396,9 @@ def main():
                     help="critical separation splitting groups (Section 2.4)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-shared", action="store_true", help="skip the shared-step run")
-    ap.add_argument("--autotune", type=int, default=0, choices=(0, 1),
-                    help="tune r_crit online during the block steps (Section 2.4)")
+    ap.add_argument("--autotune", type=int, default=0, choices=(0, 1, 2),
+                    help="1: tune r_crit online during the block steps (Section 2.4); 2: first "
+                         "pick the group size of each sub-step class, then tune r_crit")
     ap.add_argument("--ball", type=int, default=2, choices=range(5),
                     help="enclosing ball of the groups (Appendix B): 0 GEO, 1 SEB, 2 EBS, 3 COM, 4 CMP")
     ap.add_argument("--rebuild-interval", type=int, default=0,

@@ -230,23 +230,80 @@ __device__ DBall seb_wave(double px, double py, double pz, int cnt) {
   return B;
 }
 
+// smallest / largest float over the wave (all lanes active): an inclusive
+// DPP scan whose missing sources read the identity (+inf / -inf), then the
+// last lane is read back
+template <bool MAX>
+__device__ __forceinline__ float wave_extreme(float x) {
+  constexpr int ident = MAX ? (int)0xff800000 : (int)0x7f800000;
+  float v = x;
+#define GOTHIC_EXT_STEP(ctrl, rows)                                                    \
+  {                                                                                    \
+    const float o = __int_as_float(                                                    \
+        __builtin_amdgcn_update_dpp(ident, __float_as_int(v), ctrl, rows, 0xf, false)); \
+    v = MAX ? fmaxf(v, o) : fminf(v, o);                                               \
+  }
+  GOTHIC_EXT_STEP(0x111, 0xf)
+  GOTHIC_EXT_STEP(0x112, 0xf)
+  GOTHIC_EXT_STEP(0x114, 0xf)
+  GOTHIC_EXT_STEP(0x118, 0xf)
+  GOTHIC_EXT_STEP(0x142, 0xa)
+  GOTHIC_EXT_STEP(0x143, 0xc)
+#undef GOTHIC_EXT_STEP
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// uniform-lane broadcast of a double (two readlanes, no LDS)
+__device__ __forceinline__ double lane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// a 64-bit value moved by DPP (both halves); lanes without a source read 0
+template <int CTRL, int ROWS>
+__device__ __forceinline__ long long dpp64(long long v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, ROWS, 0xf, false);
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// largest value over the wave for values that are >= 0 or exactly -1 (their
+// bit patterns, read as signed 64-bit integers, order like the values): an
+// inclusive max scan by DPP whose last lane is read back
+__device__ __forceinline__ double wave_max_nonneg(double x) {
+  long long v = __double_as_longlong(x);
+#define GOTHIC_MAX_STEP(ctrl, rows)            \
+  {                                            \
+    const long long o = dpp64<ctrl, rows>(v);  \
+    v = o > v ? o : v;                         \
+  }
+  GOTHIC_MAX_STEP(0x111, 0xf)
+  GOTHIC_MAX_STEP(0x112, 0xf)
+  GOTHIC_MAX_STEP(0x114, 0xf)
+  GOTHIC_MAX_STEP(0x118, 0xf)
+  GOTHIC_MAX_STEP(0x142, 0xa)
+  GOTHIC_MAX_STEP(0x143, 0xc)
+#undef GOTHIC_MAX_STEP
+  return lane_d(__longlong_as_double(v), 63);
+}
+
 // Ritter's sphere: the diameter of two far members, grown in member order
 __device__ void ebs_wave(double px, double py, double pz, int cnt, double &cx, double &cy,
                          double &cz) {
   const int lane = lane_id();
   const bool v = lane < cnt;
-  const double x0 = __shfl(px, 0, 64), y0 = __shfl(py, 0, 64), z0 = __shfl(pz, 0, 64);
+  const double x0 = lane_d(px, 0), y0 = lane_d(py, 0), z0 = lane_d(pz, 0);
   // farthest member from member 0 (first one on ties), then farthest from it
   double d = v ? d2of(px, py, pz, x0, y0, z0) : -1.0;
-  double dm = d;
-  for (int o = 32; o >= 1; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+  double dm = wave_max_nonneg(d);
   const int y = first_lane(__ballot(v && d == dm));
-  const double yx = __shfl(px, y, 64), yy = __shfl(py, y, 64), yz = __shfl(pz, y, 64);
+  const double yx = lane_d(px, y), yy = lane_d(py, y), yz = lane_d(pz, y);
   d = v ? d2of(px, py, pz, yx, yy, yz) : -1.0;
-  dm = d;
-  for (int o = 32; o >= 1; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+  dm = wave_max_nonneg(d);
   const int z = first_lane(__ballot(v && d == dm));
-  const double zx = __shfl(px, z, 64), zy = __shfl(py, z, 64), zz = __shfl(pz, z, 64);
+  const double zx = lane_d(px, z), zy = lane_d(py, z), zz = lane_d(pz, z);
   cx = 0.5 * (yx + zx);
   cy = 0.5 * (yy + zy);
   cz = 0.5 * (yz + zz);
@@ -259,8 +316,8 @@ __device__ void ebs_wave(double px, double py, double pz, int cnt, double &cx, d
     const unsigned long long m = __ballot(v && lane > q && dq > r);
     if (!m) break;
     q = first_lane(m);
-    const double dd = __shfl(dq, q, 64);
-    const double qx = __shfl(px, q, 64), qy = __shfl(py, q, 64), qz = __shfl(pz, q, 64);
+    const double dd = lane_d(dq, q);
+    const double qx = lane_d(px, q), qy = lane_d(py, q), qz = lane_d(pz, q);
     const double rn = 0.5 * (r + dd);
     const double f = (rn - r) / dd;
     cx += (qx - cx) * f;
@@ -272,7 +329,7 @@ __device__ void ebs_wave(double px, double py, double pz, int cnt, double &cx, d
 
 __device__ __forceinline__ float ball_radius(float4 p, float cx, float cy, float cz) {
   const float dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
-  return wave_max(sqrtf(dx * dx + dy * dy + dz * dz));
+  return wave_extreme<true>(sqrtf(dx * dx + dy * dy + dz * dz));
 }
 
 // one wave per group; loop control is wave-uniform and the member load is
@@ -302,8 +359,10 @@ group_ball_k(int64_t n, const Ctl *__restrict__ ctl, const uint32_t *__restrict_
     const float4 p = pos[ai < n ? ai : 0];
     float cx, cy, cz;
     // GEO (also the fallback half of CMP)
-    const float lx = wave_min(p.x), ly = wave_min(p.y), lz = wave_min(p.z);
-    const float hx = wave_max(p.x), hy = wave_max(p.y), hz = wave_max(p.z);
+    const float lx = wave_extreme<false>(p.x), ly = wave_extreme<false>(p.y),
+                lz = wave_extreme<false>(p.z);
+    const float hx = wave_extreme<true>(p.x), hy = wave_extreme<true>(p.y),
+                hz = wave_extreme<true>(p.z);
     cx = 0.5f * (lx + hx);
     cy = 0.5f * (ly + hy);
     cz = 0.5f * (lz + hz);
@@ -340,7 +399,7 @@ group_ball_k(int64_t n, const Ctl *__restrict__ ctl, const uint32_t *__restrict_
     const float r = ball_radius(p, cx, cy, cz);
     ball[g] = make_float4(cx, cy, cz, r * kWiden);  // same from all lanes
     if (amag) {  // acceleration MAC: the group's smallest |a_old|
-      const float am = wave_min(amag[ai < n ? ai : 0]);
+      const float am = wave_extreme<false>(amag[ai < n ? ai : 0]);
       gamin[g] = am;
     }
   }

@@ -253,7 +253,9 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       const float4 r0 = a.nrec[2 * (size_t)node];
       const float4 r1 = a.nrec[2 * (size_t)node + 1];
       const float dx = r0.x - bl.x, dy = r0.y - bl.y, dz = r0.z - bl.z;
-      const float rji = sqrtf(dx * dx + dy * dy + dz * dz);
+      // the hardware square root (within 1 ulp): the MAC decision it feeds
+      // is only sensitive far beyond that
+      const float rji = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
       const float dist = fmaxf(rji - bl.w, 0.f);
       // multipole acceptance (Section 2.2); with the acceleration and
       // multipole MACs a node of positive size that may hold a member of the

@@ -547,12 +547,22 @@ static void meter_mark(gothic_ctx *c, int k, bool rebuilt, bool tuned, bool pick
   T.pending_pick = picked;
 }
 
+// How a block sub-step's evaluation is run and metered (defaults: a plain
+// evaluation with params.group_size and the caller's active flags).
+struct EvalOpts {
+  int meter_class = 0;       // sub-step class the walk time is booked to
+  bool tuned = false;        // r_crit came from the class's Brent search
+  bool picked = false;       // the group size came from the class's picker
+  int kmax = 0;              // finest level (class weights of the rebuild models)
+  int group_G = 0;           // group size; 0 = params.group_size
+  bool sign_active = false;  // active flags are the sign bits of the masses in x4
+};
+
 static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const uint8_t *active,
                       const float4 *acc_old, float4 *o4, hipStream_t s, float r_crit,
-                      int meter_class = 0, bool tuned = false, int kmax = 0, int group_G = 0,
-                      bool picked = false, bool sign_active = false) {
+                      const EvalOpts &o = EvalOpts()) {
   const int64_t n = sy.n;
-  c->cur_G = group_G > 0 ? group_G : c->prm.group_size;
+  c->cur_G = o.group_G > 0 ? o.group_G : c->prm.group_size;
   if (c->prm.mac == 1 && !acc_old)
     return set_error(GOTHIC_EINVAL,
                      "the acceleration MAC needs the previous accelerations (gothic_tree_forces_ex)");
@@ -570,7 +580,7 @@ static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const 
   if (rc) return rc;
   if ((rc = ensure_events(c))) return rc;
   const bool meter = metering(c) && !capturing;
-  if (meter && ((rc = meter_prepare(c)) || (rc = meter_collect(c, kmax)))) return rc;
+  if (meter && ((rc = meter_prepare(c)) || (rc = meter_collect(c, o.kmax)))) return rc;
   c->last_n = n;
   c->last_nsys = sy.nsys;
   c->last_stream = s;
@@ -579,7 +589,7 @@ static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const 
   constexpr int kAttempts = 6;
   for (int attempt = 0; attempt < kAttempts; ++attempt) {
     c->tune.recording = meter;
-    rc = enqueue_forces(c, sy, x4, active, acc_old, o4, s, r_crit, rebuild, sign_active);
+    rc = enqueue_forces(c, sy, x4, active, acc_old, o4, s, r_crit, rebuild, o.sign_active);
     c->tune.recording = false;
     if (rc) return rc;
     tree_used(c, sy, rebuild);
@@ -615,7 +625,7 @@ static int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const 
     if ((rc = ensure(c, n, sy.nsys, nodes, spill))) return rc;
     rebuild = true;  // the grown buffers hold no tree
   }
-  if (meter) meter_mark(c, meter_class, rebuild, tuned, picked);
+  if (meter) meter_mark(c, o.meter_class, rebuild, o.tuned, o.picked);
   return GOTHIC_OK;
 }
 
@@ -1196,8 +1206,14 @@ int gothic_sim_step(gothic_ctx *c, void *stream) {
     if (meter) meter_mark(c, cls, rebuild, tuning, picking);
   } else {
     sim_launch_predict(c, s);
-    rc = run_forces(c, sim_systems(S), S.shadow, nullptr, S.aold, S.anew, s, r_crit, cls, tuning,
-                    S.kmax, gsize, picking, true);
+    EvalOpts o;
+    o.meter_class = cls;
+    o.tuned = tuning;
+    o.picked = picking;
+    o.kmax = S.kmax;
+    o.group_G = gsize;
+    o.sign_active = true;
+    rc = run_forces(c, sim_systems(S), S.shadow, nullptr, S.aold, S.anew, s, r_crit, o);
     if (rc) return rc;
     if (c->tree.since == 1) ++S.builds;
     sim_launch_correct(c, s);

@@ -228,3 +228,33 @@ def test_captured_substeps_replay_the_launched_ones(batched):
     assert c1.stats()["flags"] == 0
     ms, k = c1.walk_time()
     assert k == 3 << kmax and ms > 0
+
+
+def test_tree_forces_inside_a_user_graph_capture():
+    """A caller captures one evaluation into its own HIP graph (after one
+    uncaptured call of the same size sized the scratch) and replays it on new
+    positions: every replay, with unrelated eager work and a synchronisation
+    in between, equals an eager evaluation of the same input bit for bit."""
+    n, eps, theta = 6000, 1 / 64, 0.5
+    xs = [ics.plummer(n, seed=s) for s in (91, 92, 93)]
+    say(f"[gpu] tree_forces captured by the caller, n={n}, 3 replays")
+    ctx = g.Context(device=0, multipole=2, check=0)
+    xt = torch.from_numpy(xs[0]).cuda()
+    out = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    ctx.tree_forces(xt, eps, theta, out=out)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.graph(graph, stream=side):
+        ctx.tree_forces(xt, eps, theta, out=out)
+    ref_ctx = g.Context(device=0, multipole=2)
+    for k, x in enumerate(xs + xs[:1]):
+        xt.copy_(torch.from_numpy(x).cuda())
+        out.fill_(float("nan"))
+        graph.replay()
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        ref = ref_ctx.tree_forces(torch.from_numpy(x).cuda(), eps, theta)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), k
+        assert float(junk) == float(junk)

@@ -199,3 +199,51 @@ def test_autotune_picks_group_size_per_class(graph):
     dx = np.abs(p1 - p0).max(1) / (np.abs(p0).max(1) + 1e-3)
     say(f"  position difference to the untuned run: p99 {np.percentile(dx, 99):.2e}")
     assert np.percentile(dx, 99) < 1e-3
+
+
+def test_group_sizes_with_batched_systems_and_errors():
+    """Per-class group sizes and their picking also drive a batched block-step
+    run (every system's groups use the class's size); bad arguments are
+    refused without changing anything."""
+    kmax = 3
+    x, offs, eps, v = ics.batched_systems(5, seed=87, lg_min=10, lg_max=13, with_vel=True)
+    say(f"[gpu] batched systems n={x.shape[0]}: autotune = 2, graph vs launched with one table")
+    runs = []
+    for graph in (0, 1):
+        ctx = g.Context(device=0, graph=graph)
+        pos = torch.from_numpy(x[:, :3].astype(np.float64)).cuda()
+        vel = torch.from_numpy(v.astype(np.float64)).cuda()
+        mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).cuda()
+        ctx.sim_bind_batched(pos, vel, mass, offs, eps, 0.5, eta=0.1, kmax=kmax)
+        ctx.set_params(check=0)
+        ctx.sim_set_group_sizes([16, 64, 8, 32])
+        runs.append((ctx, pos, vel))
+    for step in range(2 << kmax):
+        for ctx, _, _ in runs:
+            ctx.sim_step()
+        torch.cuda.synchronize()
+        (_, p0, v0), (_, p1, v1) = runs
+        assert torch.equal(p0, p1) and torch.equal(v0, v1), step
+    ctx = runs[1][0]
+    assert ctx.stats()["flags"] == 0
+    with pytest.raises(g.GothicError):
+        ctx.sim_set_group_sizes([0] * 33)  # more classes than there are
+    with pytest.raises(g.GothicError):
+        ctx.sim_set_group_sizes([32, 128])  # not a size the walk has
+    _, _, gs = ctx.sim_tuning(4, with_groups=True)
+    assert gs.tolist() == [16, 64, 8, 32]  # unchanged by the refused calls
+    with pytest.raises(g.GothicError):
+        ctx.sim_tuning(33)
+    # autotune = 2 on the batched run: sizes picked from the candidates
+    ctx2 = g.Context(device=0, graph=1, autotune=2)
+    pos = torch.from_numpy(x[:, :3].astype(np.float64)).cuda()
+    vel = torch.from_numpy(v.astype(np.float64)).cuda()
+    mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).cuda()
+    ctx2.sim_bind_batched(pos, vel, mass, offs, eps, 0.5, eta=0.1, kmax=kmax)
+    ctx2.set_params(check=0)
+    ctx2.sim_step(16 << kmax)
+    torch.cuda.synchronize()
+    assert ctx2.stats()["flags"] == 0
+    _, _, gs2 = ctx2.sim_tuning(kmax + 1, with_groups=True)
+    say(f"  picked group sizes per class {gs2.tolist()}")
+    assert set(gs2.tolist()) <= {8, 16, 32, 64}

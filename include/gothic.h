@@ -9,12 +9,20 @@
  *     (|r_j - r_i|^2 + eps^2)^{3/2} (G = 1) that the tree approximates;
  *   - Section 2.1: space-filling-curve keys, key sort, breadth-first octree,
  *     pseudo j-particles (mass, centre of mass, enclosing radius b_J);
- *   - Section 2.2: the opening-angle MAC b_J / d <= theta (Barnes & Hut);
+ *   - Section 2.2: the opening-angle MAC b_J / d <= theta (Barnes & Hut),
+ *     and the acceleration (Springel) and multipole (Warren & Salmon) MACs;
  *   - Section 2.3: groups of i-particles sharing one walk through a pseudo
  *     i-particle (r_I, b_I) with d = lambda r_JI, and a small interaction list
- *     flushed when full;
- *   - Section 2.5: several lanes per i-particle (ij-parallelisation);
- *   - Section 2.7: block time steps (only particles due at time t are active).
+ *     flushed when full; Appendix B: the five enclosing balls of the groups;
+ *   - Section 2.4: groups split at a critical separation r_crit, tuned by
+ *     Brent's method on the measured time;
+ *   - Section 2.5: several lanes per i-particle (ij-parallelisation), chosen
+ *     per sub-step class if asked (the per-step S left as future work in
+ *     Section 4);
+ *   - Section 2.6 and Appendix C: reuse of the tree until the growth models
+ *     of the walk time say a rebuild pays;
+ *   - Section 2.7: block time steps (only particles due at time t are active);
+ *   - Section 3.2: the float64 direct sum the force errors are measured against.
  *
  * Conventions for every call:
  *   - Particle arrays are DEVICE pointers owned by the caller.  The library
@@ -27,6 +35,11 @@
  *   - Not thread-safe per context: one context serves one host thread (and
  *     its calls run in stream order).
  *   - Units: G = 1.  Outputs are in the caller's particle order.
+ *   - Debugging aid: with the environment variable GOTHIC_POISON_ALLOC set
+ *     (to anything but "0") when a context grows its scratch, every new
+ *     floating-point scratch buffer is first filled with NaN bytes (and the
+ *     device synchronised), so results that depended on memory no kernel
+ *     wrote would show it.  Off by default; costs one fill per allocation.
  */
 #ifndef GOTHIC_H
 #define GOTHIC_H

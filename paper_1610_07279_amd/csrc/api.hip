@@ -2,11 +2,13 @@
 // management, argument checks, the kernel pipeline of one force evaluation,
 // and read-back of intermediate results for tests.
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <type_traits>
 
 #include "common.h"
 
@@ -109,6 +111,21 @@ __global__ void extract_groups_k(const Ctl *ctl, const uint32_t *gf, uint32_t *g
   }
 }
 
+// Debugging aid: with the environment variable GOTHIC_POISON_ALLOC set (to
+// anything but "0"), every new floating-point buffer starts as all-ones bytes
+// (NaN in every lane), so a kernel that reads memory no kernel of the
+// evaluation wrote gives visibly wrong results instead of results that depend
+// on what the memory held before.  Index buffers are left alone.
+template <class T>
+static constexpr bool kFloatBuffer =
+    std::is_floating_point<T>::value || std::is_same<T, float4>::value ||
+    std::is_same<T, float2>::value || std::is_same<T, double4>::value;
+
+static bool poison_alloc() {
+  const char *v = getenv("GOTHIC_POISON_ALLOC");
+  return v && v[0] && strcmp(v, "0") != 0;
+}
+
 template <class T>
 static int dev_alloc(T **p, int64_t count) {
   if (*p) {
@@ -120,6 +137,12 @@ static int dev_alloc(T **p, int64_t count) {
   if (e != hipSuccess) {
     *p = nullptr;
     return hip_check(e, "hipMalloc");
+  }
+  if (kFloatBuffer<T> && poison_alloc()) {
+    // synchronous, so no later launch on any stream can overtake it
+    if ((e = hipMemset(*p, 0xff, sizeof(T) * (size_t)count)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess)
+      return hip_check(e, "poison fill");
   }
   return GOTHIC_OK;
 }

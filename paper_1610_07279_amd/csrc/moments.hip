@@ -174,13 +174,16 @@ internal_moments_k(int l, Ctl *__restrict__ ctl, const uint32_t *__restrict__ ch
       inner = false;
     }
     const bool mine = inner && q < nc;  // this lane reads child q
+    // Lanes without a child read record 0, the root, which this pass writes
+    // last: it may hold anything (NaN included), so those lanes contribute
+    // through selects, never through a product with a zero weight.
     const float4 r0 = nrec[2 * (size_t)(inner ? cf : 0u)];
     const float4 r = nrec[2 * (size_t)(mine ? cf + q : 0u)];
     const float w = mine ? r.w : 0.f;
     const float M = seg_sum8(w);
-    const float sx = seg_sum8(w * (r.x - r0.x));
-    const float sy = seg_sum8(w * (r.y - r0.y));
-    const float sz = seg_sum8(w * (r.z - r0.z));
+    const float sx = seg_sum8(mine ? w * (r.x - r0.x) : 0.f);
+    const float sy = seg_sum8(mine ? w * (r.y - r0.y) : 0.f);
+    const float sz = seg_sum8(mine ? w * (r.z - r0.z) : 0.f);
     float cx = r0.x, cy = r0.y, cz = r0.z;
     if (M > 0.f) {
       cx = r0.x + sx / M;

@@ -10,7 +10,7 @@ import pytest
 
 import ics
 import oracle
-from gpu_util import rel_rms, run_gpu, say, tie_params
+from gpu_util import diagnose_forces, rel_rms, run_gpu, say, tie_params
 
 pytestmark = pytest.mark.gpu
 
@@ -147,6 +147,8 @@ def _check_forces(x, eps, theta, active=None, tol=1e-5, **params):
     ent = gg["entries"].astype(np.int64)
     say(f"  rms acc {e_acc:.2e} pot {e_pot:.2e} (tie groups {e_tie:.2e}); groups {cnt.shape[0]} "
         f"clean {clean.sum()}; interactions {st['interactions']}")
+    if not (e_acc <= tol and e_pot <= tol):
+        diagnose_forces(ctx, x, ref, out, ok)
     assert e_acc <= tol and e_pot <= tol
     assert e_tie <= 1e-2  # bounded by the truncation error of one node
     assert clean.mean() >= 0.9

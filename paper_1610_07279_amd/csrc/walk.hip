@@ -98,6 +98,48 @@ __device__ __forceinline__ int lanes_per_i(int S) {
 // so that with d = r_J - r_i, ri = 1/R, u = ri^2, s = 3 S d, w = 1.5 u d.S.d:
 //   a   += d ri^3 (M + u (5 w - 1.5 tr)) - u ri^3 s
 //   phi -= ri (M + u (w - 0.5 tr))
+
+// one monopole list entry j on the i-particle at pi
+__device__ __forceinline__ void mono_term(const float4 j, const float4 pi, float eps2, float &fx,
+                                          float &fy, float &fz, float &fp) {
+  const float dx = j.x - pi.x, dy = j.y - pi.y, dz = j.z - pi.z;
+  const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+  const float ri = __builtin_amdgcn_rsqf(r2);
+  const float mr = j.w * ri;
+  const float mr3 = mr * ri * ri;
+  fp += mr;
+  fx = fmaf(mr3, dx, fx);
+  fy = fmaf(mr3, dy, fy);
+  fz = fmaf(mr3, dz, fz);
+}
+
+// one quadrupole list entry (q0, q1, q2) on the i-particle at pi; with
+// v = u d.(3S).d = 2w the two uses of w become fused multiply-adds
+__device__ __forceinline__ void quad_term(const float4 q0, const float4 q1, const float4 q2,
+                                          const float4 pi, float eps2, float &fx, float &fy,
+                                          float &fz, float &fp) {
+  const float dx = q0.x - pi.x, dy = q0.y - pi.y, dz = q0.z - pi.z;
+  const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+  const float ri = __builtin_amdgcn_rsqf(r2);
+  const float u = ri * ri;
+  const float ri3 = ri * u;
+  // s = 3 S d   (q1 = 3(xx yy zz xy), q2 = 3(xz yz) | -tr/2, -3tr/2)
+  const float sx = fmaf(q1.x, dx, fmaf(q1.w, dy, q2.x * dz));
+  const float sy = fmaf(q1.w, dx, fmaf(q1.y, dy, q2.y * dz));
+  const float sz = fmaf(q2.x, dx, fmaf(q2.y, dy, q1.z * dz));
+  const float v = u * fmaf(dx, sx, fmaf(dy, sy, dz * sz));  // 3 u d.S.d = 2w
+  const float coef = ri3 * fmaf(u, fmaf(2.5f, v, q2.w), q0.w);
+  const float r5 = ri3 * u;
+  fx = fmaf(-r5, sx, fmaf(coef, dx, fx));
+  fy = fmaf(-r5, sy, fmaf(coef, dy, fy));
+  fz = fmaf(-r5, sz, fmaf(coef, dz, fz));
+  fp = fmaf(ri, fmaf(u, fmaf(0.5f, v, q2.z), q0.w), fp);
+}
+
+// The list is split into rounds of S entries, lane sub of an i-particle
+// taking entry round * S + sub.  Full rounds run under wave-uniform loop
+// control (scalar compare, immediate LDS offsets in the unrolled body); the
+// last partial round, if any, under per-lane control.
 template <int MULTI, int LOGS>
 __device__ __forceinline__ void flush(const WalkArgs &a, const float4 *pl, const float4 *ql,
                                       int np, int nq, float4 pi, float eps2, int sub, int S_rt,
@@ -105,41 +147,29 @@ __device__ __forceinline__ void flush(const WalkArgs &a, const float4 *pl, const
   wave_sync();
   const int S = lanes_per_i<LOGS>(S_rt);
   float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
-#pragma unroll 4
-  for (int k = sub; k < np; k += S) {
-    const float4 j = pl[k];
-    const float dx = j.x - pi.x, dy = j.y - pi.y, dz = j.z - pi.z;
-    const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-    const float ri = __builtin_amdgcn_rsqf(r2);
-    const float mr = j.w * ri;
-    const float mr3 = mr * ri * ri;
-    fp += mr;
-    fx = fmaf(mr3, dx, fx);
-    fy = fmaf(mr3, dy, fy);
-    fz = fmaf(mr3, dz, fz);
+  {
+    constexpr int U = 4;
+    const float4 *pj = pl + sub;
+    int k0 = 0;
+    for (; k0 + U * S <= np; k0 += U * S) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) mono_term(pj[k0 + u * S], pi, eps2, fx, fy, fz, fp);
+    }
+    for (int k = k0 + sub; k < np; k += S) mono_term(pl[k], pi, eps2, fx, fy, fz, fp);
   }
   if (MULTI == 2) {
-#pragma unroll 2
-    for (int k = sub; k < nq; k += S) {
-      const float4 q0 = ql[3 * k], q1 = ql[3 * k + 1], q2 = ql[3 * k + 2];
-      const float dx = q0.x - pi.x, dy = q0.y - pi.y, dz = q0.z - pi.z;
-      const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-      const float ri = __builtin_amdgcn_rsqf(r2);
-      const float u = ri * ri;
-      const float ri3 = ri * u;
-      // s = 3 S d   (q1 = 3(xx yy zz xy), q2 = 3(xz yz) | -tr/2, -3tr/2)
-      const float sx = fmaf(q1.x, dx, fmaf(q1.w, dy, q2.x * dz));
-      const float sy = fmaf(q1.w, dx, fmaf(q1.y, dy, q2.y * dz));
-      const float sz = fmaf(q2.x, dx, fmaf(q2.y, dy, q1.z * dz));
-      const float q3 = fmaf(dx, sx, fmaf(dy, sy, dz * sz));  // 3 d.S.d
-      const float w = (0.5f * u) * q3;                         // 1.5 u d.S.d
-      const float coef = ri3 * fmaf(u, fmaf(5.0f, w, q2.w), q0.w);
-      const float r5 = ri3 * u;
-      fx = fmaf(-r5, sx, fmaf(coef, dx, fx));
-      fy = fmaf(-r5, sy, fmaf(coef, dy, fy));
-      fz = fmaf(-r5, sz, fmaf(coef, dz, fz));
-      fp = fmaf(ri, fmaf(u, w + q2.z, q0.w), fp);
+    constexpr int U = 2;
+    const float4 *qj = ql + 3 * sub;
+    int k0 = 0;
+    for (; k0 + U * S <= nq; k0 += U * S) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const float4 *q = qj + 3 * (k0 + u * S);
+        quad_term(q[0], q[1], q[2], pi, eps2, fx, fy, fz, fp);
+      }
     }
+    for (int k = k0 + sub; k < nq; k += S)
+      quad_term(ql[3 * k], ql[3 * k + 1], ql[3 * k + 2], pi, eps2, fx, fy, fz, fp);
   }
   if (a.compensated) {
     neumaier(acc.x, acc.cx, fx);

@@ -36,7 +36,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3          # MI355X vector FP32, 256 CU x 2.4 GHz x 256 flop/clk
-                                  # (packed FP32; one non-packed FMA per lane-slot is half)
 FLOP_MONO = 24                    # per monopole interaction (20 + rsqrt weighted 4)
 FLOP_QUAD = 60                    # per quadrupole node interaction (operations of the factored
                                   # quadrupole term, rsq weighted 4)
@@ -521,8 +520,6 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": walk_traffic(),
-                     "peak_nonpacked": FP32_PEAK_TFLOPS / 2,
-                     "frac_nonpacked": achieved / (FP32_PEAK_TFLOPS / 2),
                      "kernel": "walk_k<2>", "flops_per_interaction": {"mono": FLOP_MONO,
                                                                        "quad": FLOP_QUAD}},
     }

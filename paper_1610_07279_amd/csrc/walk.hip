@@ -282,6 +282,13 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       pops += nb;
       const float4 r0 = a.nrec[2 * (size_t)node];
       const float4 r1 = a.nrec[2 * (size_t)node + 1];
+      // the second moments are read with the record, before the MAC decides
+      // whether they are needed, so the two loads share one wait
+      float4 s0 = make_float4(0.f, 0.f, 0.f, 0.f), s1 = s0;
+      if (MULTI == 2) {
+        s0 = a.quad[2 * (size_t)node];
+        s1 = a.quad[2 * (size_t)node + 1];
+      }
       const float dx = r0.x - bl.x, dy = r0.y - bl.y, dz = r0.z - bl.z;
       // the hardware square root (within 1 ulp): the MAC decision it feeds
       // is only sensitive far beyond that
@@ -325,7 +332,6 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
           }
           if (accept) {
             const int q = nq + (int)lanes_below(am);
-            const float4 s0 = a.quad[2 * (size_t)node], s1 = a.quad[2 * (size_t)node + 1];
             ql[3 * q] = r0;
             ql[3 * q + 1] = make_float4(3.f * s0.x, 3.f * s0.y, 3.f * s0.z, 3.f * s0.w);
             ql[3 * q + 2] = make_float4(3.f * s1.x, 3.f * s1.y, -0.5f * s1.z, -1.5f * s1.z);

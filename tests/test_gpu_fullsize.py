@@ -1,9 +1,9 @@
 """Parity at the workloads' full sizes, on outputs the oracle can afford.
 
 * NFW 2^24, eps 1/512, theta 0.5, quadrupole, in the launch configuration the
-  benchmark times (G = 32, r_crit = 0.5, list depth 384): bit-exact keys,
-  permutation and octree; forces of 48 sampled groups against the float64
-  tree.
+  benchmark times (G = 32, r_crit = 0.25, list depth 384, EBS balls): bit-exact
+  keys, permutation, octree and groups; forces of 48 sampled groups against
+  the float64 tree.
 * Galaxy-like model 2^22 (NFW halo + Hernquist bulge + exponential disk),
   eps 1/256, theta 0.5, monopole: plain FP32 and compensated accumulation
   against the float64 tree and the float64 direct sum on 4096 random
@@ -55,20 +55,25 @@ def _sampled_groups_parity(out, x, perm, tree, ps, mom, grp, eps, theta, multipo
 
 def test_nfw16m_bench_configuration():
     n, eps, theta = 1 << 24, 1 / 512, 0.5
-    say("[gpu] NFW 2^24 quadrupole, G=32, r_crit=0.5")
+    say("[gpu] NFW 2^24 quadrupole, G=32, r_crit=0.25, list depth 384, EBS balls")
     x = ics.nfw(n, seed=501)
-    ctx = g.Context(device=0, multipole=2, group_size=32, r_crit=0.5, list_depth=384)
+    ctx = g.Context(device=0, multipole=2, group_size=32, r_crit=0.25, list_depth=384,
+                    ball=oracle.BALL_EBS)
     out = ctx.tree_forces(torch.from_numpy(x).cuda(), eps, theta).cpu().numpy()
     ks, perm, cube = ctx.keys()
     t = ctx.tree()
     gg = ctx.groups()
     say("  oracle tree at 2^24")
-    ks_o, perm_o, tree, ps, mom, rc = _oracle_prep(x, 16, 32, 0.5)
+    ks_o, perm_o, tree, ps, mom, rc = _oracle_prep(x, 16, 32, 0.25)
     assert np.array_equal(ks, ks_o) and np.array_equal(perm, perm_o)
     for f in ("first", "count", "child_first", "n_child", "level"):
         assert np.array_equal(t[f], tree[f]), f
-    grp = oracle.groups(np.ones(n, np.uint8), ps, 32, rc)
+    grp = oracle.groups(np.ones(n, np.uint8), ps, 32, rc, oracle.BALL_EBS)
     assert np.array_equal(gg["first"], grp["first"]) and np.array_equal(gg["count"], grp["count"])
+    # EBS centres: float64 on both sides, rounded to float32 by the library
+    scale = np.abs(grp["ball"][:, :3]).max(1) + grp["ball"][:, 3]
+    close = np.abs(gg["ball"][:, :3] - grp["ball"][:, :3]).max(1) <= 1e-6 * scale
+    assert close.mean() >= 0.999
     rng = np.random.default_rng(5)
     ng = grp["first"].size
     sel = np.unique(np.r_[rng.choice(ng, 40, replace=False), np.argsort(-grp["ball"][:, 3])[:8]])

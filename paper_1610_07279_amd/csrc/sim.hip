@@ -147,8 +147,16 @@ sim_predict_k(int64_t n, unsigned nsys, const uint32_t *__restrict__ soff,
       cnt += due ? 1u : 0u;
     }
   }
+  // one atomic per workgroup instead of one per wave: every count lands on
+  // the same counter, and same-address atomics serialise
+  __shared__ unsigned wcnt[4];
   cnt = wave_sum(cnt);
-  if (lane_id() == 0 && cnt) atomicAdd(&sc->n_active, (unsigned long long)cnt);
+  if (lane_id() == 0) wcnt[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned t = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    if (t) atomicAdd(&sc->n_active, (unsigned long long)t);
+  }
 }
 
 __global__ void __launch_bounds__(256)

@@ -24,6 +24,8 @@ constexpr unsigned kFlagNodeOverflow = 2u;
 constexpr unsigned kFlagSpillOverflow = 4u;
 constexpr unsigned kFlagBadIndex = 8u;  // an index failed its range check (a bug)
 
+constexpr int kXworkStride = 32;  // unsigned words per claim counter (128 bytes)
+
 // Device-resident control block: every count the pipeline needs lives here so
 // no kernel launch depends on a host read-back.
 struct Ctl {
@@ -33,7 +35,10 @@ struct Ctl {
   unsigned n_groups;
   unsigned lvl_start[kMaxLevels + 2];  // nodes of level l: [lvl_start[l], lvl_start[l+1])
   unsigned nsys;                       // systems of the evaluation (roots 0 .. nsys-1)
-  unsigned xwork[8];                   // per-XCD group counters of the persistent walk
+  // per-XCD group counters of the persistent walk, one 128-byte line apart
+  // (counter x at index kXworkStride x) so that the XCDs' claims do not
+  // queue on one line
+  unsigned xwork[8 * kXworkStride];
   unsigned scan_total;                 // scratch: total of the last scan
   unsigned tree_ok;                    // the last build finished without overflow
   unsigned pad1;

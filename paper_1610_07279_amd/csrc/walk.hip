@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       const unsigned lo = (unsigned)(((unsigned long long)xr * ng) / kXcds);
       const unsigned hi = (unsigned)(((unsigned long long)(xr + 1) * ng) / kXcds);
       const unsigned cl =
-          __builtin_amdgcn_readfirstlane(atomicAdd(&ctl->xwork[xr], lane == 0 ? 1u : 0u));
+          __builtin_amdgcn_readfirstlane(atomicAdd(&ctl->xwork[kXworkStride * xr], lane == 0 ? 1u : 0u));
       if (lo + cl < hi) {
         g = lo + cl;
         break;

@@ -4,8 +4,10 @@ Each pin is fixed by physics or mathematics, not by the oracle itself:
 closed forms (two bodies, a symmetric cube of masses, the Plummer sphere's
 enclosed mass), Newton's third law (momentum), the tree reducing to the direct
 sum when the opening angle is zero, mass closure of every interaction list,
-the truncation error falling with theta, and the multipole orders of the
-monopole and quadrupole terms (error ~ (b/d)^2 and (b/d)^3).
+the truncation error falling with theta, the multipole orders of the
+monopole and quadrupole terms (error ~ (b/d)^2 and (b/d)^3, in the
+acceleration and in the potential), and the binomial series of a symmetric
+pair of masses, whose b^4 term is the quadrupole node's residual.
 """
 import numpy as np
 import pytest
@@ -224,3 +226,99 @@ def test_multipole_mac_error_scales_with_delta():
         assert np.median(err) <= delta
         assert np.median(err) < prev
         prev = np.median(err)
+
+
+# ---------------------------------------------------------------- quadrupole closed forms
+def _pair_node(D, b, along):
+    """An i-particle at (D, 0, 0) and two masses m = 1/2 at -b and +b along
+    `along` (0 = x, the line of sight; 2 = z, across it), far enough that the
+    pair is one level-1 node accepted whole (theta 0.9, groups of one)."""
+    xyzm = np.zeros((3, 4), np.float32)
+    xyzm[0] = (D, 0.0, 0.0, 1.0)
+    xyzm[1, along] = -b
+    xyzm[2, along] = b
+    xyzm[1:, 3] = 0.5
+    act = np.array([1, 0, 0], np.uint8)
+    return xyzm, act
+
+
+def _tree_and_direct(xyzm, act, eps, multipole):
+    r = oracle.tree_forces(xyzm, eps, 0.9, active=act, n_leaf=1, group_size=1,
+                           multipole=multipole)
+    # the pair's node and the i-particle's own one-particle leaf
+    assert r["counts"][0, 0] == 2 and r["counts"][0, 1] == 0
+    d = oracle.direct(xyzm, eps, idx=np.array([0]))
+    return r["acc_pot"][0], d[0]
+
+
+@pytest.mark.parametrize("D", [8.0, 16.0, 32.0])
+def test_quadrupole_pair_across_the_line_of_sight_closed_form(D):
+    # Two masses m at (0, 0, +-b) seen from (D, 0, 0) with softening eps:
+    # exactly  phi = -2m (R^2 + b^2)^(-1/2),  a_x = -2m D (R^2 + b^2)^(-3/2),
+    # R^2 = D^2 + eps^2.  The second-order expansion of the softened kernel
+    # about the centre of mass keeps the b^2 terms, so the tree's residual is
+    # the b^4 term of the binomial series:
+    #   phi_exact - phi_tree = -(3/4) m b^4 / R^5,
+    #   a_exact  - a_tree    = -(15/4) m b^4 D / R^7   (each + O(b^6)).
+    # A wrong sign or factor of the trace term leaves a b^2 residual instead.
+    m, b, eps = 0.5, 0.25, 1.0 / 64
+    xyzm, act = _pair_node(D, b, along=2)
+    t, d = _tree_and_direct(xyzm, act, eps, multipole=2)
+    R = np.sqrt(D * D + eps * eps)
+    assert np.isclose(d[3], -2 * m / np.sqrt(R * R + b * b), rtol=1e-14)
+    assert np.isclose(d[0], -2 * m * D / (R * R + b * b) ** 1.5, rtol=1e-14)
+    next_phi = 15.0 / 16 * m * b ** 6 / R ** 7   # size of the b^6 term
+    next_acc = 105.0 / 16 * m * b ** 6 * D / R ** 9
+    assert abs((d[3] - t[3]) - (-0.75 * m * b ** 4 / R ** 5)) <= 2 * next_phi
+    assert abs((d[0] - t[0]) - (-3.75 * m * b ** 4 * D / R ** 7)) <= 2 * next_acc
+    assert t[1] == 0.0 and t[2] == 0.0
+
+
+def test_quadrupole_pair_along_the_line_of_sight_error_order():
+    # Two masses on the line of sight (the y.S.y term is nonzero): the pair
+    # has no dipole (centre of mass) and no octupole (symmetric), so the
+    # quadrupole node's error in a and phi falls as (b/D)^4; the monopole's
+    # as (b/D)^2.
+    b, eps = 0.25, 1.0 / 64
+    Ds = (8.0, 16.0, 32.0)
+    for multipole, order in ((1, 2), (2, 4)):
+        ea, ep = [], []
+        for D in Ds:
+            xyzm, act = _pair_node(D, b, along=0)
+            t, d = _tree_and_direct(xyzm, act, eps, multipole)
+            ea.append(abs(t[0] - d[0]) / abs(d[0]))
+            ep.append(abs(t[3] - d[3]) / abs(d[3]))
+        for errs in (ea, ep):
+            slopes = np.diff(np.log(errs)) / np.diff(np.log(Ds))
+            assert np.all(np.abs(slopes + order) < 0.2), (multipole, slopes)
+
+
+@pytest.mark.parametrize("multipole,order", [(1, 2), (2, 3)])
+def test_multipole_potential_error_order(multipole, order):
+    # An unequal pair on the line of sight: 3/4 at x = -s and 1/4 at x = +3s
+    # (centre of mass at 0) seen from (D, 0, 0).  Its multipole series along
+    # that line is -(1/D)(1 + 3 (s/D)^2 + 6 (s/D)^3 + ...): the octupole term
+    # is nonzero, so the relative potential error of a monopole node falls as
+    # (s/D)^2 and that of a quadrupole node as (s/D)^3.
+    s, eps = 0.25, 1.0 / 64
+    Ds = (8.0, 16.0, 32.0)
+    errs = []
+    for D in Ds:
+        xyzm = np.array([[D, 0, 0, 1.0], [-s, 0, 0, 0.75], [3 * s, 0, 0, 0.25]], np.float32)
+        act = np.array([1, 0, 0], np.uint8)
+        t, d = _tree_and_direct(xyzm, act, eps, multipole)
+        errs.append(abs(t[3] - d[3]) / abs(d[3]))
+    slopes = np.diff(np.log(errs)) / np.diff(np.log(Ds))
+    assert np.all(np.abs(slopes + order) < 0.2), slopes
+
+
+def test_quadrupole_potential_beats_monopole():
+    xyzm = ics.nfw(8192, seed=31)
+    xyzm[:, 3] *= np.random.default_rng(32).uniform(0.5, 1.5, 8192).astype(np.float32)
+    d = oracle.direct(xyzm, 1.0 / 128)
+
+    def phi_err(mp):
+        p = oracle.tree_forces(xyzm, 1.0 / 128, 0.5, multipole=mp)["acc_pot"][:, 3]
+        return np.sqrt(((p - d[:, 3]) ** 2).sum() / (d[:, 3] ** 2).sum())
+
+    assert phi_err(2) < 0.5 * phi_err(1)

@@ -283,3 +283,55 @@ def test_cmp_ball_is_the_smaller_of_geo_and_com():
     assert np.array_equal(cmp_[use_com], com[use_com])
     assert np.array_equal(cmp_[~use_com], geo[~use_com])
     assert 0 < use_com.mean() < 1
+
+
+# ---------------------------------------------------------------- balls worked by hand
+def _one_group(pts, masses):
+    """All points active, one group, in the given order (they are passed as
+    already key-sorted positions)."""
+    ps = np.zeros((len(pts), 4))
+    ps[:, :3] = pts
+    ps[:, 3] = masses
+    return ps, np.ones(len(pts), np.uint8)
+
+
+def test_com_ball_is_mass_weighted():
+    # masses 1 and 3 at x = 0 and x = 4: the centre of mass is x = 3 (not the
+    # plain mean 2), radius 3
+    ps, act = _one_group([[0, 0, 0], [4, 0, 0]], [1.0, 3.0])
+    b = oracle.groups(act, ps, 2, 0.0, oracle.BALL_COM)["ball"][0]
+    assert np.allclose(b, [3, 0, 0, 3], rtol=0, atol=1e-15)
+    # 3-D: masses 1, 1, 2 at (0,0,0), (2,0,0), (0,2,0): centre (1/2, 1, 0),
+    # farthest member (2,0,0) at sqrt(9/4 + 1)
+    ps, act = _one_group([[0, 0, 0], [2, 0, 0], [0, 2, 0]], [1.0, 1.0, 2.0])
+    b = oracle.groups(act, ps, 4, 0.0, oracle.BALL_COM)["ball"][0]
+    assert np.allclose(b, [0.5, 1.0, 0.0, np.sqrt(3.25)], rtol=0, atol=1e-15)
+    # CMP keeps GEO here: the bounding-box ball (centre (1, 1, 0), radius
+    # sqrt 2) is smaller than the COM ball
+    c = oracle.groups(act, ps, 4, 0.0, oracle.BALL_CMP)["ball"][0]
+    assert np.allclose(c, [1, 1, 0, np.sqrt(2)], rtol=0, atol=1e-15)
+    # and takes COM when that is smaller: equal masses at (0,0,0), (4,0,0),
+    # (2,3,0): COM (2, 1, 0) radius sqrt 5 < GEO (2, 1.5, 0) radius 2.5
+    ps, act = _one_group([[0, 0, 0], [4, 0, 0], [2, 3, 0]], [1.0, 1.0, 1.0])
+    c = oracle.groups(act, ps, 4, 0.0, oracle.BALL_CMP)["ball"][0]
+    assert np.allclose(c, [2, 1, 0, np.sqrt(5)], rtol=0, atol=1e-15)
+
+
+def test_ebs_ball_worked_by_hand():
+    # Ritter's sphere.  Members in order: P0 (0,0,0), P1 (6,0,0), P2 (3,4,0),
+    # P3 (3,0.5,-5).  Farthest from P0 is P1 (36 against 25 and 34.25);
+    # farthest from P1 is P0.  Start: centre (3,0,0), radius 3.
+    # P2 lies 4 > 3 out: the grown sphere is the smallest one holding the old
+    # sphere and P2, i.e. tangent to the old one on the far side and passing
+    # through P2: radius (3 + 4)/2 = 3.5, centre P2 + (c - P2) 3.5/4 =
+    # (3, 0.5, 0).  P3 then lies 5 > 3.5 out: radius (3.5 + 5)/2 = 4.25,
+    # centre P3 + (c - P3) 4.25/5 = (3, 0.5, -0.75).  The ball's radius is the
+    # largest member distance from that centre, P3's 4.25.
+    pts = [[0, 0, 0], [6, 0, 0], [3, 4, 0], [3, 0.5, -5]]
+    ps, act = _one_group(pts, [1.0] * 4)
+    b = oracle.groups(act, ps, 4, 0.0, oracle.BALL_EBS)["ball"][0]
+    assert np.allclose(b, [3, 0.5, -0.75, 4.25], rtol=0, atol=1e-12)
+    # without P3 the sphere stops after the first growth
+    ps, act = _one_group(pts[:3], [1.0] * 3)
+    b = oracle.groups(act, ps, 4, 0.0, oracle.BALL_EBS)["ball"][0]
+    assert np.allclose(b, [3, 0.5, 0, 3.5], rtol=0, atol=1e-12)

@@ -78,6 +78,7 @@ def run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, shared, steps, warmup)
     torch.cuda.synchronize()
     ctx.sim_reset_counters()
     ctx.walk_time()
+    ctx.clear_flags()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.sim_step(steps)
@@ -85,10 +86,11 @@ def run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, shared, steps, warmup)
     t1 = time.perf_counter()
     info = ctx.sim_info()
     walk_ms, launches = ctx.walk_time()
-    st = ctx.stats()
-    if st["flags"]:
-        raise RuntimeError(f"device flags {st['flags']} set during the timed steps")
-    return dict(seconds=t1 - t0, info=info, walk_ms=walk_ms, walk_launches=launches)
+    st = ctx._stats_raw()
+    if st["sticky_flags"]:  # any sub-step of the timed window, not only the last
+        raise RuntimeError(f"device flags {st['sticky_flags']} set during the timed steps")
+    return dict(seconds=t1 - t0, info=info, walk_ms=walk_ms, walk_launches=launches,
+                pos=pos.cpu().numpy().astype(np.float32))
 
 
 def batched_bench(cycles=1, kmax=6):
@@ -125,7 +127,7 @@ def batched_bench(cycles=1, kmax=6):
     torch.cuda.synchronize()
     t_b = time.perf_counter() - t0
     info = ctx.sim_info()
-    if ctx.stats()["flags"]:
+    if ctx._stats_raw()["sticky_flags"]:
         raise RuntimeError("device flags set in the batched steps")
 
     ctxs, keep = [], []
@@ -186,34 +188,67 @@ def batched_bench(cycles=1, kmax=6):
                                      "speedup": f_s / f_b}}
 
 
-def cpu_baseline(x, eps, theta, multipole, group_size, n_leaf, r_crit, target_s=15.0):
-    """The float64 oracle walk on a random sample of the groups of the same
-    all-active system (its tree preparation is not timed)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(x, state, eps, theta, multipole, group_size, n_leaf, r_crit, ball, kmax,
+                 window, target_s=15.0):
+    """The float64 oracle walk on the workload of the timed block sub-steps:
+    the particles (positions at the end of the timed run), their levels and
+    last update sub-steps give the due sets of the next `window` sub-steps (no
+    level changes assumed); random groups drawn uniformly from all groups of
+    those sub-steps (r_crit, ball as the GPU run) are walked by the oracle
+    until about target_s seconds; tree, moments and groups are not timed."""
     import oracle
+    lev, last, s_now = state
     t0 = time.perf_counter()
     k, _ = oracle.keys(x, 0)
     ks, perm = oracle.sort(k)
     tree = oracle.build(ks, n_leaf)
     ps = x[perm].astype(np.float64)
     mom = oracle.moments(tree, ps)
-    grp = oracle.groups(np.ones(x.shape[0], np.uint8), ps, group_size, float(np.float32(r_crit)))
+    rc = float(np.float32(r_crit))
+    per = []  # the groups of each sub-step (sub-steps with the same due set share them)
+    seen = {}
+    step = np.left_shift(1, kmax - lev.astype(np.int64))
+    for t in range(s_now + 1, s_now + 1 + window):
+        due = ((t - last) % step == 0) & (t > last)
+        key = hash(np.packbits(due).tobytes())
+        if key not in seen:
+            seen[key] = oracle.groups(due[perm].astype(np.uint8), ps, group_size, rc, ball)
+        per.append(seen[key])
     prep = time.perf_counter() - t0
-    ng = grp["first"].size
-    rng = np.random.default_rng(7)
-    nsel, spent, inter, done = 32, 0.0, 0, 0
-    while spent < target_s and done < ng:
-        sel = rng.choice(ng, size=min(nsel, ng), replace=False)
-        t = time.perf_counter()
-        _, cnt, _ = oracle.walk(tree, mom, ps, grp, eps, theta, multipole, gsel=sel)
-        spent += time.perf_counter() - t
-        inter += int(((cnt[sel, 0] + cnt[sel, 1]) * grp["count"][sel]).sum())
-        done += sel.size
-        nsel *= 2
+    counts = np.array([p["first"].size for p in per], np.int64)
+    ends = np.cumsum(counts)
+    order = np.random.default_rng(7).permutation(int(ends[-1]))
+    spent, inter, done, batch = 0.0, 0, 0, 32
+    while spent < target_s and done < order.size:
+        pick = order[done:done + batch]
+        which = np.searchsorted(ends, pick, side="right")
+        for w in np.unique(which):
+            sel = pick[which == w] - (ends[w] - counts[w])
+            grp = per[w]
+            t = time.perf_counter()
+            _, cnt, _ = oracle.walk(tree, mom, ps, grp, eps, theta, multipole, gsel=sel)
+            spent += time.perf_counter() - t
+            inter += int(((cnt[sel, 0] + cnt[sel, 1]) * grp["count"][sel]).sum())
+        done += pick.size
+        batch *= 2
     return dict(value=inter / spent, unit="interactions/s", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"float64 oracle walk of {done} random groups ({group_size} i-particles "
-                       f"each) of the all-active step, {inter:.3e} interactions in {spent:.1f} s; "
-                       f"tree preparation ({prep:.1f} s) not timed")
+                kind="oracle", cpu=cpu_model(),
+                sample=f"float64 oracle walk of {done} groups drawn at random from the "
+                       f"{int(counts.sum())} groups of the next {window} block sub-steps' due "
+                       f"sets (G {group_size}, r_crit {r_crit}, ball {ball}, quadrupole), "
+                       f"{inter:.3e} interactions in {spent:.1f} s on "
+                       f"{oracle.num_threads()} threads of {cpu_model()}; tree and groups "
+                       f"({prep:.1f} s) not timed")
 
 
 def rel_error(tree, ref):
@@ -476,6 +511,11 @@ def main():
 
     log(f"bench: block steps (warmup {args.warmup}, timed {args.steps})")
     blk = run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, False, args.steps, args.warmup)
+    # the state the CPU baseline's due sets come from (end of the block run)
+    _, lev_end, last_end = ctx.sim_state()
+    state_end = (lev_end, last_end, blk["info"]["substep"])
+    x_end = x.copy()
+    x_end[:, :3] = blk["pos"]
     log(f"bench: block {blk['seconds'] / args.steps * 1e3:.2f} ms/step, "
         f"{blk['info']['interactions_total'] / blk['seconds']:.3e} interactions/s, levels "
         f"{[c for c in blk['info']['level_count'] if c]}")
@@ -491,6 +531,7 @@ def main():
     flops = FLOP_MONO * (inter - quad) + FLOP_QUAD * quad
     walk_s = blk["walk_ms"] / 1e3
     achieved = flops / walk_s / 1e12 if walk_s > 0 else 0.0
+
     out = {
         "metric": METRIC,
         "value": inter / blk["seconds"],
@@ -513,15 +554,26 @@ def main():
                    "parallelism": "single GPU"},
         "block": {"s_per_step": blk["seconds"] / args.steps,
                   "interactions_per_s": inter / blk["seconds"],
+                  "interactions": inter,
+                  "quad_node_interactions": quad,
+                  "mono_interactions": inter - quad,
                   "active_per_step": ib["active_total"] / args.steps,
                   "level_count": ib["level_count"][:kmax + 1],
                   "tree_builds": ib["tree_builds"],
+                  "walk_launches": blk["walk_launches"],
                   "walk_ms_per_step": blk["walk_ms"] / max(blk["walk_launches"], 1)},
+        # achieved = (mono x 24 + quad x 60) flop / (walk launches x walk_ms_mean),
+        # the walk timed by HIP events around every launch on its own stream
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": walk_traffic(),
-                     "kernel": "walk_k<2>", "flops_per_interaction": {"mono": FLOP_MONO,
-                                                                       "quad": FLOP_QUAD}},
+                     "traffic_source": "profiles/walk_nfw16m_hbm_traffic.md: rocprofv3 "
+                                       "FETCH_SIZE + WRITE_SIZE per walk launch, scaled by a "
+                                       "copy kernel; null unless the walk source is the one "
+                                       "the counters were taken on",
+                     "kernel": "walk_k<2>", "flops": flops,
+                     "walk_ms_mean": blk["walk_ms"] / max(blk["walk_launches"], 1),
+                     "flops_per_interaction": {"mono": FLOP_MONO, "quad": FLOP_QUAD}},
     }
     if shd is not None:
         inter_s = shd["info"]["interactions_total"]
@@ -537,8 +589,9 @@ def main():
             f"serial {out['batched']['serial_64_contexts_ms_per_substep']:.2f}")
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(x, eps, theta, multipole, args.group_size, 16,
-                                           args.r_crit)
+        out["cpu_baseline"] = cpu_baseline(x_end, state_end, eps, theta, multipole,
+                                           args.group_size, 16, args.r_crit, args.ball, kmax,
+                                           args.steps)
     print(json.dumps(out), flush=True)
 
 

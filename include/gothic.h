@@ -153,6 +153,16 @@ typedef struct {
                          not fit are abandoned on the device, the arrays grow
                          (at least 2x) and the evaluation repeats (check
                          mode). */
+  int64_t max_scratch_bytes; /* cap on the device scratch one context holds, in
+                         bytes; 0 = no cap.  A call that would grow the scratch
+                         past it returns GOTHIC_ENOMEM, and gothic_get_scratch
+                         reports the size it needed */
+  int spill_per_wave; /* initial capacity of each walk wave's global pending-node
+                         stack (Section 2.3 keeps the pending nodes of a walk in
+                         small buffers), in entries: 0 = 16384, else 256..2^24.
+                         A walk that outgrows it drops the children it cannot
+                         hold and sets the frontier-overflow flag; check mode
+                         then grows it 4x and repeats the evaluation */
 } gothic_params;
 
 /* Statistics of the last force evaluation (filled by gothic_get_stats). */
@@ -172,6 +182,12 @@ typedef struct {
                              internal index check failed) */
   int32_t n_systems;      /* non-empty systems of the evaluation (1 unless
                              batched) */
+  int32_t sticky_flags;   /* the flags above ORed over every evaluation of the
+                             context since its creation or the last
+                             gothic_clear_flags() (repeats after growing in
+                             check mode excepted: their first attempt's
+                             overflow was handled); with check = 0 this is how
+                             an overflow in any but the last evaluation shows */
 } gothic_stats;
 
 /* Default tunables (see gothic_params). */
@@ -372,6 +388,15 @@ int gothic_sim_set_group_sizes(gothic_ctx *c, int nclass, const int *group_size)
 /* Counts of the last evaluation; synchronises the stream of that call. */
 int gothic_get_stats(gothic_ctx *c, gothic_stats *out);
 
+/* Clear the sticky flags (and those of the last evaluation) on `stream`. */
+int gothic_clear_flags(gothic_ctx *c, void *stream);
+
+/* Device scratch: *held = bytes the context holds now; *required = bytes a
+ * refused call needed (GOTHIC_ECAPTURE under stream capture, or GOTHIC_ENOMEM
+ * from params.max_scratch_bytes), 0 after a call that did not need to grow.
+ * Either pointer may be NULL.  Host-side only; never synchronises. */
+int gothic_get_scratch(gothic_ctx *c, int64_t *held, int64_t *required);
+
 /*
  * Introspection of the last evaluation, for bit-exact tests.  All outputs are
  * caller-owned DEVICE buffers sized from gothic_get_stats; any pointer may be
@@ -392,11 +417,36 @@ int gothic_get_stats(gothic_ctx *c, gothic_stats *out);
  *     entries of the group's walk)
  */
 int gothic_get_keys(gothic_ctx *c, uint64_t *keys_sorted, uint32_t *perm, double *cube);
-int gothic_get_tree(gothic_ctx *c, uint32_t *first, uint32_t *count, uint32_t *child_first,
-                    uint8_t *n_child, uint8_t *level);
+int gothic_get_tree(gothic_ctx *c, int64_t *n_nodes, uint32_t *first, uint32_t *count,
+                    uint32_t *child_first, uint8_t *n_child, uint8_t *level);
 int gothic_get_nodes(gothic_ctx *c, float *com_m, float *b, float *quad);
-int gothic_get_groups(gothic_ctx *c, uint32_t *alist, uint32_t *gfirst, uint32_t *gcount,
-                      float *ball, uint32_t *entries);
+int gothic_get_groups(gothic_ctx *c, int64_t *n_active, int64_t *n_groups, uint32_t *alist,
+                      uint32_t *gfirst, uint32_t *gcount, float *ball, uint32_t *entries);
+/* (n_nodes, n_active, n_groups: HOST int64 out-parameters, NULL skips.) */
+
+/*
+ * Interaction lists of chosen groups of the last evaluation (Sections 2.2-2.3:
+ * the nodes a group's walk accepted as pseudo j-particles and the leaves it
+ * opened into their particles), for checking the walk's decisions.  The walk
+ * of each listed group is run again on the stored tree, groups and positions
+ * with the same kernel code, so its decisions and forces are those of the
+ * evaluation.
+ *   ngsel    number of groups, 0..2^20; gsel HOST uint32 [ngsel] group indices
+ *            (< n_groups of the last evaluation)
+ *   cap      entries kept per group (1..2^26)
+ *   entries  DEVICE uint32 [ngsel][cap]: per group, in the order decided, an
+ *            accepted node J as J and an opened leaf J as J | 0x80000000
+ *            (node indices as in gothic_get_tree); entries past cap are
+ *            counted but not stored
+ *   counts   DEVICE uint32 [ngsel][2]: accepted nodes, opened leaves
+ *   acc_pot  DEVICE float [n][4]: the rows of the listed groups' particles are
+ *            written (the same values the evaluation wrote)
+ * Not for the scratch-free entry point's evaluations.  Synchronises.  Returns
+ * EINVAL for bad arguments or no evaluation, EOVERFLOW when the last
+ * evaluation overflowed.
+ */
+int gothic_get_lists(gothic_ctx *c, int64_t ngsel, const uint32_t *gsel, int64_t cap,
+                     uint32_t *entries, uint32_t *counts, float *acc_pot);
 
 /* Message of the last failed call on this host thread ("" if none). */
 const char *gothic_last_error(void);

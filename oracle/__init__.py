@@ -52,7 +52,9 @@ def _load():
     lib.orc_groups.argtypes = [i64, P, P, i32, f64, P, P, P, P, i32]
     lib.orc_seb.argtypes = [i32, P, P]
     lib.orc_walk.argtypes = [i64, P, P, P, P, P, P, P, P, P, i64, P, P, P,
-                             f64, f64, i32, f64, f64, P, i64, P, P, P, i32, f64, P]
+                             f64, f64, i32, f64, f64, P, i64, P, P, P, i32, f64, P, P, i64, P]
+    lib.orc_walk_replay.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, f64, f64, i32, f64,
+                                    f64, i32, f64, P, i64, P, P, i64, P, P, P, P, P]
     _lib = lib
     return lib
 
@@ -162,9 +164,11 @@ def seb(pts: np.ndarray):
 
 
 def walk(tree, mom, ps, grp, eps, theta, multipole=1, tie_rel=1e-5, tie_abs=0.0,
-         gsel=None, mac=0, delta=0.0, amag=None):
+         gsel=None, mac=0, delta=0.0, amag=None, lists_cap=0):
     """mac 0: opening angle theta; 1: acceleration MAC with accuracy delta and
-    amag = |a_old| of every particle in key order; 2: Warren-Salmon with delta."""
+    amag = |a_old| of every particle in key order; 2: Warren-Salmon with delta.
+    lists_cap > 0 (with gsel) also returns each selected group's list as
+    (accepted node indices, opened leaf indices)."""
     com, b, S = mom
     if mac == 1:
         amag = np.ascontiguousarray(amag, dtype=np.float64)
@@ -175,6 +179,9 @@ def walk(tree, mom, ps, grp, eps, theta, multipole=1, tie_rel=1e-5, tie_abs=0.0,
     mass = np.zeros(max(ng, 1), np.float64)
     if gsel is not None:
         gsel = np.ascontiguousarray(gsel, dtype=np.int64)
+    want_lists = lists_cap > 0 and gsel is not None
+    lists = np.zeros((gsel.size if want_lists else 1, max(lists_cap, 1)), np.uint32)
+    lcount = np.zeros((gsel.size if want_lists else 1, 2), np.uint32)
     _load().orc_walk(tree["first"].size, _p(tree["first"]), _p(tree["count"]),
                      _p(tree["child_first"]), _p(tree["n_child"]), _p(com), _p(b), _p(S),
                      _p(ps), _p(grp["alist"]), ng, _p(grp["first"]), _p(grp["count"]),
@@ -182,7 +189,16 @@ def walk(tree, mom, ps, grp, eps, theta, multipole=1, tie_rel=1e-5, tie_abs=0.0,
                      float(tie_rel), float(tie_abs),
                      _p(gsel) if gsel is not None else None,
                      0 if gsel is None else gsel.size, _p(out), _p(cnt), _p(mass),
-                     int(mac), float(delta), _p(amag) if mac == 1 else None)
+                     int(mac), float(delta), _p(amag) if mac == 1 else None,
+                     _p(lists) if want_lists else None, int(lists_cap), _p(lcount))
+    if want_lists:
+        got = []
+        for q in range(gsel.size):
+            nl, nf = int(lcount[q, 0]), int(lcount[q, 1])
+            if nl + nf > lists_cap:
+                raise ValueError("lists_cap too small")
+            got.append((lists[q, :nl].copy(), lists[q, nl:nl + nf] & 0x7fffffff))
+        return out, cnt[:ng], mass[:ng], got
     return out, cnt[:ng], mass[:ng]
 
 
@@ -227,3 +243,45 @@ def direct(xyzm, eps, idx=None):
     out = np.zeros((idx.size, 4), np.float64)
     _load().orc_direct(n, _p(xyzm), float(eps), idx.size, _p(idx), _p(out))
     return out
+
+
+def walk_replay(ref, gsel, lists, eps, theta, multipole=1, tie_rel=1e-5, tie_abs=0.0, mac=0,
+                delta=0.0, acc_old=None):
+    """Check another walk's interaction lists for the groups gsel of the
+    float64 evaluation `ref` (the dict of tree_forces): lists[k] = (accepted
+    node indices, opened leaf indices) of group gsel[k].  The tree is walked
+    again following those decisions and each is compared with the float64
+    MAC.  Returns (out [n,4] float64 forces of the listed groups' particles
+    from the given lists, in the caller's order, NaN elsewhere; info [k,6]:
+    visited, decisions differing inside the near-tie window, differing
+    outside it, entries never reached, inconsistent entries, list entries;
+    mass [k] summed mass of each list)."""
+    t = ref["tree"]
+    grp = ref["groups"]
+    ps = ref["ps"]
+    n = ps.shape[0]
+    gsel = np.ascontiguousarray(gsel, dtype=np.int64)
+    k = gsel.size
+    cap = max([a.size + b.size for a, b in lists] + [1])
+    ent = np.zeros((max(k, 1), cap), np.uint32)
+    nent = np.zeros((max(k, 1), 2), np.uint32)
+    for q, (acc_nodes, leaves) in enumerate(lists):
+        ent[q, :acc_nodes.size] = acc_nodes
+        ent[q, acc_nodes.size:acc_nodes.size + leaves.size] = leaves.astype(np.uint32) | 0x80000000
+        nent[q] = (acc_nodes.size, leaves.size)
+    amag = np.zeros(1)
+    if mac == 1:
+        a3 = np.asarray(acc_old, np.float64)[:, :3]
+        amag = np.ascontiguousarray(np.sqrt((a3 * a3).sum(1))[ref["perm"]])
+    out = np.full((n, 4), np.nan, np.float64)
+    info = np.zeros((max(k, 1), 6), np.int64)
+    mass = np.zeros(max(k, 1), np.float64)
+    _load().orc_walk_replay(t["first"].size, _p(t["first"]), _p(t["count"]), _p(t["child_first"]),
+                            _p(t["n_child"]), _p(ref["com"]), _p(ref["b"]), _p(ref["S"]), _p(ps),
+                            _p(grp["alist"]), _p(grp["first"]), _p(grp["count"]), _p(grp["ball"]),
+                            float(eps), float(theta), int(multipole), float(tie_rel),
+                            float(tie_abs), int(mac), float(delta), _p(amag), k, _p(gsel), None,
+                            cap, _p(ent), _p(nent), _p(out), _p(info), _p(mass))
+    acc = np.full((n, 4), np.nan, np.float64)
+    acc[ref["perm"]] = out
+    return acc, info[:k], mass[:k]

@@ -610,7 +610,8 @@ void orc_walk(int64_t nn, const uint32_t *first, const uint32_t *count,
               const uint32_t *gfirst, const uint32_t *gcount, const double *ball,
               double eps, double theta, int multipole, double tie_rel, double tie_abs,
               const int64_t *gsel, int64_t ngsel, double *out, int64_t *cnt,
-              double *mass, int mac, double delta, const double *amag) {
+              double *mass, int mac, double delta, const double *amag,
+              uint32_t *lists, int64_t lcap, uint32_t *lcount) {
   const double e2 = eps * eps;
   const int64_t nsel = gsel ? ngsel : ng;
 #pragma omp parallel
@@ -619,6 +620,7 @@ void orc_walk(int64_t nn, const uint32_t *first, const uint32_t *count,
     uint32_t *lst = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nn > 0 ? nn : 1));
     size_t cap_p = 1024;
     uint32_t *plst = (uint32_t *)malloc(sizeof(uint32_t) * cap_p);
+    uint32_t *leaf_of_entry = (uint32_t *)malloc(sizeof(uint32_t) * cap_p);
 #pragma omp for schedule(dynamic, 4)
     for (int64_t t = 0; t < nsel; ++t) {
       const int64_t g = gsel ? gsel[t] : t;
@@ -659,8 +661,12 @@ void orc_walk(int64_t nn, const uint32_t *first, const uint32_t *count,
           if ((size_t)(np + count[J]) > cap_p) {
             while ((size_t)(np + count[J]) > cap_p) cap_p *= 2;
             plst = (uint32_t *)realloc(plst, sizeof(uint32_t) * cap_p);
+            leaf_of_entry = (uint32_t *)realloc(leaf_of_entry, sizeof(uint32_t) * cap_p);
           }
-          for (uint32_t j = first[J]; j < first[J] + count[J]; ++j) plst[np++] = j;
+          for (uint32_t j = first[J]; j < first[J] + count[J]; ++j) {
+            leaf_of_entry[np] = J;
+            plst[np++] = j;
+          }
         } else {
           for (uint32_t c = 0; c < n_child[J]; ++c) q[qt++] = child_first[J] + c;
         }
@@ -669,6 +675,15 @@ void orc_walk(int64_t nn, const uint32_t *first, const uint32_t *count,
       for (int64_t k = 0; k < nl; ++k) msum += com[4 * lst[k] + 3];
       for (int64_t k = 0; k < np; ++k) msum += ps[4 * plst[k] + 3];
       cnt[3 * g] = nl; cnt[3 * g + 1] = np; cnt[3 * g + 2] = ties;
+      if (lists) {  /* the list itself: accepted nodes, then opened leaves | bit 31 */
+        int64_t w = 0, nleaf = 0;
+        for (int64_t k = 0; k < nl; ++k, ++w)
+          if (w < lcap) lists[t * lcap + w] = lst[k];
+        for (int64_t k = 0; k < np; k += (int64_t)count[leaf_of_entry[k]], ++nleaf, ++w)
+          if (w < lcap) lists[t * lcap + w] = leaf_of_entry[k] | 0x80000000u;
+        lcount[2 * t] = (uint32_t)nl;
+        lcount[2 * t + 1] = (uint32_t)nleaf;
+      }
       mass[g] = msum;
       for (uint32_t a = gfirst[g]; a < gfirst[g] + gcount[g]; ++a) {
         const uint32_t i = alist[a];
@@ -687,6 +702,119 @@ void orc_walk(int64_t nn, const uint32_t *first, const uint32_t *count,
         for (int c = 0; c < 4; ++c) out[4 * (int64_t)i + c] = acc[c];
       }
     }
-    free(q); free(lst); free(plst);
+    free(q); free(lst); free(plst); free(leaf_of_entry);
   }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Check of another implementation's walk decisions (Sections 2.2-2.3), for
+ * groups where single- and double-precision MAC decisions may legitimately
+ * differ.  For each selected group g its interaction list is given as the
+ * set of accepted nodes and the set of opened leaves (entries[k*cap ..],
+ * nent[2k] accepted then nent[2k+1] leaves in any order; a leaf entry has bit
+ * 31 set).  The tree is walked again from the group's root (groot[k], or node
+ * 0 when groot is NULL), following the GIVEN decisions; at every visited node
+ * the float64 MAC decision is taken as in orc_walk and compared:
+ *   info[6k+0]  nodes visited
+ *   info[6k+1]  decisions that differ from float64 inside the near-tie window
+ *   info[6k+2]  decisions that differ outside it (an error)
+ *   info[6k+3]  entries never reached by the walk (an error)
+ *   info[6k+4]  inconsistent entries (a leaf neither accepted nor opened, an
+ *               internal node listed as an opened leaf, a duplicate) (an error)
+ *   info[6k+5]  list entries
+ * mass[k] = summed mass of the list (mass closure); out[n][4] (sorted order)
+ * = the float64 forces of the group's particles from the GIVEN list.          */
+void orc_walk_replay(int64_t nn, const uint32_t *first, const uint32_t *count,
+                     const uint32_t *child_first, const uint8_t *n_child,
+                     const double *com, const double *b, const double *S,
+                     const double *ps, const uint32_t *alist, const uint32_t *gfirst,
+                     const uint32_t *gcount, const double *ball, double eps, double theta,
+                     int multipole, double tie_rel, double tie_abs, int mac, double delta,
+                     const double *amag, int64_t ngsel, const int64_t *gsel,
+                     const uint32_t *groot, int64_t cap, const uint32_t *entries,
+                     const uint32_t *nent, double *out, int64_t *info, double *mass) {
+  const double e2 = eps * eps;
+  uint8_t *mark = (uint8_t *)calloc((size_t)(nn > 0 ? nn : 1), 1);
+  uint32_t *q = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nn > 0 ? nn : 1));
+  uint32_t *lst = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nn > 0 ? nn : 1));
+  uint32_t *lf = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nn > 0 ? nn : 1));
+  for (int64_t k = 0; k < ngsel; ++k) {
+    const int64_t g = gsel[k];
+    int64_t *inf = info + 6 * k;
+    for (int c = 0; c < 6; ++c) inf[c] = 0;
+    const uint32_t *e = entries + k * cap;
+    const int64_t ne = (int64_t)nent[2 * k] + (int64_t)nent[2 * k + 1];
+    inf[5] = ne;
+    for (int64_t t = 0; t < ne; ++t) {
+      const uint32_t J = e[t] & 0x7fffffffu;
+      const uint8_t want = (e[t] & 0x80000000u) ? 2 : 1;
+      if (J >= (uint64_t)nn || mark[J]) { ++inf[4]; continue; }
+      mark[J] = want;
+    }
+    const double rI[3] = {ball[4 * g], ball[4 * g + 1], ball[4 * g + 2]};
+    const double bI = ball[4 * g + 3];
+    double amin = INFINITY;
+    if (mac == 1)
+      for (uint32_t a = gfirst[g]; a < gfirst[g] + gcount[g]; ++a)
+        if (amag[alist[a]] < amin) amin = amag[alist[a]];
+    int64_t qh = 0, qt = 0, nl = 0, np = 0, used = 0;
+    if (nn > 0) q[qt++] = groot ? groot[k] : 0;
+    while (qh < qt) {
+      const uint32_t J = q[qh++];
+      ++inf[0];
+      const double dx = com[4 * J] - rI[0], dy = com[4 * J + 1] - rI[1], dz = com[4 * J + 2] - rI[2];
+      const double rJI = sqrt(dx * dx + dy * dy + dz * dz);
+      const double d = ((bI < rJI) ? 1.0 - bI / rJI : 0.0) * rJI;
+      const double td = theta * d;
+      const double big = b[J] > td ? b[J] : td;
+      const double scale = fabs(com[4 * J]) + fabs(com[4 * J + 1]) + fabs(com[4 * J + 2]) +
+                           fabs(rI[0]) + fabs(rI[1]) + fabs(rI[2]) + bI;
+      const double B2 = S[6 * J] + S[6 * J + 1] + S[6 * J + 2];
+      const int acc = mac_accept(mac, d, b[J], com[4 * J + 3], B2, theta, delta, amin);
+      int tie;
+      if (mac == 0) {
+        tie = b[J] > 0 && fabs(b[J] - td) <= tie_rel * big + tie_abs * scale;
+      } else {
+        const double dlo = d * (1.0 - tie_rel) - tie_abs * scale;
+        const double dhi = d * (1.0 + tie_rel) + tie_abs * scale;
+        tie = mac_accept(mac, dlo > 0 ? dlo : 0, b[J], com[4 * J + 3], B2, theta, delta, amin) !=
+              mac_accept(mac, dhi, b[J], com[4 * J + 3], B2, theta, delta, amin);
+      }
+      const int given = mark[J];
+      const int given_acc = given == 1;
+      if (given) ++used;
+      mark[J] = 0;
+      if (given == 2 && n_child[J] != 0) ++inf[4];
+      if (given == 0 && n_child[J] == 0) { ++inf[4]; continue; }
+      if (given_acc != acc) ++inf[tie ? 1 : 2];
+      if (given_acc) lst[nl++] = J;
+      else if (n_child[J] == 0) lf[np++] = J;
+      else
+        for (uint32_t c = 0; c < n_child[J]; ++c) q[qt++] = child_first[J] + c;
+    }
+    inf[3] = ne - inf[4] - used;
+    for (int64_t t = 0; t < ne; ++t)
+      if ((e[t] & 0x7fffffffu) < (uint64_t)nn) mark[e[t] & 0x7fffffffu] = 0;
+    double msum = 0;
+    for (int64_t t = 0; t < nl; ++t) msum += com[4 * lst[t] + 3];
+    for (int64_t t = 0; t < np; ++t)
+      for (uint32_t j = first[lf[t]]; j < first[lf[t]] + count[lf[t]]; ++j) msum += ps[4 * j + 3];
+    mass[k] = msum;
+    for (uint32_t a = gfirst[g]; a < gfirst[g] + gcount[g]; ++a) {
+      const uint32_t i = alist[a];
+      const double yi[3] = {ps[4 * i], ps[4 * i + 1], ps[4 * i + 2]};
+      double acc4[4] = {0, 0, 0, 0};
+      for (int64_t t = 0; t < nl; ++t) {
+        const uint32_t J = lst[t];
+        pair_mono(yi, com + 4 * J, com[4 * J + 3], e2, acc4);
+        if (multipole == 2) pair_quad(yi, com + 4 * J, S + 6 * J, e2, acc4);
+      }
+      for (int64_t t = 0; t < np; ++t)
+        for (uint32_t j = first[lf[t]]; j < first[lf[t]] + count[lf[t]]; ++j)
+          pair_mono(yi, ps + 4 * j, ps[4 * j + 3], e2, acc4);
+      acc4[3] += ps[4 * i + 3] / eps; /* remove the self pair's -m_i/eps */
+      for (int c = 0; c < 4; ++c) out[4 * (int64_t)i + c] = acc4[c];
+    }
+  }
+  free(mark); free(q); free(lst); free(lf);
 }

@@ -35,7 +35,8 @@ class Params(C.Structure):
                 ("check", C.c_int), ("timing", C.c_int), ("r_crit", C.c_float),
                 ("graph", C.c_int), ("autotune", C.c_int), ("rebuild_interval", C.c_int),
                 ("mac", C.c_int), ("mac_delta", C.c_float), ("ball", C.c_int),
-                ("node_capacity", C.c_int64)]
+                ("node_capacity", C.c_int64), ("max_scratch_bytes", C.c_int64),
+                ("spill_per_wave", C.c_int)]
 
 
 class TuneResult(C.Structure):
@@ -51,7 +52,7 @@ class Stats(C.Structure):
                 ("n_groups", C.c_int64), ("n_levels", C.c_int64), ("node_entries", C.c_int64),
                 ("part_entries", C.c_int64), ("interactions", C.c_int64),
                 ("node_interactions", C.c_int64), ("mac_tests", C.c_int64),
-                ("flags", C.c_int32), ("n_systems", C.c_int32)]
+                ("flags", C.c_int32), ("n_systems", C.c_int32), ("sticky_flags", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -89,9 +90,12 @@ def _load():
     lib.gothic_direct_forces.argtypes = [P, i64, P, f32, i64, P, P, P]
     lib.gothic_get_stats.argtypes = [P, C.POINTER(Stats)]
     lib.gothic_get_keys.argtypes = [P, P, P, P]
-    lib.gothic_get_tree.argtypes = [P, P, P, P, P, P]
+    lib.gothic_get_tree.argtypes = [P, P, P, P, P, P, P]
     lib.gothic_get_nodes.argtypes = [P, P, P, P]
-    lib.gothic_get_groups.argtypes = [P, P, P, P, P, P]
+    lib.gothic_get_groups.argtypes = [P, P, P, P, P, P, P, P]
+    lib.gothic_get_lists.argtypes = [P, i64, P, i64, P, P, P]
+    lib.gothic_get_scratch.argtypes = [P, P, P]
+    lib.gothic_clear_flags.argtypes = [P, P]
     lib.gothic_get_walk_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(i64)]
     lib.gothic_sim_bind.argtypes = [P, i64, P, P, P, f32, f32, C.c_double, i32, i32, P]
     lib.gothic_sim_bind_batched.argtypes = [P, i32, P, P, P, P, P, P, C.c_double, i32, i32, P]
@@ -105,7 +109,8 @@ def _load():
     lib.gothic_sim_get_state.argtypes = [P, P, P, P]
     for name in ("gothic_create", "gothic_destroy", "gothic_set_params", "gothic_get_params",
                  "gothic_tree_forces", "gothic_tree_forces_batched", "gothic_tree_forces_ex",
-                 "gothic_get_stats",
+                 "gothic_get_stats", "gothic_get_lists", "gothic_get_scratch",
+                 "gothic_clear_flags",
                  "gothic_get_keys", "gothic_get_tree", "gothic_get_nodes", "gothic_get_groups",
                  "gothic_get_walk_time", "gothic_sim_bind", "gothic_sim_bind_batched",
                  "gothic_sim_step", "gothic_sim_reset_counters", "gothic_sim_get_info",
@@ -139,11 +144,29 @@ def default_params() -> Params:
 _FLOAT_PARAMS = ("r_crit", "mac_delta")
 
 
-def _check_acc_old(acc_old, n):
+def _need(t, name, dtype, shape, device):
+    """ValueError unless t is a contiguous `dtype` tensor of `shape` (None in a
+    dimension: any size) on the GPU `device` (a torch.device).  Every pointer
+    the library receives goes through here first: a host or other-device
+    tensor would otherwise reach the kernels as a wild address."""
+    if t is None:
+        raise ValueError(f"{name} is required")
+    shp = tuple(t.shape)
+    if t.dtype != dtype or len(shp) != len(shape) or any(
+            w is not None and w != g for w, g in zip(shape, shp)):
+        want = ",".join("*" if w is None else str(w) for w in shape)
+        raise ValueError(f"{name} must be a {dtype} [{want}] tensor (got {t.dtype} {list(shp)})")
+    if not t.is_cuda or t.device != device:
+        raise ValueError(f"{name} must be on {device} (got {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _check_acc_old(acc_old, n, device):
     import torch
-    if acc_old is not None and (acc_old.dtype != torch.float32 or tuple(acc_old.shape) != (n, 4)
-                                or not acc_old.is_cuda or not acc_old.is_contiguous()):
-        raise ValueError("acc_old must be a contiguous float32 [n,4] GPU tensor")
+    if acc_old is not None:
+        _need(acc_old, "acc_old", torch.float32, (n, 4), device)
 
 
 def _ptr(t):
@@ -205,19 +228,7 @@ class Context:
         """acc_pot [n,4] float32 (ax, ay, az, phi) for the active rows of xyzm;
         acc_old [n,4] (previous accelerations) feeds the acceleration MAC."""
         import torch
-        if xyzm.dtype != torch.float32 or xyzm.dim() != 2 or xyzm.shape[1] != 4:
-            raise ValueError("xyzm must be a float32 [n,4] tensor")
-        if not xyzm.is_cuda or not xyzm.is_contiguous():
-            raise ValueError("xyzm must be a contiguous GPU tensor")
-        n = xyzm.shape[0]
-        if active is not None:
-            if active.dtype != torch.uint8 or active.shape != (n,) or not active.is_cuda \
-                    or not active.is_contiguous():
-                raise ValueError("active must be a contiguous uint8 [n] GPU tensor")
-        if out is None:
-            out = torch.zeros((n, 4), dtype=torch.float32, device=xyzm.device)
-        elif out.dtype != torch.float32 or out.shape != (n, 4) or not out.is_contiguous():
-            raise ValueError("out must be a contiguous float32 [n,4] tensor")
+        n, out = self._forces_args(xyzm, active, out)
         s = _stream_of(xyzm, stream)
         self._last_stream = s
         if acc_old is None:
@@ -228,24 +239,38 @@ class Context:
                                             stream=stream, acc_old=acc_old)
         return out
 
+    @property
+    def torch_device(self):
+        import torch
+        return torch.device("cuda", self.device)
+
+    def _forces_args(self, xyzm, active, out):
+        """Check xyzm [n,4], active [n] and out [n,4] (allocated if None): all on
+        this context's GPU.  Returns (n, out)."""
+        import torch
+        dev = self.torch_device
+        _need(xyzm, "xyzm", torch.float32, (None, 4), dev)
+        n = xyzm.shape[0]
+        if active is not None:
+            _need(active, "active", torch.uint8, (n,), dev)
+        if out is None:
+            out = torch.zeros((n, 4), dtype=torch.float32, device=dev)
+        _need(out, "out", torch.float32, (n, 4), dev)
+        return n, out
+
     def direct_forces(self, xyzm, eps: float, idx=None, out=None, stream=None):
         """float64 [ni,4] (ax, ay, az, phi) by direct summation over all of
         xyzm for the targets idx (int64 GPU tensor; None = every particle)."""
         import torch
-        if xyzm.dtype != torch.float32 or xyzm.dim() != 2 or xyzm.shape[1] != 4:
-            raise ValueError("xyzm must be a float32 [n,4] tensor")
-        if not xyzm.is_cuda or not xyzm.is_contiguous():
-            raise ValueError("xyzm must be a contiguous GPU tensor")
+        dev = self.torch_device
+        _need(xyzm, "xyzm", torch.float32, (None, 4), dev)
         n = xyzm.shape[0]
         if idx is not None:
-            if idx.dtype != torch.int64 or idx.dim() != 1 or not idx.is_cuda \
-                    or not idx.is_contiguous():
-                raise ValueError("idx must be a contiguous int64 [ni] GPU tensor")
+            _need(idx, "idx", torch.int64, (None,), dev)
         ni = n if idx is None else idx.shape[0]
         if out is None:
-            out = torch.empty((ni, 4), dtype=torch.float64, device=xyzm.device)
-        elif out.dtype != torch.float64 or out.shape != (ni, 4) or not out.is_contiguous():
-            raise ValueError("out must be a contiguous float64 [ni,4] tensor")
+            out = torch.empty((ni, 4), dtype=torch.float64, device=dev)
+        _need(out, "out", torch.float64, (ni, 4), dev)
         s = _stream_of(xyzm, stream)
         self._last_stream = s
         _check(lib.gothic_direct_forces(self._h, n, _ptr(xyzm), float(eps), ni, _ptr(idx),
@@ -267,24 +292,11 @@ class Context:
                             acc_old=None):
         """Forces of nsys independent systems in one evaluation: system s owns rows
         offsets[s]:offsets[s+1] of xyzm (eps, theta: scalars or one per system)."""
-        import torch
         offs, nsys, e, t = self._systems(offsets, eps, theta)
-        if xyzm.dtype != torch.float32 or xyzm.dim() != 2 or xyzm.shape[1] != 4:
-            raise ValueError("xyzm must be a float32 [n,4] tensor")
-        if not xyzm.is_cuda or not xyzm.is_contiguous():
-            raise ValueError("xyzm must be a contiguous GPU tensor")
-        n = xyzm.shape[0]
+        n, out = self._forces_args(xyzm, active, out)
         if offs[-1] != n:
             raise ValueError("offsets[-1] must equal the number of rows of xyzm")
-        if active is not None:
-            if active.dtype != torch.uint8 or active.shape != (n,) or not active.is_cuda \
-                    or not active.is_contiguous():
-                raise ValueError("active must be a contiguous uint8 [n] GPU tensor")
-        if out is None:
-            out = torch.zeros((n, 4), dtype=torch.float32, device=xyzm.device)
-        elif out.dtype != torch.float32 or out.shape != (n, 4) or not out.is_contiguous():
-            raise ValueError("out must be a contiguous float32 [n,4] tensor")
-        _check_acc_old(acc_old, n)
+        _check_acc_old(acc_old, n, self.torch_device)
         s = _stream_of(xyzm, stream)
         self._last_stream = s
         _check(lib.gothic_tree_forces_ex(
@@ -299,19 +311,12 @@ class Context:
         returns the result dict (evaluations = 0 for a cached bucket).  out
         receives the forces of a final checked evaluation."""
         import numpy as np
-        import torch
-        n = xyzm.shape[0]
+        n, out = self._forces_args(xyzm, active, out)
         if offsets is None:
             offsets = np.array([0, n], np.int64)
         offs, nsys, e, t = self._systems(offsets, eps, theta)
-        if xyzm.dtype != torch.float32 or xyzm.dim() != 2 or xyzm.shape[1] != 4 or \
-                not xyzm.is_cuda or not xyzm.is_contiguous() or offs[-1] != n:
-            raise ValueError("xyzm must be a contiguous float32 [n,4] GPU tensor covering offsets")
-        if active is not None and (active.dtype != torch.uint8 or active.shape != (n,)
-                                   or not active.is_cuda or not active.is_contiguous()):
-            raise ValueError("active must be a contiguous uint8 [n] GPU tensor")
-        if out is None:
-            out = torch.zeros((n, 4), dtype=torch.float32, device=xyzm.device)
+        if offs[-1] != n:
+            raise ValueError("offsets[-1] must equal the number of rows of xyzm")
         res = TuneResult()
         s = _stream_of(xyzm, stream)
         self._last_stream = s
@@ -325,11 +330,11 @@ class Context:
         """Bind float64 [n,3] pos/vel and float32 [n] mass (GPU tensors, updated in
         place by sim_step) and compute the t = 0 forces and levels."""
         import torch
+        dev = self.torch_device
+        _need(pos, "pos", torch.float64, (None, 3), dev)
         n = pos.shape[0]
-        for t, dt, shp in ((pos, torch.float64, (n, 3)), (vel, torch.float64, (n, 3)),
-                           (mass, torch.float32, (n,))):
-            if t.dtype != dt or tuple(t.shape) != shp or not t.is_cuda or not t.is_contiguous():
-                raise ValueError("pos/vel must be float64 [n,3], mass float32 [n], contiguous GPU")
+        _need(vel, "vel", torch.float64, (n, 3), dev)
+        _need(mass, "mass", torch.float32, (n,), dev)
         self._sim_keep = (pos, vel, mass)
         self._sim_nsys = 1
         s = _stream_of(pos, stream)
@@ -343,11 +348,11 @@ class Context:
         with its own softening, opening angle and time-step hierarchy."""
         import torch
         offs, nsys, e, t = self._systems(offsets, eps, theta)
+        dev = self.torch_device
+        _need(pos, "pos", torch.float64, (None, 3), dev)
         n = pos.shape[0]
-        for a, dt, shp in ((pos, torch.float64, (n, 3)), (vel, torch.float64, (n, 3)),
-                           (mass, torch.float32, (n,))):
-            if a.dtype != dt or tuple(a.shape) != shp or not a.is_cuda or not a.is_contiguous():
-                raise ValueError("pos/vel must be float64 [n,3], mass float32 [n], contiguous GPU")
+        _need(vel, "vel", torch.float64, (n, 3), dev)
+        _need(mass, "mass", torch.float32, (n,), dev)
         if offs[-1] != n:
             raise ValueError("offsets[-1] must equal the number of rows of pos")
         self._sim_keep = (pos, vel, mass)
@@ -454,7 +459,11 @@ class Context:
         cf = torch.empty(m, dtype=torch.int32, device=dev)
         nc = torch.empty(m, dtype=torch.uint8, device=dev)
         lv = torch.empty(m, dtype=torch.uint8, device=dev)
-        _check(lib.gothic_get_tree(self._h, _ptr(f), _ptr(c), _ptr(cf), _ptr(nc), _ptr(lv)))
+        nn_out = C.c_int64()
+        _check(lib.gothic_get_tree(self._h, C.byref(nn_out), _ptr(f), _ptr(c), _ptr(cf), _ptr(nc),
+                                   _ptr(lv)))
+        if nn_out.value != nn:
+            raise GothicError(EINVAL, "node count changed between calls")
         u = lambda t: t[:nn].cpu().numpy().view("uint32")
         return dict(first=u(f), count=u(c), child_first=u(cf), n_child=nc[:nn].cpu().numpy(),
                     level=lv[:nn].cpu().numpy())
@@ -481,11 +490,55 @@ class Context:
         gc = torch.empty(max(ng, 1), dtype=torch.int32, device=dev)
         ball = torch.empty((max(ng, 1), 4), dtype=torch.float32, device=dev)
         ent = torch.empty((max(ng, 1), 2), dtype=torch.int32, device=dev)
-        _check(lib.gothic_get_groups(self._h, _ptr(al), _ptr(gf), _ptr(gc), _ptr(ball),
-                                     _ptr(ent)))
+        na_out, ng_out = C.c_int64(), C.c_int64()
+        _check(lib.gothic_get_groups(self._h, C.byref(na_out), C.byref(ng_out), _ptr(al),
+                                     _ptr(gf), _ptr(gc), _ptr(ball), _ptr(ent)))
+        if (na_out.value, ng_out.value) != (na, ng):
+            raise GothicError(EINVAL, "group counts changed between calls")
         u = lambda t, k: t[:k].cpu().numpy().view("uint32")
         return dict(alist=u(al, na), first=u(gf, ng), count=u(gc, ng),
                     ball=ball[:ng].cpu().numpy(), entries=u(ent, ng))
+
+
+    def lists(self, groups, cap: int = 1 << 16):
+        """Interaction lists of the given groups of the last evaluation: a list of
+        (nodes uint32 array, leaves uint32 array) per group (accepted pseudo
+        j-particles and opened leaves, node indices as in tree()), and the
+        [n,4] float32 forces the re-walk wrote for those groups' particles
+        (NaN elsewhere)."""
+        import numpy as np
+        import torch
+        gsel = np.ascontiguousarray(groups, dtype=np.uint32)
+        k = gsel.size
+        dev = self.torch_device
+        n = self._stats_raw()["n"]
+        ent = torch.empty((max(k, 1), cap), dtype=torch.int32, device=dev)
+        cnt = torch.empty((max(k, 1), 2), dtype=torch.int32, device=dev)
+        acc = torch.full((max(n, 1), 4), float("nan"), dtype=torch.float32, device=dev)
+        _check(lib.gothic_get_lists(self._h, k, gsel.ctypes.data_as(C.c_void_p), cap, _ptr(ent),
+                                    _ptr(cnt), _ptr(acc)))
+        e = ent.cpu().numpy().view("uint32")
+        c = cnt.cpu().numpy().view("uint32")
+        out = []
+        for q in range(k):
+            tot = int(c[q, 0]) + int(c[q, 1])
+            if tot > cap:
+                raise ValueError(f"group {gsel[q]} has {tot} list entries, more than cap {cap}")
+            row = e[q, :tot]
+            leaf = (row & 0x80000000) != 0
+            out.append((row[~leaf].copy(), (row[leaf] & 0x7fffffff).copy()))
+        return out, acc[:n].cpu().numpy()
+
+    def scratch(self):
+        """(bytes held, bytes a refused call needed) of this context's scratch."""
+        held, req = C.c_int64(), C.c_int64()
+        _check(lib.gothic_get_scratch(self._h, C.byref(held), C.byref(req)))
+        return held.value, req.value
+
+    def clear_flags(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.torch_device)
+        _check(lib.gothic_clear_flags(self._h, C.c_void_p(s.cuda_stream)))
 
 
 _default_ctx = {}

@@ -23,6 +23,7 @@ constexpr unsigned kFlagNonFinite = 1u;
 constexpr unsigned kFlagNodeOverflow = 2u;
 constexpr unsigned kFlagSpillOverflow = 4u;
 constexpr unsigned kFlagBadIndex = 8u;  // an index failed its range check (a bug)
+constexpr unsigned kFlagMask = 15u;
 
 constexpr int kXworkStride = 32;  // unsigned words per claim counter (128 bytes)
 
@@ -30,15 +31,17 @@ constexpr int kXworkStride = 32;  // unsigned words per claim counter (128 bytes
 // no kernel launch depends on a host read-back.
 struct Ctl {
   unsigned flags;
+  unsigned sticky;                     // flags of earlier evaluations, ORed (kept by resets)
   unsigned n_nodes;
   unsigned n_active;
   unsigned n_groups;
   unsigned lvl_start[kMaxLevels + 2];  // nodes of level l: [lvl_start[l], lvl_start[l+1])
   unsigned nsys;                       // systems of the evaluation (roots 0 .. nsys-1)
-  // per-XCD group counters of the persistent walk, one 128-byte line apart
-  // (counter x at index kXworkStride x) so that the XCDs' claims do not
-  // queue on one line
-  unsigned xwork[8 * kXworkStride];
+  // per-XCD group counters of the persistent walk, each on a 128-byte line
+  // of its own (counter x at index kXworkStride x, the first line after the
+  // fields above) so that the XCDs' claims neither queue on one line nor
+  // share one with the fields every wave reads
+  alignas(128) unsigned xwork[8 * kXworkStride];
   unsigned scan_total;                 // scratch: total of the last scan
   unsigned tree_ok;                    // the last build finished without overflow
   unsigned pad1;
@@ -102,8 +105,14 @@ struct Buffers {
   uint32_t *hist = nullptr;       // radix histograms
   uint32_t *part = nullptr;       // scan partials
   float *bbox_part = nullptr;     // bbox partials
-  // walk spill area
+  // walk spill area (per wave: the older part of the pending-node stack)
   uint32_t *spill = nullptr;
+  // per-group list read-back (gothic_get_lists): work list of groups and
+  // the recorded entries; null outside that call
+  const uint32_t *gsel = nullptr;
+  unsigned ngsel = 0;
+  uint32_t *rec = nullptr, *rec_n = nullptr;
+  int64_t rec_cap = 0;
   // systems (capacity cap_sys)
   SysRec *sys = nullptr;
   uint32_t *soff = nullptr;       // [nsys + 1] particle offsets
@@ -111,6 +120,14 @@ struct Buffers {
   Ctl *ctl = nullptr;
   Ctl *ctl_host = nullptr;        // pinned mirror for read-back
   float *rcrit = nullptr;         // r_crit of the evaluation (device, set before each one)
+};
+
+// The systems of one evaluation, non-empty ones only (host side).
+struct Systems {
+  int nsys = 0;
+  int64_t n = 0, max_n = 0;
+  std::vector<int64_t> off;  // nsys + 1
+  std::vector<float> eps, theta;
 };
 
 // Block-step driver state on the device (sim.hip)
@@ -214,6 +231,9 @@ struct gothic_ctx {
   int slots_multi = 0, slots_D = 0;
   int cur_G = 32;                 // group size of the evaluation being enqueued
   gothic::Buffers b;
+  gothic::Buffers *lb = nullptr;  // buffers of the last evaluation (b, or the static scratch's)
+  int64_t scratch_held = 0;       // device scratch bytes held by b
+  int64_t scratch_required = 0;   // bytes a refused call needed (ECAPTURE / ENOMEM), else 0
   uint64_t generation = 1;        // bumped whenever a device buffer or a parameter changes
   uint64_t buffers = 1;           // bumped whenever a device buffer is (re)allocated
   // last evaluation

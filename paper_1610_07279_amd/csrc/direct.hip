@@ -7,7 +7,9 @@
 // along y in chunks of whole 256-particle tiles staged through LDS.  Each
 // (target, chunk) pair writes one float64 partial; a second kernel adds the
 // chunks of a target in chunk order, so the result does not depend on timing.
-#include "common.h"
+#include <cmath>
+
+#include "api_internal.h"
 
 namespace gothic {
 namespace {
@@ -102,3 +104,44 @@ void launch_direct(int64_t n, const float4 *xyzm, double eps, int64_t ni, const 
 }
 
 }  // namespace gothic
+
+using namespace gothic;
+
+extern "C" {
+
+int gothic_direct_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps, int64_t ni,
+                         const int64_t *idx, double *acc_pot, void *stream) {
+  if (!c) return set_error(GOTHIC_EINVAL, "context is NULL");
+  if (n < 0 || n >= (int64_t)1 << 31) return set_error(GOTHIC_EINVAL, "n must be in [0, 2^31)");
+  if (!(eps > 0.f) || !std::isfinite(eps)) return set_error(GOTHIC_EINVAL, "eps must be finite and > 0");
+  if (ni < 0 || ni >= (int64_t)1 << 31) return set_error(GOTHIC_EINVAL, "ni must be in [0, 2^31)");
+  if (ni == 0) return GOTHIC_OK;
+  if (n == 0) return set_error(GOTHIC_EINVAL, "targets need particles (n = 0)");
+  if (!idx && ni > n) return set_error(GOTHIC_EINVAL, "without idx, ni must be <= n");
+  if (!xyzm || !acc_pot) return set_error(GOTHIC_EINVAL, "xyzm and acc_pot must not be NULL");
+  DeviceGuard guard(c->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int nchunk;
+  int64_t chunk;
+  direct_plan(n, ni, &nchunk, &chunk);
+  const int64_t want = (int64_t)nchunk * ni;
+  int rc;
+  if (want > c->cap_direct) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    (void)hipStreamIsCapturing(s, &cap);
+    if (cap != hipStreamCaptureStatusNone)
+      return set_error(GOTHIC_ECAPTURE, "direct-sum scratch must grow; call once uncaptured first");
+    if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
+    if ((rc = dev_alloc(&c->direct_part, want))) {
+      c->cap_direct = 0;
+      return rc;
+    }
+    c->cap_direct = want;
+  }
+  launch_direct(n, reinterpret_cast<const float4 *>(xyzm), (double)eps, ni, idx, c->direct_part,
+                acc_pot, s);
+  return hip_check(hipGetLastError(), "direct-sum launch");
+}
+
+
+}  // extern "C"

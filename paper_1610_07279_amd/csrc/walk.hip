@@ -68,7 +68,17 @@ struct WalkArgs {
   int G, logG, D, DQ;
   int wave_bytes;
   int compensated;
+  // list read-back: the groups gsel[0 .. ngsel) are walked (each by the waves
+  // in turn, no claim counters) and every accepted node J is recorded as J,
+  // every opened leaf J as J | kRecLeaf, in rec[k * rec_cap ...] for the k-th
+  // listed group, with its node and leaf counts in rec_n[2k], rec_n[2k + 1]
+  const uint32_t *gsel;
+  unsigned ngsel;
+  uint32_t *rec, *rec_n;
+  int64_t rec_cap;
 };
+
+constexpr uint32_t kRecLeaf = 0x80000000u;
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -182,7 +192,7 @@ __device__ __forceinline__ void flush(const WalkArgs &a, const float4 *pl, const
   wave_sync();
 }
 
-template <int MULTI, int LOGS>
+template <int MULTI, int LOGS, bool REC>
 __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   extern __shared__ float4 smem[];
   const int w = threadIdx.x >> 6;
@@ -205,10 +215,11 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   Ctl *ctl = a.ctl;
   if (ctl->flags & kFlagNodeOverflow) return;  // no valid tree: the host repeats
   const unsigned ng = ctl->n_groups, nn = ctl->n_nodes, nsys = ctl->nsys;
+  const unsigned nwork = REC ? a.ngsel : ng;
   const int D = a.D, DQ = a.DQ;
   // with fewer groups than waves the surplus waves have nothing to claim:
   // they leave before touching the shared counters
-  if (slot >= (int64_t)ng) return;
+  if (slot >= (int64_t)nwork) return;
 
   unsigned long long t_node = 0, t_part = 0, t_int = 0, t_nint = 0, t_mac = 0;
   // XCD-aware work distribution: the groups (key order, hence spatially
@@ -217,8 +228,20 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   // first, so neighbouring groups share that XCD's L2, then help elsewhere.
   unsigned xr = blockIdx.x % kXcds;
   int tried = 0;
+  int64_t rec_item = slot;
+  const int64_t nslots = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (;;) {
     unsigned g = ng;
+    unsigned rk = 0;  // REC: position of g in the work list
+    if (REC) {
+      if (rec_item < (int64_t)nwork) {
+        rk = (unsigned)rec_item;
+        g = a.gsel[rk];
+        if (g >= ng) g = ng;
+        rec_item += nslots;
+      }
+      tried = kXcds;
+    }
     while (tried < kXcds) {
       const unsigned lo = (unsigned)(((unsigned long long)xr * ng) / kXcds);
       const unsigned hi = (unsigned)(((unsigned long long)(xr + 1) * ng) / kXcds);
@@ -255,6 +278,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     unsigned qb = 0, qt = 1;
     int64_t stop = 0;
     unsigned long long e_node = 0, e_part = 0, n_mac = 0;
+    int64_t rec_len = 0, rec_leaves = 0;
     if (lane == 0) queue[0] = sy;
     wave_sync();
 
@@ -313,6 +337,14 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       const bool leaf = __float_as_uint(r1.w) != 0u;
       const bool open_leaf = has && qv < nn && !accept && leaf;
       const bool open_int = has && qv < nn && !accept && !leaf;
+      if (REC) {
+        const unsigned long long rm = __ballot(accept || open_leaf);
+        const int64_t at = rec_len + (int64_t)lanes_below(rm);
+        if ((accept || open_leaf) && at < a.rec_cap)
+          a.rec[(int64_t)rk * a.rec_cap + at] = node | (open_leaf ? kRecLeaf : 0u);
+        rec_len += __popcll(rm);
+        rec_leaves += __popcll(__ballot(open_leaf));
+      }
 
       // (1) accepted pseudo j-particles
       const unsigned long long am = __ballot(accept);
@@ -414,13 +446,17 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     // same value from every lane
     a.gent[2 * (size_t)g] = (uint32_t)e_node;
     a.gent[2 * (size_t)g + 1] = (uint32_t)e_part;
+    if (REC && lane == 0) {
+      a.rec_n[2 * (size_t)rk] = (uint32_t)(rec_len - rec_leaves);
+      a.rec_n[2 * (size_t)rk + 1] = (uint32_t)rec_leaves;
+    }
     t_node += e_node;
     t_part += e_part;
     t_int += (unsigned long long)gc * (e_node + e_part);
     t_nint += (unsigned long long)gc * e_node;
     t_mac += n_mac;
   }
-  if (lane == 0 && t_mac) {
+  if (!REC && lane == 0 && t_mac) {
     atomicAdd(&ctl->node_entries, t_node);
     atomicAdd(&ctl->part_entries, t_part);
     atomicAdd(&ctl->interactions, t_int);
@@ -455,23 +491,24 @@ static int waves_per_block(int wb) {
 // walk_k<MULTI, LOGS> for the S = 64 / G the launch uses: compile-time S for
 // G = 64, 32, 16, 8 (the tuner's candidates), run-time S otherwise
 typedef void (*WalkFn)(WalkArgs);
+template <bool REC>
 static WalkFn walk_fn(int multi, int G) {
   const int S = 64 / G;
   if (multi == 2) {
     switch (S) {
-      case 1: return walk_k<2, 0>;
-      case 2: return walk_k<2, 1>;
-      case 4: return walk_k<2, 2>;
-      case 8: return walk_k<2, 3>;
-      default: return walk_k<2, -1>;
+      case 1: return walk_k<2, 0, REC>;
+      case 2: return walk_k<2, 1, REC>;
+      case 4: return walk_k<2, 2, REC>;
+      case 8: return walk_k<2, 3, REC>;
+      default: return walk_k<2, -1, REC>;
     }
   }
   switch (S) {
-    case 1: return walk_k<1, 0>;
-    case 2: return walk_k<1, 1>;
-    case 4: return walk_k<1, 2>;
-    case 8: return walk_k<1, 3>;
-    default: return walk_k<1, -1>;
+    case 1: return walk_k<1, 0, REC>;
+    case 2: return walk_k<1, 1, REC>;
+    case 4: return walk_k<1, 2, REC>;
+    case 8: return walk_k<1, 3, REC>;
+    default: return walk_k<1, -1, REC>;
   }
 }
 
@@ -487,7 +524,7 @@ static void walk_occupancy(gothic_ctx *c) {
   for (int lg = 0; lg < kGroupSizes; ++lg) {
     int per_cu = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, walk_fn(multi, 1 << lg), wpb * 64, wpb * wb);
+        &per_cu, walk_fn<false>(multi, 1 << lg), wpb * 64, wpb * wb);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     c->slots_g[lg] = c->num_cus * per_cu * wpb;
   }
@@ -534,12 +571,19 @@ void launch_walk(gothic_ctx *c, int64_t n, float4 *acc_pot, hipStream_t s) {
   list_dims(multi, c->prm.list_depth, &a.D, &a.DQ);
   a.wave_bytes = wave_bytes_for(multi, a.D, a.DQ);
   a.compensated = c->prm.compensated;
+  a.gsel = B.gsel;
+  a.ngsel = B.ngsel;
+  a.rec = B.rec;
+  a.rec_n = B.rec_n;
+  a.rec_cap = B.rec_cap;
+  const bool rec = B.rec != nullptr;
   const int wpb = waves_per_block(a.wave_bytes);
   walk_occupancy(c);
   const int own = c->slots_g[lg];
   const int slots = own < c->walk_waves ? own : c->walk_waves;
   const int blocks = slots / wpb;
-  hipLaunchKernelGGL(walk_fn(multi, a.G), dim3(blocks), dim3(wpb * 64), wpb * a.wave_bytes, s, a);
+  hipLaunchKernelGGL(rec ? walk_fn<true>(multi, a.G) : walk_fn<false>(multi, a.G), dim3(blocks),
+                     dim3(wpb * 64), wpb * a.wave_bytes, s, a);
 }
 
 }  // namespace gothic

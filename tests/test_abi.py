@@ -77,3 +77,43 @@ def test_oracle_does_not_enter_the_package():
         if f.endswith((".py", ".hip", ".h", ".cpp")):
             txt = open(f).read()
             assert "import oracle" not in txt and "liboracle" not in txt and "orc_" not in txt, f
+
+
+def test_new_tunables_default_and_validate():
+    import paper_1610_07279_amd as g
+    p = g.default_params()
+    assert p.max_scratch_bytes == 0 and p.spill_per_wave == 0
+
+
+def test_host_tensors_are_refused_before_the_library():
+    """The binding refuses a tensor that is not on the context's GPU before it
+    passes any pointer: a host pointer reaching a kernel would fault."""
+    import torch
+
+    import paper_1610_07279_amd as g
+
+    class OnGpu:  # a stand-in for a cuda:0 tensor (no GPU here)
+        def __init__(self, shape, dtype):
+            self.shape, self.dtype = shape, dtype
+            self.is_cuda = True
+            self.device = torch.device("cuda", 0)
+
+        def is_contiguous(self):
+            return True
+
+    ctx = g.Context.__new__(g.Context)  # no device needed: nothing reaches the library
+    ctx._h = None
+    ctx.device = 0
+    x = OnGpu((100, 4), torch.float32)
+    with pytest.raises(ValueError, match="out must be on"):
+        ctx._forces_args(x, None, torch.zeros((100, 4), dtype=torch.float32))
+    with pytest.raises(ValueError, match="active must be on"):
+        ctx._forces_args(x, torch.ones(100, dtype=torch.uint8), None)
+    with pytest.raises(ValueError, match="xyzm must be on"):
+        ctx._forces_args(torch.zeros((100, 4)), None, None)
+    with pytest.raises(ValueError, match="xyzm must be a"):
+        ctx._forces_args(OnGpu((100, 3), torch.float32), None, None)
+    other = OnGpu((100, 4), torch.float32)
+    other.device = torch.device("cuda", 1)
+    with pytest.raises(ValueError, match="out must be on"):
+        ctx._forces_args(x, None, other)

@@ -1,16 +1,18 @@
 """GPU parity of the HIP library against the float64 oracle (through the C ABI).
 
-Integer results (keys, permutation, tree arrays, groups, per-group list
-lengths away from MAC near-ties) must be bit-exact.  Floating results: node
-moments to single-precision round-off, forces within 1e-5 relative rms of the
-oracle's float64 tree (same keys, tree, groups and MAC).
+Integer results (keys, permutation, tree arrays, groups, per-group lists away
+from MAC near-ties) must be bit-exact.  Floating results: node moments to
+single-precision round-off; forces of every active particle within 1e-5
+relative rms of a float64 evaluation of the same list: the oracle's own tree
+for groups without a near tie, and for groups with one the GPU's read-back
+list, whose every decision the oracle checks (gpu_util.gate_forces).
 """
 import numpy as np
 import pytest
 
 import ics
 import oracle
-from gpu_util import diagnose_forces, rel_rms, run_gpu, say, tie_params
+from gpu_util import diagnose_forces, gate_forces, rel_rms, run_gpu, say, tie_params
 
 pytestmark = pytest.mark.gpu
 
@@ -122,40 +124,24 @@ def test_groups_match(G, r_crit):
 def _check_forces(x, eps, theta, active=None, tol=1e-5, **params):
     ctx, out = run_gpu(x, eps, theta, active=active, **params)
     st = ctx.stats()
-    gg = ctx.groups()
+    multipole = params.get("multipole", 1)
     ref = oracle.tree_forces(x, eps, theta, active=active, n_leaf=params.get("n_leaf", 16),
-                             group_size=params.get("group_size", 32),
-                             multipole=params.get("multipole", 1),
+                             group_size=params.get("group_size", 32), multipole=multipole,
                              key_kind=params.get("key_kind", 0),
                              r_crit=params.get("r_crit", -0.0625), **tie_params())
     act = np.ones(x.shape[0], bool) if active is None else active.astype(bool)
     assert np.all(np.isnan(out[~act])), "inactive rows must stay untouched"
     assert np.all(np.isfinite(out[act]))
+    try:
+        gate_forces(ctx, ref, out, act, eps, theta, multipole, tol=tol)
+    except AssertionError:
+        diagnose_forces(ctx, x, ref, out, act)
+        raise
     cnt = ref["counts"]
-    clean = cnt[:, 2] == 0
-    # particles of groups with a MAC near-tie may legitimately use a different
-    # (equally valid) decomposition: the 1e-5 bar applies to identical lists
-    og = ref["groups"]
-    tie_rows = np.zeros(x.shape[0], bool)
-    for q in np.flatnonzero(~clean):
-        tie_rows[ref["perm"][og["alist"][og["first"][q]:og["first"][q] + og["count"][q]]]] = True
-    ok = act & ~tie_rows
-    a, r = out[ok], ref["acc_pot"][ok]
-    e_acc = rel_rms(a, r) if ok.any() else 0.0
-    e_pot = rel_rms(a, r, cols=slice(3, 4)) if ok.any() else 0.0
-    e_tie = rel_rms(out[act & tie_rows], ref["acc_pot"][act & tie_rows]) if tie_rows.any() else 0.0
-    ent = gg["entries"].astype(np.int64)
-    say(f"  rms acc {e_acc:.2e} pot {e_pot:.2e} (tie groups {e_tie:.2e}); groups {cnt.shape[0]} "
-        f"clean {clean.sum()}; interactions {st['interactions']}")
-    if not (e_acc <= tol and e_pot <= tol):
-        diagnose_forces(ctx, x, ref, out, ok)
-    assert e_acc <= tol and e_pot <= tol
-    assert e_tie <= 1e-2  # bounded by the truncation error of one node
-    assert clean.mean() >= 0.9
-    assert np.array_equal(ent[clean, 0], cnt[clean, 0])
-    assert np.array_equal(ent[clean, 1], cnt[clean, 1])
-    if clean.all():
+    if (cnt[:, 2] == 0).all():
+        gg = ctx.groups()
         assert st["interactions"] == int(((cnt[:, 0] + cnt[:, 1]) * gg["count"]).sum())
+    assert st["sticky_flags"] == 0
     return ctx, out, ref
 
 

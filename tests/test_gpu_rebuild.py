@@ -13,7 +13,7 @@ import pytest
 
 import ics
 import oracle
-from gpu_util import rel_rms, say, tie_params
+from gpu_util import gate_forces, oracle_parts, rel_rms, say, tie_params
 
 pytestmark = pytest.mark.gpu
 
@@ -33,11 +33,7 @@ def _oracle_on_old_tree(x_old, x_new, eps, theta, act, multipole, G=32, r_crit=-
     rc = float(np.float32(r_crit))
     rc = -rc * cube[3] if rc < 0 else rc
     grp = oracle.groups(act[perm], ps, G, rc)
-    out, cnt, _ = oracle.walk(tree, mom, ps, grp, eps, theta, multipole, **tie_params())
-    clean = cnt[:, 2] == 0
-    rows = np.concatenate([grp["alist"][grp["first"][q]:grp["first"][q] + grp["count"][q]]
-                           for q in np.flatnonzero(clean)])
-    return out, perm, rows, ks, tree, mom
+    return oracle_parts(tree, mom, ps, grp, perm), ks, tree, mom
 
 
 @pytest.mark.parametrize("multipole", [1, 2])
@@ -61,18 +57,18 @@ def test_reused_tree_matches_the_oracle(multipole):
         ks, perm, _ = ctx.keys()
         keys.append(ks.copy())
         built_from = xs[0] if i < 3 else xs[3]
-        ref, perm_o, rows, ks_o, tree_o, mom_o = _oracle_on_old_tree(built_from, x, eps, theta,
-                                                                      act, multipole)
-        assert np.array_equal(ks, ks_o) and np.array_equal(perm, perm_o), i
+        parts, ks_o, tree_o, mom_o = _oracle_on_old_tree(built_from, x, eps, theta, act,
+                                                         multipole)
+        assert np.array_equal(ks, ks_o) and np.array_equal(perm, parts["perm"]), i
         t = ctx.tree()
         assert np.array_equal(t["first"], tree_o["first"]), i
         # node radii of the (reused) tree at the current positions
         _, b, _ = ctx.nodes()
         scale = np.abs(mom_o[0][:, :3]).sum(1) + mom_o[1]
         assert np.all(np.abs(b - mom_o[1]) <= 1e-5 * mom_o[1] + 2e-6 * scale), i
-        e = rel_rms(o[perm_o[rows]], ref[rows])
-        say(f"  evaluation {i} ({'new' if i in (0, 3) else 'reused'} tree): rms {e:.2e}")
-        assert e <= 1e-5
+        gate_forces(ctx, parts, o, act.astype(bool), eps, theta, multipole,
+                    sel=np.arange(parts["groups"]["first"].size),
+                    label=f"evaluation {i} ({'new' if i in (0, 3) else 'reused'} tree): ")
         assert np.all(np.isnan(o[act == 0]))
     assert np.array_equal(keys[0], keys[1]) and np.array_equal(keys[0], keys[2])
     assert not np.array_equal(keys[2], keys[3])
@@ -93,7 +89,7 @@ def test_fixed_interval_in_block_steps(graph):
         ctx.set_params(check=0)
         ctx.sim_step(4 << kmax)
         info = ctx.sim_info()
-        assert ctx.stats()["flags"] == 0
+        assert ctx.stats()["sticky_flags"] == 0
         res.append((info, pos.cpu().numpy()))
     (i1, p1), (ik, pk) = res
     assert i1["tree_builds"] == 4 << kmax
@@ -139,5 +135,5 @@ def test_automatic_interval():
     ctx.sim_step(steps)
     info = ctx.sim_info()
     say(f"  {info['tree_builds']} builds in {steps} sub-steps")
-    assert ctx.stats()["flags"] == 0
+    assert ctx.stats()["sticky_flags"] == 0
     assert 1 <= info["tree_builds"] < steps

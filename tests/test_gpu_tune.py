@@ -13,7 +13,7 @@ import pytest
 
 import ics
 import oracle
-from gpu_util import rel_rms, say, tie_params
+from gpu_util import gate_forces, rel_rms, say, tie_params
 
 pytestmark = pytest.mark.gpu
 
@@ -24,14 +24,11 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
 import paper_1610_07279_amd as g  # noqa: E402
 
 
-def _oracle_rms(x, eps, theta, out, active, **kw):
-    ref = oracle.tree_forces(x, eps, theta, active=active, **kw, **tie_params())
-    og = ref["groups"]
-    clean = ref["counts"][:, 2] == 0
-    rows = np.concatenate([og["alist"][og["first"][q]:og["first"][q] + og["count"][q]]
-                           for q in np.flatnonzero(clean)])
-    orig = ref["perm"][rows]
-    return rel_rms(out[orig], ref["acc_pot"][orig]), clean.mean()
+def _oracle_gate(ctx, x, eps, theta, out, active, multipole=1, **kw):
+    ref = oracle.tree_forces(x, eps, theta, active=active, multipole=multipole, **kw,
+                             **tie_params())
+    act = np.ones(x.shape[0], bool) if active is None else active.astype(bool)
+    return gate_forces(ctx, ref, out, act, eps, theta, multipole)
 
 
 def test_autotune_choice_cache_and_parity():
@@ -53,10 +50,8 @@ def test_autotune_choice_cache_and_parity():
     assert p["r_crit"] == pytest.approx(res["r_crit"])
     o = out.cpu().numpy()
     assert np.all(np.isnan(o[act == 0])) and np.all(np.isfinite(o[act == 1]))
-    e, clean = _oracle_rms(x, eps, theta, o, act, multipole=2, group_size=res["group_size"],
-                           r_crit=res["r_crit"])
-    say(f"  chosen configuration vs oracle: rms {e:.2e}, tie-free groups {clean:.3f}")
-    assert e <= 1e-5 and clean >= 0.9
+    _oracle_gate(ctx, x, eps, theta, o, act, multipole=2, group_size=res["group_size"],
+                 r_crit=res["r_crit"])
     # same bucket: from the cache, identical choice
     res2 = ctx.autotune(xt, eps, theta, active=at, out=out)
     assert res2["evaluations"] == 0
@@ -82,7 +77,7 @@ def test_online_rcrit_tuning_in_block_steps(graph):
         ctx.set_params(check=0)
         ctx.sim_step(16 << kmax)
         torch.cuda.synchronize()
-        assert ctx.stats()["flags"] == 0
+        assert ctx.stats()["sticky_flags"] == 0
         runs.append((ctx, pos.cpu().numpy(), vel.cpu().numpy()))
     (c0, p0, _), (c1, p1, _) = runs
     r, k = c1.sim_tuning(kmax + 1)
@@ -158,7 +153,7 @@ def test_group_size_per_class_replays_equal_launches():
         (c0, p0, v0), (c1, p1, v1) = runs
         assert torch.equal(p0, p1) and torch.equal(v0, v1), step
         assert c0.stats()["n_groups"] == c1.stats()["n_groups"], step
-    assert runs[1][0].stats()["flags"] == 0
+    assert runs[1][0].stats()["sticky_flags"] == 0
     # the last sub-step of a cycle (every particle due) walks groups of the
     # size its class is given
     n_groups = []
@@ -189,7 +184,7 @@ def test_autotune_picks_group_size_per_class(graph):
         ctx.set_params(check=0)
         ctx.sim_step(16 << kmax)
         torch.cuda.synchronize()
-        assert ctx.stats()["flags"] == 0
+        assert ctx.stats()["sticky_flags"] == 0
         runs.append((ctx, pos.cpu().numpy()))
     (c0, p0), (c1, p1) = runs
     r, k, gs = c1.sim_tuning(kmax + 1, with_groups=True)
@@ -225,7 +220,7 @@ def test_group_sizes_with_batched_systems_and_errors():
         (_, p0, v0), (_, p1, v1) = runs
         assert torch.equal(p0, p1) and torch.equal(v0, v1), step
     ctx = runs[1][0]
-    assert ctx.stats()["flags"] == 0
+    assert ctx.stats()["sticky_flags"] == 0
     with pytest.raises(g.GothicError):
         ctx.sim_set_group_sizes([0] * 33)  # more classes than there are
     with pytest.raises(g.GothicError):
@@ -243,7 +238,7 @@ def test_group_sizes_with_batched_systems_and_errors():
     ctx2.set_params(check=0)
     ctx2.sim_step(16 << kmax)
     torch.cuda.synchronize()
-    assert ctx2.stats()["flags"] == 0
+    assert ctx2.stats()["sticky_flags"] == 0
     _, _, gs2 = ctx2.sim_tuning(kmax + 1, with_groups=True)
     say(f"  picked group sizes per class {gs2.tolist()}")
     assert set(gs2.tolist()) <= {8, 16, 32, 64}

@@ -254,6 +254,37 @@ int gothic_tree_forces_ex(gothic_ctx *c, int nsys, const int64_t *offsets, const
                           const float *eps, const float *theta, const uint8_t *active,
                           const float *acc_old, float *acc_pot, void *stream);
 
+/*
+ * Scratch-free variant of gothic_tree_forces, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and argument
+ * errors as gothic_tree_forces, with these differences:
+ *   - no device or pinned memory is allocated or freed by the call: all
+ *     scratch lives in one fixed array of 256 MiB per GPU (a file-scope
+ *     __device__ array, looked up when a context is created on that GPU and
+ *     held until the process ends).  n is limited by it: about 5e5
+ *     particles at n_leaf = 16; a larger n returns GOTHIC_ENOMEM and
+ *     gothic_get_scratch() reports the bytes it needed.  The context's own
+ *     scratch is neither used nor changed.
+ *   - never synchronises (params.check is ignored); device errors (non-finite
+ *     input, node or pending-stack overflow) are reported by the next
+ *     gothic_get_stats(), which returns GOTHIC_ENONFINITE / GOTHIC_EOVERFLOW.
+ *     The pending stack holds params.spill_per_wave entries per walk wave
+ *     (0: 4096); the node arrays hold params.node_capacity nodes (0: about
+ *     n + 8 n / n_leaf).
+ *   - always builds a new tree (params.rebuild_interval and autotune do not
+ *     apply); the acceleration MAC (mac = 1) returns EINVAL.
+ *   - every scratch-free call on one GPU shares the array and leaves its
+ *     contents behind (the next call clears what must start at zero): calls
+ *     that may overlap in time on one GPU (other streams, other host threads,
+ *     other contexts) race and must be ordered by the caller.  The read-back
+ *     calls (gothic_get_stats, gothic_get_keys, ...) after a scratch-free call
+ *     read that array, valid until the next scratch-free call on the GPU.
+ */
+int gothic_tree_forces_noalloc(gothic_ctx *c, int64_t n, const float *xyzm, float eps,
+                               float theta, const uint8_t *active, float *acc_pot,
+                               void *stream);
+
 /* Result of gothic_autotune. */
 typedef struct {
   int group_size;         /* chosen G */

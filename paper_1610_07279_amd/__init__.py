@@ -85,6 +85,7 @@ def _load():
     lib.gothic_set_params.argtypes = [P, C.POINTER(Params)]
     lib.gothic_get_params.argtypes = [P, C.POINTER(Params)]
     lib.gothic_tree_forces.argtypes = [P, i64, P, f32, f32, P, P, P]
+    lib.gothic_tree_forces_noalloc.argtypes = [P, i64, P, f32, f32, P, P, P]
     lib.gothic_tree_forces_batched.argtypes = [P, i32, P, P, P, P, P, P, P]
     lib.gothic_tree_forces_ex.argtypes = [P, i32, P, P, P, P, P, P, P, P]
     lib.gothic_direct_forces.argtypes = [P, i64, P, f32, i64, P, P, P]
@@ -237,6 +238,17 @@ class Context:
         else:
             return self.tree_forces_batched(xyzm, [0, n], eps, theta, active=active, out=out,
                                             stream=stream, acc_old=acc_old)
+        return out
+
+    def tree_forces_noalloc(self, xyzm, eps: float, theta: float, active=None, out=None,
+                            stream=None):
+        """As tree_forces, through the scratch-free entry point (the library
+        allocates nothing; out must be given or is allocated here, by torch)."""
+        n, out = self._forces_args(xyzm, active, out)
+        s = _stream_of(xyzm, stream)
+        self._last_stream = s
+        _check(lib.gothic_tree_forces_noalloc(self._h, n, _ptr(xyzm), float(eps), float(theta),
+                                              _ptr(active), _ptr(out), s))
         return out
 
     @property

@@ -110,6 +110,10 @@ int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const uint8_t
 // note that the evaluation just enqueued on s used the buffers lb
 void mark_last(gothic_ctx *c, const Systems &sy, hipStream_t s, Buffers *lb);
 
+// ---- noalloc.hip: look up this device's copy of the static scratch array
+// (device current); called once per context creation
+int static_scratch_attach(int dev);
+
 // ---- sim_api.hip
 void free_graphs(gothic_ctx *c);
 void free_sim(gothic_ctx *c);

@@ -231,7 +231,8 @@ struct gothic_ctx {
   int slots_multi = 0, slots_D = 0;
   int cur_G = 32;                 // group size of the evaluation being enqueued
   gothic::Buffers b;
-  gothic::Buffers *lb = nullptr;  // buffers of the last evaluation (b, or the static scratch's)
+  gothic::Buffers sb;             // buffers of the last scratch-free call (in the static array)
+  gothic::Buffers *lb = nullptr;  // buffers of the last evaluation (b or sb)
   int64_t scratch_held = 0;       // device scratch bytes held by b
   int64_t scratch_required = 0;   // bytes a refused call needed (ECAPTURE / ENOMEM), else 0
   uint64_t generation = 1;        // bumped whenever a device buffer or a parameter changes

@@ -112,6 +112,7 @@ int gothic_create(gothic_ctx **out, int hip_device, const gothic_params *p) {
   hipDeviceProp_t prop;
   if ((rc = hip_check(hipGetDeviceProperties(&prop, hip_device), "hipGetDeviceProperties")))
     return rc;
+  if ((rc = static_scratch_attach(hip_device))) return rc;
   gothic_ctx *c = new gothic_ctx();
   c->device = hip_device;
   c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;

@@ -39,12 +39,6 @@ __global__ void extract_groups_k(const Ctl *ctl, const uint32_t *gf, uint32_t *g
   }
 }
 
-// Debugging aid: with the environment variable GOTHIC_POISON_ALLOC set (to
-// anything but "0"), every new floating-point buffer starts as all-ones bytes
-// (NaN in every lane), so a kernel that reads memory no kernel of the
-// evaluation wrote gives visibly wrong results instead of results that depend
-// on what the memory held before.  Index buffers are left alone.
-
 // copy the control block of the last evaluation to the host (synchronises)
 static int fetch_ctl(gothic_ctx *c, Ctl *h) {
   Buffers *lb = c->lb ? c->lb : &c->b;

@@ -89,8 +89,14 @@ def run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, shared, steps, warmup)
     st = ctx._stats_raw()
     if st["sticky_flags"]:  # any sub-step of the timed window, not only the last
         raise RuntimeError(f"device flags {st['sticky_flags']} set during the timed steps")
+    last = {k: st[k] for k in ("n_active", "n_groups", "node_entries", "part_entries",
+                               "interactions", "mac_tests")}
+    ent = st["node_entries"] + st["part_entries"]
+    # i-particles per group and list entry: the fraction of the walk's lanes
+    # that carry an i-particle in the force loops of the last sub-step
+    last["group_fill"] = st["interactions"] / max(ent * ctx.params["group_size"], 1)
     return dict(seconds=t1 - t0, info=info, walk_ms=walk_ms, walk_launches=launches,
-                pos=pos.cpu().numpy().astype(np.float32))
+                pos=pos.cpu().numpy().astype(np.float32), last=last)
 
 
 def batched_bench(cycles=1, kmax=6):
@@ -284,7 +290,7 @@ def mac_sweep(args):
     t0 = time.perf_counter()
     ref = g.Context(device=0).direct_forces(xd, eps, idx=it).cpu().numpy()
     log(f"mac sweep: direct sum for {idx.size} targets in {time.perf_counter() - t0:.1f} s")
-    base = dict(multipole=2, group_size=args.group_size, list_depth=args.list_depth,
+    base = dict(multipole=2, group_size=args.group_size, walk_width=args.walk_width, list_depth=args.list_depth,
                 r_crit=args.r_crit, ball=args.ball, rebuild_interval=args.rebuild_interval)
     prev = g.Context(device=0, **base).tree_forces(xd, eps, 0.5)
     pos0 = torch.from_numpy(x[:, :3].astype(np.float64)).to(dev)
@@ -341,7 +347,7 @@ def ball_sweep(args):
         xd = torch.from_numpy(make()).to(torch.device("cuda", 0))
         radii, firsts = {}, {}
         for kind in (1, 0, 2, 3, 4):  # SEB first: the reference radius
-            ctx = g.Context(device=0, multipole=2, group_size=args.group_size,
+            ctx = g.Context(device=0, multipole=2, group_size=args.group_size, walk_width=args.walk_width,
                             list_depth=args.list_depth, r_crit=args.r_crit, ball=kind, timing=1)
             out = ctx.tree_forces(xd, eps, theta)
             ctx.set_params(check=0)
@@ -394,7 +400,7 @@ def n_sweep(args):
         pos0 = torch.from_numpy(x[:, :3].astype(np.float64)).to(dev)
         vel0 = torch.from_numpy(v).to(dev)
         mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).to(dev)
-        ctx = g.Context(device=0, multipole=2, group_size=args.group_size,
+        ctx = g.Context(device=0, multipole=2, group_size=args.group_size, walk_width=args.walk_width,
                         list_depth=args.list_depth, r_crit=args.r_crit, timing=1,
                         graph=args.graph, rebuild_interval=args.rebuild_interval, ball=args.ball,
                         mac=1, mac_delta=2.0 ** -7)
@@ -418,6 +424,233 @@ def n_sweep(args):
         torch.cuda.empty_cache()
 
 
+def _rel_stats(tree, ref):
+    """global rms, 50th / 99th percentile / max of |a_tree - a_ref| / |a_ref|."""
+    e = rel_error(tree, ref)
+    d = tree[:, :3].astype(np.float64) - ref[:, :3]
+    g = float(np.sqrt((d ** 2).sum() / (ref[:, :3] ** 2).sum()))
+    return {"rms": g, "p50": float(np.percentile(e, 50)), "p99": float(np.percentile(e, 99)),
+            "max": float(e.max())}
+
+
+def _time_forces(ctx, xd, eps, theta, out, reps, warm=3):
+    """wall ms per evaluation (reps back-to-back, unchecked) and walk ms (events)."""
+    import torch
+    for _ in range(warm):
+        ctx.tree_forces(xd, eps, theta, out=out)
+    torch.cuda.synchronize()
+    ctx.walk_time()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.tree_forces(xd, eps, theta, out=out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps * 1e3
+    ms, k = ctx.walk_time()
+    return wall, ms / max(k, 1)
+
+
+def config_c1(args):
+    """Plummer N = 8192 (seed 101), eps 1/64, theta 0.5, monopole, one
+    shared-step force with every particle active: GPU time per evaluation
+    (latency-bound at this N), interactions, errors against the library's
+    float64 direct sum; cpu_baseline: the float64 oracle's direct sum and tree
+    on every host thread, and the GPU forces against the oracle tree."""
+    import torch
+
+    import ics
+    import paper_1610_07279_amd as g
+    n, eps, theta = 8192, 1 / 64, 0.5
+    x = ics.plummer(n, seed=101)
+    xd = torch.from_numpy(x).cuda()
+    ctx = g.Context(device=0, timing=1)
+    out = ctx.tree_forces(xd, eps, theta)
+    st = ctx.stats()
+    ctx.set_params(check=0)
+    wall, walk = _time_forces(ctx, xd, eps, theta, out, reps=200)
+    a = out.cpu().numpy()
+    # the same evaluation captured once in a HIP graph by the caller and replayed
+    # (the pipeline is some two hundred small launches at this N)
+    ctx.set_params(timing=0)
+    side = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        ctx.tree_forces(xd, eps, theta, out=out)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(200):
+        graph.replay()
+    torch.cuda.synchronize()
+    replay_us = (time.perf_counter() - t0) / 200 * 1e6
+    if not np.array_equal(out.cpu().numpy(), a):
+        raise RuntimeError("the captured evaluation differs from the eager one")
+    ref = g.Context(device=0).direct_forces(xd, eps).cpu().numpy()
+    row = {"config": "C1", "workload": "Plummer N=8192 (seed 101), eps 1/64, theta 0.5, "
+                                        "monopole, all active",
+           "us_per_evaluation": wall * 1e3, "us_per_evaluation_graph_replay": replay_us,
+           "walk_us": walk * 1e3,
+           "interactions": st["interactions"], "groups": st["n_groups"],
+           "vs_float64_direct": _rel_stats(a, ref)}
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        od = oracle.direct(x, eps)
+        t_direct = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ot = oracle.tree_forces(x, eps, theta)
+        t_tree = time.perf_counter() - t0
+        row["vs_float64_oracle_tree"] = _rel_stats(a, ot["acc_pot"])
+        row["oracle_tree_vs_direct"] = _rel_stats(ot["acc_pot"].astype(np.float32), od)
+        row["cpu_baseline"] = {"kind": "oracle", "cores": oracle.num_threads(), "cpu": cpu_model(),
+                               "direct_s": t_direct, "tree_s": t_tree,
+                               "value": 1.0 / t_tree, "unit": "evaluations/s (tree)",
+                               "sample": "one whole evaluation of each (float64; tree: keys, "
+                                         "sort, octree, moments, groups, walk)"}
+    return row
+
+
+def config_c2(args):
+    """NFW N = 2^20 (seed 201), eps 1/128, quadrupole, theta 0.5, block steps
+    on kmax = 8 levels: one full block cycle (2^(kmax - k_lo) finest sub-steps,
+    k_lo the coarsest populated level at t = 0), timed after one untimed cycle,
+    against shared steps at the finest step (mean of 5 after 2 untimed);
+    speed-up = 2^(kmax - k_lo) t_shared / t_cycle.  cpu_baseline: the float64
+    oracle walk on a sample of groups of an all-active evaluation."""
+    import torch
+
+    import ics
+    import paper_1610_07279_amd as g
+    n, eps, theta, kmax = 1 << 20, 1 / 128, 0.5, 8
+    x, v = ics.nfw(n, seed=201, with_vel=True)
+    dev = torch.device("cuda", 0)
+    pos0 = torch.from_numpy(x[:, :3].astype(np.float64)).to(dev)
+    vel0 = torch.from_numpy(v).to(dev)
+    mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).to(dev)
+    kw = dict(multipole=2, group_size=args.group_size, walk_width=args.walk_width, list_depth=args.list_depth,
+              r_crit=args.r_crit, ball=args.ball, rebuild_interval=args.rebuild_interval,
+              graph=args.graph, timing=1)
+    ctx = g.Context(device=0, **kw)
+    pos, vel = pos0.clone(), vel0.clone()
+    ctx.sim_bind(pos, vel, mass, eps, theta, eta=0.1, kmax=kmax)
+    hist0 = ctx.sim_info()["level_count"][:kmax + 1]
+    k_lo = min(k for k, c in enumerate(hist0) if c)
+    cycle = 1 << (kmax - k_lo)
+    ctx.set_params(check=0)
+    ctx.sim_step(cycle)  # untimed cycle: captures, first trees
+    torch.cuda.synchronize()
+    ctx.sim_reset_counters()
+    t0 = time.perf_counter()
+    ctx.sim_step(cycle)
+    torch.cuda.synchronize()
+    t_cycle = time.perf_counter() - t0
+    ib = ctx.sim_info()
+    if ctx._stats_raw()["sticky_flags"]:
+        raise RuntimeError("device flags set in the block cycle")
+    shd = run_sim(g.Context(device=0, **kw), pos0, vel0, mass, eps, theta, 0.1, kmax, True, 5, 2)
+    t_shared = shd["seconds"] / 5
+    row = {"config": "C2", "workload": "NFW N=2^20 (seed 201), eps 1/128, theta 0.5, "
+                                        "quadrupole, block steps kmax 8",
+           "level_count_t0": hist0, "k_lo": k_lo, "cycle_substeps": cycle,
+           "cycle_s": t_cycle, "cycle_interactions": ib["interactions_total"],
+           "cycle_tree_builds": ib["tree_builds"],
+           "cycle_interactions_per_s": ib["interactions_total"] / t_cycle,
+           "shared_s_per_step": t_shared,
+           "shared_interactions_per_s": shd["info"]["interactions_total"] / shd["seconds"],
+           "speedup_block_vs_shared": cycle * t_shared / t_cycle,
+           "level_count_end": ib["level_count"][:kmax + 1],
+           "tunables": {k: kw[k] for k in ("group_size", "list_depth", "r_crit", "ball")}}
+    if not args.no_cpu:
+        lev = np.full(n, kmax, np.uint8)
+        last = np.zeros(n, np.int64)
+        row["cpu_baseline"] = cpu_baseline(x, (lev, last, 0), eps, theta, 2, args.group_size, 16,
+                                           args.r_crit, args.ball, kmax, 1, target_s=10.0)
+    return row
+
+
+def config_c3(args):
+    """Galaxy N = 2^22 (NFW halo 80 %, Hernquist bulge 5 %, exponential disk
+    15 %; seeds 301-303), eps 1/256, theta 0.5, monopole, all active: float32
+    and Neumaier-compensated accumulation, errors against the library's float64
+    direct sum on 4096 random particles (seed 304); cpu_baseline: the float64
+    oracle's direct sum for the same 4096 targets."""
+    import torch
+
+    import ics
+    import paper_1610_07279_amd as g
+    n, eps, theta = 1 << 22, 1 / 256, 0.5
+    x = ics.galaxy(n)
+    xd = torch.from_numpy(x).cuda()
+    idx = np.sort(np.random.default_rng(304).choice(n, 4096, replace=False)).astype(np.int64)
+    it = torch.from_numpy(idx).cuda()
+    ref = g.Context(device=0).direct_forces(xd, eps, idx=it).cpu().numpy()
+    row = {"config": "C3", "workload": "galaxy N=2^22 (seeds 301-303), eps 1/256, theta 0.5, "
+                                        "monopole, all active; 4096 targets (seed 304)"}
+    outs = {}
+    for comp in (0, 1):
+        ctx = g.Context(device=0, timing=1, compensated=comp, group_size=args.group_size, walk_width=args.walk_width,
+                        list_depth=args.list_depth)
+        out = ctx.tree_forces(xd, eps, theta)
+        st = ctx.stats()
+        ctx.set_params(check=0)
+        wall, walk = _time_forces(ctx, xd, eps, theta, out, reps=5, warm=1)
+        a = out[it].cpu().numpy()
+        outs[comp] = a
+        row["compensated" if comp else "fp32"] = {
+            "ms_per_evaluation": wall, "walk_ms": walk, "interactions": st["interactions"],
+            "vs_float64_direct": _rel_stats(a, ref)}
+    d = outs[0][:, :3].astype(np.float64) - outs[1][:, :3]
+    row["fp32_vs_compensated_rms"] = float(np.sqrt((d ** 2).sum() / (ref[:, :3] ** 2).sum()))
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        od = oracle.direct(x, eps, idx=idx)
+        t_direct = time.perf_counter() - t0
+        row["library_direct_vs_oracle_direct"] = _rel_stats(ref.astype(np.float64), od)
+        row["cpu_baseline"] = {"kind": "oracle", "cores": oracle.num_threads(),
+                               "cpu": cpu_model(), "direct_s": t_direct,
+                               "value": 4096.0 * n / t_direct, "unit": "pairs/s",
+                               "sample": f"float64 direct sum of 4096 targets against all {n}"}
+    return row
+
+
+def config_c4(args):
+    """64 systems (N_s log-uniform in [2^12, 2^18], Plummer / NFW, seed 401),
+    monopole, theta 0.5: the timed autotuner's choice of (group size, walk
+    width, list depth, r_crit) for one all-active batched evaluation, its time
+    against the default tunables, and the batched block-step comparison of the
+    headline run (one captured batched sub-step vs 64 contexts)."""
+    import torch
+
+    import ics
+    import paper_1610_07279_amd as g
+    x, offs, eps, _ = ics.batched_systems(64, seed=401, with_vel=True)
+    n = x.shape[0]
+    xt = torch.from_numpy(x).cuda()
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    ctx = g.Context(device=0)
+    res = ctx.autotune(xt, eps, 0.5, offsets=offs, out=out)
+    ref = g.Context(device=0, check=0)
+    ref.tree_forces_batched(xt, offs, eps, 0.5, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        ref.tree_forces_batched(xt, offs, eps, 0.5, out=out)
+    torch.cuda.synchronize()
+    t_def = (time.perf_counter() - t0) / 10 * 1e3
+    ctx.set_params(check=0)
+    ctx.tree_forces_batched(xt, offs, eps, 0.5, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        ctx.tree_forces_batched(xt, offs, eps, 0.5, out=out)
+    torch.cuda.synchronize()
+    t_tuned = (time.perf_counter() - t0) / 10 * 1e3
+    row = {"config": "C4", "workload": f"64 systems, N={n} in all", "autotune": res,
+           "all_active_ms_default": t_def, "all_active_ms_tuned": t_tuned}
+    row["batched_block_steps"] = batched_bench()
+    return row
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,6 +658,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1 << 24)
     ap.add_argument("--group-size", type=int, default=32)
+    ap.add_argument("--walk-width", type=int, default=64, choices=(16, 32, 64),
+                    help="lanes sharing one traversal (64: one group per wave)")
     ap.add_argument("--list-depth", type=int, default=384)
     ap.add_argument("--r-crit", type=float, default=0.25,
                     help="critical separation splitting groups (Section 2.4)")
@@ -454,7 +689,16 @@ def main():
                          "given); n: time per step for N = 2^10 ... 2^24; then exit")
     ap.add_argument("--sweep-sample", type=int, default=1 << 14,
                     help="particles whose force error a sweep measures")
+    ap.add_argument("--config", choices=("C1", "C2", "C3", "C4"), default=None,
+                    help="the report of one of the smaller workloads (C1 Plummer 8192 forces, "
+                         "C2 NFW 2^20 block cycle vs shared, C3 galaxy 2^22 float32 vs "
+                         "compensated, C4 64 batched systems with the autotuner), one JSON "
+                         "line, then exit")
     args = ap.parse_args()
+    if args.config:
+        fn = {"C1": config_c1, "C2": config_c2, "C3": config_c3, "C4": config_c4}[args.config]
+        print(json.dumps(fn(args)), flush=True)
+        return
     if args.sweep:
         if "--n" not in sys.argv:
             args.n = 1 << 23
@@ -486,7 +730,7 @@ def main():
     x, v = ics.nfw(n, seed=501, with_vel=True)
     dev = torch.device("cuda", 0)
     if args.forces_only:
-        ctx = g.Context(device=0, multipole=multipole, group_size=args.group_size,
+        ctx = g.Context(device=0, multipole=multipole, group_size=args.group_size, walk_width=args.walk_width,
                         list_depth=args.list_depth, r_crit=args.r_crit, timing=1)
         xd = torch.from_numpy(x).to(dev)
         out = ctx.tree_forces(xd, eps, theta)
@@ -504,13 +748,20 @@ def main():
     pos0 = torch.from_numpy(x[:, :3].astype(np.float64)).to(dev)
     vel0 = torch.from_numpy(v).to(dev)
     mass = torch.from_numpy(np.ascontiguousarray(x[:, 3])).to(dev)
-    ctx = g.Context(device=0, multipole=multipole, group_size=args.group_size,
+    ctx = g.Context(device=0, multipole=multipole, group_size=args.group_size, walk_width=args.walk_width,
                     list_depth=args.list_depth, r_crit=args.r_crit, timing=1, graph=args.graph,
                     rebuild_interval=args.rebuild_interval, ball=args.ball,
                     autotune=args.autotune)
 
     log(f"bench: block steps (warmup {args.warmup}, timed {args.steps})")
     blk = run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, False, args.steps, args.warmup)
+    tuning = None
+    if args.autotune:
+        # the online tuner's state after the block run: r_crit and (with
+        # autotune 2) the group shape picked for each sub-step class
+        r, k, gs, ws = ctx.sim_tuning(kmax + 1, with_groups=True)
+        tuning = [{"class": c, "group_size": int(gs[c]), "walk_width": int(ws[c]),
+                   "r_crit_best": float(r[c]), "searches": int(k[c])} for c in range(kmax + 1)]
     # the state the CPU baseline's due sets come from (end of the block run)
     _, lev_end, last_end = ctx.sim_state()
     state_end = (lev_end, last_end, blk["info"]["substep"])
@@ -547,8 +798,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"NFW sphere N={n}, c=10, eps=1/512, theta=0.5 quadrupole, "
                                f"block steps kmax=8 (eta=0.1), finest sub-steps",
-                   "n": n, "group_size": args.group_size, "list_depth": args.list_depth,
-                   "r_crit": args.r_crit, "graph": args.graph,
+                   "n": n, "group_size": args.group_size, "walk_width": args.walk_width,
+                   "list_depth": args.list_depth, "r_crit": args.r_crit, "graph": args.graph,
                    "rebuild_interval": args.rebuild_interval, "ball": args.ball,
                    "autotune": args.autotune,
                    "parallelism": "single GPU"},
@@ -561,7 +812,8 @@ def main():
                   "level_count": ib["level_count"][:kmax + 1],
                   "tree_builds": ib["tree_builds"],
                   "walk_launches": blk["walk_launches"],
-                  "walk_ms_per_step": blk["walk_ms"] / max(blk["walk_launches"], 1)},
+                  "walk_ms_per_step": blk["walk_ms"] / max(blk["walk_launches"], 1),
+                  "last_substep": blk["last"]},
         # achieved = (mono x 24 + quad x 60) flop / (walk launches x walk_ms_mean),
         # the walk timed by HIP events around every launch on its own stream
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
@@ -575,6 +827,8 @@ def main():
                      "walk_ms_mean": blk["walk_ms"] / max(blk["walk_launches"], 1),
                      "flops_per_interaction": {"mono": FLOP_MONO, "quad": FLOP_QUAD}},
     }
+    if tuning is not None:
+        out["block"]["tuning_per_class"] = tuning
     if shd is not None:
         inter_s = shd["info"]["interactions_total"]
         out["shared"] = {"s_per_step": shd["seconds"] / args.steps,

@@ -112,8 +112,9 @@ typedef struct {
                          drifting optimum).  One search per class of
                          sub-steps with the same due levels.  Synchronises on
                          the previous sub-step's walk.  2: as 1, after first
-                         picking the group size of each class by timing
-                         (gothic_sim_set_group_sizes) (default 0) */
+                         picking the group shape (group size and walk width)
+                         of each class by timing (gothic_sim_set_group_sizes)
+                         (default 0) */
   int rebuild_interval; /* tree reuse (Section 2.6): 1 = build a new tree for
                          every evaluation (default); k > 1 = build one every
                          k evaluations and walk the last one in between, with
@@ -163,6 +164,13 @@ typedef struct {
                          A walk that outgrows it drops the children it cannot
                          hold and sets the frontier-overflow flag; check mode
                          then grows it 4x and repeats the evaluation */
+  int walk_width;     /* W: lanes that share one tree traversal (the paper's
+                         T_sub, Table 2): 64 = one group per wave64 (default;
+                         0 means 64), 16 or 32 = 64 / W groups walked side by
+                         side in one wave, each by its own W lanes with its own
+                         pending stack and a 1/(64/W) share of the wave's
+                         list budget.  group_size must not exceed W; each
+                         i-particle gets S = W / group_size lanes */
 } gothic_params;
 
 /* Statistics of the last force evaluation (filled by gothic_get_stats). */
@@ -293,6 +301,7 @@ typedef struct {
                              system's key-cube side) */
   int evaluations;        /* timed evaluations spent; 0 = taken from the cache */
   double ms;              /* best measured time of one evaluation (ms) */
+  int walk_width;         /* chosen W (16, 32 or 64) */
 } gothic_tune_result;
 
 /*
@@ -320,10 +329,12 @@ int gothic_direct_forces(gothic_ctx *c, int64_t n, const float *xyzm, float eps,
 
 /*
  * Timed search for the fastest tunables of one workload (Section 2.4 tunes
- * r_crit by Brent's method on the measured time; here the group size G and
- * the list budget are searched as well): every G in {8, 16, 32, 64} with
- * every list_depth in {128, 256, 384, 512, 768} at the current r_crit, then
- * Brent's method over log2(r_crit / L) in [-12, 0] at the best pair.  Each
+ * r_crit by Brent's method on the measured time; here the group size G, the
+ * walk width W and the list budget are searched as well): every shape (G, W)
+ * in (8, 64), (16, 64), (32, 64), (64, 64), (4, 16), (8, 16), (8, 32),
+ * (16, 32) with every list_depth in {128, 256, 384, 512, 768} at the current
+ * r_crit, then Brent's method over log2(r_crit / L) in [-12, 0] at the best
+ * triple.  Each
  * candidate is one whole evaluation timed with HIP events (after an untimed
  * one).  The winner is stored in the context's parameters and cached under
  * (batched or not, floor(log2 n), floor(log2(n / n_active)), multipole); a
@@ -362,7 +373,10 @@ int gothic_get_walk_time(gothic_ctx *c, double *ms_total, int64_t *launches);
  * particle's last acceleration).
  * gothic_sim_step advances one finest sub-step and is asynchronous (check
  * mode synchronises inside the force evaluation).  The arrays must stay
- * valid until the next bind or gothic_destroy.
+ * valid until the next bind or gothic_destroy.  Each sub-step ends by
+ * predicting the positions of the next one (the first is predicted by the
+ * bind), so a change a caller makes to pos or vel between two calls reaches
+ * the forces one sub-step later.
  */
 typedef struct {
   int64_t n;
@@ -401,20 +415,27 @@ int gothic_sim_get_steps(gothic_ctx *c, int nsys, double *dt_fine, double *dt_ma
 /* Online tuning (params.autotune): for each sub-step class c = 0..nclass-1
  * (class c = sub-steps whose index has its lowest set bit at c, capped at
  * kmax), the best r_crit of the last finished search (0 if none finished
- * yet), the number of finished searches, and the group size the class walks
- * with now (params.group_size until a size is fixed or picked).  HOST
- * arrays; any may be NULL.  0 <= nclass <= 32. */
+ * yet), the number of finished searches, and the group size and walk width
+ * the class walks with now (params.group_size / params.walk_width until a
+ * shape is fixed or picked).  HOST arrays; any may be NULL.
+ * 0 <= nclass <= 32. */
 int gothic_sim_get_tuning(gothic_ctx *c, int nclass, float *r_crit_best, int *searches,
-                          int *group_size);
-/* Group size per sub-step class (Section 4 names choosing the number of
- * threads per i-particle, S, for each step as future work; a wave holds G
- * i-particles with S = 64 / G lanes each, so this chooses S per class).
- * group_size: HOST int [nclass], each 0 (params.group_size) or a power of
- * two in 1..64; classes >= nclass keep their setting.  params.autotune = 2
- * picks the size of each class whose entry is 0 by timing G = 8, 16, 32, 64
- * on its first sub-steps.  The binding of a system (gothic_sim_bind*) clears
- * the table.  Returns EINVAL for a bad size (nothing is changed). */
-int gothic_sim_set_group_sizes(gothic_ctx *c, int nclass, const int *group_size);
+                          int *group_size, int *walk_width);
+/* Group shape per sub-step class (Section 4 names choosing the number of
+ * threads per i-particle, S, for each step as future work; a group of G
+ * i-particles is walked by W lanes with S = W / G lanes each, so this chooses
+ * S and the walk width per class).
+ * group_size: HOST int [nclass], each 0 (the class follows params.group_size
+ * and params.walk_width) or a power of two in 1..64; walk_width: HOST int
+ * [nclass], each 16, 32 or 64 (0 = 64) and at least the class's group size,
+ * or NULL for 64 throughout.  Classes >= nclass keep their setting.
+ * params.autotune = 2 picks the shape of each class whose entry is 0 by
+ * timing (G, W) = (8, 64), (16, 64), (32, 64), (64, 64), (4, 16), (8, 16),
+ * (8, 32), (16, 32) on its first sub-steps.  The binding of a system
+ * (gothic_sim_bind*) clears the table.  Returns EINVAL for a bad entry
+ * (nothing is changed). */
+int gothic_sim_set_group_sizes(gothic_ctx *c, int nclass, const int *group_size,
+                               const int *walk_width);
 
 /* Counts of the last evaluation; synchronises the stream of that call. */
 int gothic_get_stats(gothic_ctx *c, gothic_stats *out);

@@ -36,12 +36,12 @@ class Params(C.Structure):
                 ("graph", C.c_int), ("autotune", C.c_int), ("rebuild_interval", C.c_int),
                 ("mac", C.c_int), ("mac_delta", C.c_float), ("ball", C.c_int),
                 ("node_capacity", C.c_int64), ("max_scratch_bytes", C.c_int64),
-                ("spill_per_wave", C.c_int)]
+                ("spill_per_wave", C.c_int), ("walk_width", C.c_int)]
 
 
 class TuneResult(C.Structure):
     _fields_ = [("group_size", C.c_int), ("list_depth", C.c_int), ("r_crit", C.c_float),
-                ("evaluations", C.c_int), ("ms", C.c_double)]
+                ("evaluations", C.c_int), ("ms", C.c_double), ("walk_width", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -101,8 +101,8 @@ def _load():
     lib.gothic_sim_bind.argtypes = [P, i64, P, P, P, f32, f32, C.c_double, i32, i32, P]
     lib.gothic_sim_bind_batched.argtypes = [P, i32, P, P, P, P, P, P, C.c_double, i32, i32, P]
     lib.gothic_sim_get_steps.argtypes = [P, i32, P, P]
-    lib.gothic_sim_get_tuning.argtypes = [P, i32, P, P, P]
-    lib.gothic_sim_set_group_sizes.argtypes = [P, i32, P]
+    lib.gothic_sim_get_tuning.argtypes = [P, i32, P, P, P, P]
+    lib.gothic_sim_set_group_sizes.argtypes = [P, i32, P, P]
     lib.gothic_autotune.argtypes = [P, i32, P, P, P, P, P, P, C.POINTER(TuneResult), P]
     lib.gothic_sim_step.argtypes = [P, P]
     lib.gothic_sim_reset_counters.argtypes = [P, P]
@@ -389,21 +389,30 @@ class Context:
 
     def sim_tuning(self, nclass: int = 32, with_groups: bool = False):
         """(best r_crit per sub-step class [nclass] float32, finished searches [nclass]
-        [, group size per class [nclass]]) of the online tuner (params.autotune)."""
+        [, group size per class [nclass], walk width per class [nclass]]) of the
+        online tuner (params.autotune)."""
         import numpy as np
         r = np.zeros(nclass, np.float32)
         k = np.zeros(nclass, np.int32)
         gs = np.zeros(nclass, np.int32)
+        ws = np.zeros(nclass, np.int32)
         _check(lib.gothic_sim_get_tuning(self._h, nclass, r.ctypes.data_as(C.c_void_p),
                                          k.ctypes.data_as(C.c_void_p),
-                                         gs.ctypes.data_as(C.c_void_p)))
-        return (r, k, gs) if with_groups else (r, k)
+                                         gs.ctypes.data_as(C.c_void_p),
+                                         ws.ctypes.data_as(C.c_void_p)))
+        return (r, k, gs, ws) if with_groups else (r, k)
 
-    def sim_set_group_sizes(self, sizes):
-        """Group size per sub-step class (0 = params.group_size)."""
+    def sim_set_group_sizes(self, sizes, widths=None):
+        """Group size per sub-step class (0 = params.group_size / walk_width) and
+        walk width per class (None = 64 for every class)."""
         import numpy as np
         g = np.ascontiguousarray(sizes, dtype=np.int32)
-        _check(lib.gothic_sim_set_group_sizes(self._h, g.size, g.ctypes.data_as(C.c_void_p)))
+        w = None if widths is None else np.ascontiguousarray(widths, dtype=np.int32)
+        if w is not None and w.size != g.size:
+            raise ValueError("sizes and widths differ in length")
+        _check(lib.gothic_sim_set_group_sizes(
+            self._h, g.size, g.ctypes.data_as(C.c_void_p),
+            None if w is None else w.ctypes.data_as(C.c_void_p)))
 
     def sim_step(self, nsteps: int = 1, stream=None):
         s = _stream_of(self._sim_keep[0], stream)

@@ -39,11 +39,14 @@ struct EvalOpts {
   bool picked = false;       // the group size came from the class's picker
   int kmax = 0;              // finest level (class weights of the rebuild models)
   int group_G = 0;           // group size; 0 = params.group_size
+  int walk_W = 0;            // walk width; 0 = params.walk_width
   bool sign_active = false;  // active flags are the sign bits of the masses in x4
 };
 
 // ---- context.hip
 int validate_params(const gothic_params *p);
+// params.walk_width with 0 read as 64
+inline int walk_width_of(const gothic_params &p) { return p.walk_width ? p.walk_width : 64; }
 
 // ---- scratch.hip: device scratch of a context
 // capacities every buffer of Buffers is sized from

@@ -136,6 +136,7 @@ struct SimCtl {
   double eta;
   int kmax, shared;
   unsigned long long n_active;  // due particles of the step in progress
+  unsigned long long n_next;    // due particles of the next step (counted while predicting it)
   unsigned long long last_active, steps, inter_total, node_inter_total, active_total;
   unsigned long long level_count[32];
 };
@@ -167,17 +168,20 @@ struct SimState {
 };
 
 // Captured sub-step of the block-step driver (params.graph), in segments:
-// predict + system table, tree construction (skipped when the tree is
-// reused), permute + moments + groups, walk, correct.  The pieces between
+// system table, tree construction (skipped when the tree is reused),
+// permute + moments + groups, walk, correct + predict the next sub-step
+// (the first sub-step is predicted when the system is bound).  The pieces between
 // them (control block, r_crit) and the events timing the construction and
 // the walk are launched outside.
 constexpr int kSegments = 5;
 constexpr int kGroupSizes = 7;  // G = 1, 2, 4, ..., 64
+constexpr int kWalkWidths = 3;  // W = 16, 32, 64
 struct SimGraphs {
-  // segments 0 (predict), 1 (tree) and 4 (correct); 2 and 3 (groups, walk)
-  // depend on the group size and live in exec_g[log2 G], captured on demand
+  // segments 0 (system table), 1 (tree) and 4 (correct + predict); 2 and 3 (groups, walk)
+  // depend on the group shape and live in exec_g[log2 W - 4][log2 G],
+  // captured on demand
   hipGraphExec_t exec[kSegments] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  hipGraphExec_t exec_g[kGroupSizes][2] = {};
+  hipGraphExec_t exec_g[kWalkWidths][kGroupSizes][2] = {};
   hipStream_t cap_stream = nullptr;
   uint64_t generation = 0;
   bool valid = false;
@@ -211,8 +215,9 @@ struct TuneState {
   bool pending_rebuilt = false;              // ... whether it built its tree
   bool pending_tuned = false;                // ... whether its r_crit came from cls[]
   bool pending_pick = false;                 // ... whether its G came from pick[]
-  GroupPicker pick[kTuneClasses];            // params.autotune = 2: G per class
+  GroupPicker pick[kTuneClasses];            // params.autotune = 2: (G, W) per class
   int class_G[kTuneClasses] = {};            // group size per class (0: params.group_size)
+  int class_W[kTuneClasses] = {};            // walk width per class (0: params.walk_width)
   bool recording = false;                    // record ev0 / ev1 around the next walk
   // gothic_autotune results by (batched, log2 n, log2 of n / n_active, multipole)
   std::map<std::tuple<int, int, int, int>, gothic_tune_result> cache;
@@ -227,9 +232,11 @@ struct gothic_ctx {
   int64_t cap_n = 0, cap_nodes = 0, cap_groups = 0, cap_hist = 0, cap_sys = 0, cap_anc = 0;
   int64_t spill_per_wave = 0;
   int walk_waves = 0;             // persistent walk waves (slots), the most any G launches
-  int slots_g[gothic::kGroupSizes] = {};  // walk waves per log2 G for slots_multi / slots_D
+  // walk waves per (log2 W - 4, log2 G) for slots_multi / slots_D
+  int slots_g[gothic::kWalkWidths][gothic::kGroupSizes] = {};
   int slots_multi = 0, slots_D = 0;
   int cur_G = 32;                 // group size of the evaluation being enqueued
+  int cur_W = 64;                 // ... and its walk width
   gothic::Buffers b;
   gothic::Buffers sb;             // buffers of the last scratch-free call (in the static array)
   gothic::Buffers *lb = nullptr;  // buffers of the last evaluation (b or sb)
@@ -296,7 +303,7 @@ void launch_walk(gothic_ctx *c, int64_t n, float4 *acc_pot, hipStream_t s);
 int walk_slots(gothic_ctx *c);
 // sim.hip
 void sim_launch_setup(gothic_ctx *c, hipStream_t s, double eta, int kmax, int shared);
-void sim_launch_reset(gothic_ctx *c, hipStream_t s);
+void sim_launch_reset(gothic_ctx *c, hipStream_t s, bool all);
 void sim_launch_shadow(gothic_ctx *c, hipStream_t s);
 void sim_launch_init(gothic_ctx *c, hipStream_t s);
 void sim_launch_predict(gothic_ctx *c, hipStream_t s);

@@ -54,6 +54,10 @@ int validate_params(const gothic_params *p) {
   if (p->max_scratch_bytes < 0) return set_error(GOTHIC_EINVAL, "max_scratch_bytes must be >= 0");
   if (p->spill_per_wave != 0 && (p->spill_per_wave < 256 || p->spill_per_wave > (1 << 24)))
     return set_error(GOTHIC_EINVAL, "spill_per_wave must be 0 or in 256..2^24");
+  if (p->walk_width != 0 && p->walk_width != 16 && p->walk_width != 32 && p->walk_width != 64)
+    return set_error(GOTHIC_EINVAL, "walk_width must be 0, 16, 32 or 64");
+  if (G > walk_width_of(*p))
+    return set_error(GOTHIC_EINVAL, "group_size must not exceed walk_width");
   return GOTHIC_OK;
 }
 
@@ -92,6 +96,7 @@ void gothic_default_params(gothic_params *p) {
   p->node_capacity = 0;
   p->max_scratch_bytes = 0;
   p->spill_per_wave = 0;
+  p->walk_width = 64;
 }
 
 const char *gothic_last_error(void) { return g_last_error.c_str(); }
@@ -153,7 +158,7 @@ int gothic_set_params(gothic_ctx *c, const gothic_params *p) {
       a.group_size != b.group_size || a.list_depth != b.list_depth ||
       a.compensated != b.compensated || a.graph != b.graph || a.mac != b.mac ||
       a.mac_delta != b.mac_delta || a.ball != b.ball || a.node_capacity != b.node_capacity ||
-      a.spill_per_wave != b.spill_per_wave)
+      a.spill_per_wave != b.spill_per_wave || a.walk_width != b.walk_width)
     ++c->generation;
   c->prm = *p;
   return GOTHIC_OK;

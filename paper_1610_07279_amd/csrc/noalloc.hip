@@ -118,6 +118,7 @@ int gothic_tree_forces_noalloc(gothic_ctx *c, int64_t n, const float *xyzm, floa
   int rc = make_systems(1, off, &eps, &theta, false, &sy);
   if (rc) return rc;
   c->cur_G = c->prm.group_size;
+  c->cur_W = walk_width_of(c->prm);
   const Caps k = static_caps(c, n);
   const int64_t need = scratch_bytes(k);
   if (need > kStaticScratchBytes) {

@@ -273,7 +273,10 @@ int meter_collect(gothic_ctx *c, int kmax) {
   if ((rc = hip_check(hipEventElapsedTime(&walk, T.ev0, T.ev1), "hipEventElapsedTime"))) return rc;
   if (T.pending_pick) {
     T.pick[k].observe((double)walk);
-    if (T.pick[k].decided()) T.class_G[k] = T.pick[k].current();
+    if (T.pick[k].decided()) {
+      T.class_G[k] = T.pick[k].current();
+      T.class_W[k] = T.pick[k].current_width();
+    }
   } else if (T.pending_tuned) {
     T.cls[k].observe((double)walk);
   }
@@ -329,6 +332,7 @@ int run_forces(gothic_ctx *c, const Systems &sy, const float4 *x4, const uint8_t
                const EvalOpts &o) {
   const int64_t n = sy.n;
   c->cur_G = o.group_G > 0 ? o.group_G : c->prm.group_size;
+  c->cur_W = o.walk_W > 0 ? o.walk_W : walk_width_of(c->prm);
   if (c->prm.mac == 1 && !acc_old)
     return set_error(GOTHIC_EINVAL,
                      "the acceleration MAC needs the previous accelerations (gothic_tree_forces_ex)");

@@ -15,7 +15,9 @@
 //   multiple of that coarser step.  Time is counted in finest sub-steps s
 //   (t = s dt_fine); particle i is due at s when s - s_i = 2^(kmax - k_i).
 // The sub-step counter and every count live on the device, so a step needs
-// no host round-trip.  Several independent systems can be stepped together:
+// no host round-trip.  The correction of sub-step s and the prediction of
+// s + 1 are one pass over the float64 state; the prediction of the first
+// sub-step is made when the system is bound.  Several independent systems can be stepped together:
 // each has its own dt_fine / dt_max (from its own minimum step) and the
 // shared counter s counts every system's own finest sub-steps.
 #include "common.h"
@@ -159,43 +161,83 @@ sim_predict_k(int64_t n, unsigned nsys, const uint32_t *__restrict__ soff,
   }
 }
 
+// End of sub-step s and start of s+1 in one pass over the float64 state: the
+// particles due at s are corrected (and take new levels), then every
+// particle is predicted to s+1 into the float32 shadow with its due flag.
+// The same arithmetic as a correction pass followed by a prediction pass,
+// with the state read once.
 __global__ void __launch_bounds__(256)
-sim_correct_k(int64_t n, unsigned nsys, const uint32_t *__restrict__ soff,
-              double *__restrict__ pos, double *__restrict__ vel,
-              const float4 *__restrict__ anew, float4 *__restrict__ aold,
-              int64_t *__restrict__ si, uint8_t *__restrict__ lev,
-              const uint8_t *__restrict__ act, const SimSys *__restrict__ ss,
-              const SimCtl *__restrict__ sc) {
-  const int64_t s = sc->s + 1;
+sim_correct_predict_k(int64_t n, unsigned nsys, const uint32_t *__restrict__ soff,
+                      double *__restrict__ pos, double *__restrict__ vel,
+                      const float *__restrict__ mass, const float4 *__restrict__ anew,
+                      float4 *__restrict__ aold, int64_t *__restrict__ si,
+                      uint8_t *__restrict__ lev, float4 *__restrict__ shadow,
+                      uint8_t *__restrict__ act, const SimSys *__restrict__ ss, SimCtl *sc) {
+  const int64_t s = sc->s + 1;  // the sub-step being finished
   const double eta = sc->eta;
   const int kmax = sc->kmax, shared = sc->shared;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    if (!act[i]) continue;
-    const SimSys &r = ss[sys_of(soff, nsys, (uint32_t)i)];
-    const int k = lev[i];
-    const double dt = ldexp(r.dt_fine, kmax - k);
-    const float4 ao = aold[i], an = anew[i];
-    const double h = 0.5 * dt * dt;
-    pos[3 * i] += dt * vel[3 * i] + h * (double)ao.x;
-    pos[3 * i + 1] += dt * vel[3 * i + 1] + h * (double)ao.y;
-    pos[3 * i + 2] += dt * vel[3 * i + 2] + h * (double)ao.z;
-    vel[3 * i] += 0.5 * dt * ((double)ao.x + (double)an.x);
-    vel[3 * i + 1] += 0.5 * dt * ((double)ao.y + (double)an.y);
-    vel[3 * i + 2] += 0.5 * dt * ((double)ao.z + (double)an.z);
-    aold[i] = an;
-    si[i] = s;
-    if (!shared) {
-      const int kw = level_for(step_of(an, r.eps, eta), r.dt_max, kmax);
-      int kn = k;
-      if (kw > k) {
-        kn = kw;  // finer at once
-      } else if (kw < k && k > 0) {
-        const int64_t coarse = (int64_t)1 << (kmax - k + 1);
-        if (s % coarse == 0) kn = k - 1;  // coarser by one, on that level's grid
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  unsigned cnt = 0;
+  for (int64_t base = w0 * 64; base < n; base += nw * 64) {
+    const int64_t i = base + lane_id();
+    if (i < n) {
+      const SimSys &r = ss[sys_of(soff, nsys, (uint32_t)i)];
+      double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+      double vx = vel[3 * i], vy = vel[3 * i + 1], vz = vel[3 * i + 2];
+      float4 a = aold[i];
+      int64_t last = si[i];
+      int k = lev[i];
+      if (act[i]) {
+        const double dt = ldexp(r.dt_fine, kmax - k);
+        const float4 an = anew[i];
+        const double h = 0.5 * dt * dt;
+        x += dt * vx + h * (double)a.x;
+        y += dt * vy + h * (double)a.y;
+        z += dt * vz + h * (double)a.z;
+        vx += 0.5 * dt * ((double)a.x + (double)an.x);
+        vy += 0.5 * dt * ((double)a.y + (double)an.y);
+        vz += 0.5 * dt * ((double)a.z + (double)an.z);
+        pos[3 * i] = x; pos[3 * i + 1] = y; pos[3 * i + 2] = z;
+        vel[3 * i] = vx; vel[3 * i + 1] = vy; vel[3 * i + 2] = vz;
+        a = an;
+        aold[i] = an;
+        last = s;
+        si[i] = s;
+        if (!shared) {
+          const int kw = level_for(step_of(an, r.eps, eta), r.dt_max, kmax);
+          int kn = k;
+          if (kw > k) {
+            kn = kw;
+          } else if (kw < k && k > 0) {
+            const int64_t coarse = (int64_t)1 << (kmax - k + 1);
+            if (s % coarse == 0) kn = k - 1;
+          }
+          k = kn;
+          lev[i] = (uint8_t)kn;
+        }
       }
-      lev[i] = (uint8_t)kn;
+      // prediction to s + 1
+      const int64_t el = s + 1 - last;
+      const double tau = (double)el * r.dt_fine;
+      const double h = 0.5 * tau * tau;
+      const double px = x + tau * vx + h * (double)a.x;
+      const double py = y + tau * vy + h * (double)a.y;
+      const double pz = z + tau * vz + h * (double)a.z;
+      const bool due = el == ((int64_t)1 << (kmax - k));
+      const float m = mass[i];
+      shadow[i] = make_float4((float)px, (float)py, (float)pz, due ? -m : m);
+      act[i] = due ? 1 : 0;
+      cnt += due ? 1u : 0u;
     }
+  }
+  __shared__ unsigned wcnt[4];
+  cnt = wave_sum(cnt);
+  if (lane_id() == 0) wcnt[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned t = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    if (t) atomicAdd(&sc->n_next, (unsigned long long)t);
   }
 }
 
@@ -207,7 +249,8 @@ __global__ void sim_advance_k(SimCtl *sc, const Ctl *ctl) {
     sc->node_inter_total += ctl->node_interactions;
     sc->active_total += sc->n_active;
     sc->last_active = sc->n_active;
-    sc->n_active = 0;
+    sc->n_active = sc->n_next;  // the next step was predicted with this one's correction
+    sc->n_next = 0;
   }
 }
 
@@ -220,9 +263,13 @@ __global__ void sim_setup_k(SimCtl *sc, double eta, int kmax, int shared) {
   }
 }
 
-__global__ void sim_reset_k(SimCtl *sc) {
+// all = 1 (a new binding): also the due counts of the predicted step
+__global__ void sim_reset_k(SimCtl *sc, int all) {
   if (threadIdx.x == 0) {
-    sc->n_active = 0;
+    if (all) {
+      sc->n_active = 0;
+      sc->n_next = 0;
+    }
     sc->steps = 0;
     sc->inter_total = 0;
     sc->node_inter_total = 0;
@@ -257,8 +304,8 @@ void sim_launch_setup(gothic_ctx *c, hipStream_t s, double eta, int kmax, int sh
   hipLaunchKernelGGL(sim_setup_k, dim3(1), dim3(64), 0, s, c->sim.sc, eta, kmax, shared);
 }
 
-void sim_launch_reset(gothic_ctx *c, hipStream_t s) {
-  hipLaunchKernelGGL(sim_reset_k, dim3(1), dim3(64), 0, s, c->sim.sc);
+void sim_launch_reset(gothic_ctx *c, hipStream_t s, bool all) {
+  hipLaunchKernelGGL(sim_reset_k, dim3(1), dim3(64), 0, s, c->sim.sc, all ? 1 : 0);
 }
 
 void sim_launch_shadow(gothic_ctx *c, hipStream_t s) {
@@ -284,10 +331,13 @@ void sim_launch_predict(gothic_ctx *c, hipStream_t s) {
                      S.sc);
 }
 
+// the end of a sub-step: correct the due particles and predict the next
+// sub-step, then advance the clock
 void sim_launch_correct(gothic_ctx *c, hipStream_t s) {
   SimState &S = c->sim;
-  hipLaunchKernelGGL(sim_correct_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n, (unsigned)S.nsys,
-                     S.soff, S.pos, S.vel, S.anew, S.aold, S.si, S.lev, S.act, S.ss, S.sc);
+  hipLaunchKernelGGL(sim_correct_predict_k, dim3(grid_for(S.n)), dim3(256), 0, s, S.n,
+                     (unsigned)S.nsys, S.soff, S.pos, S.vel, S.mass, S.anew, S.aold, S.si, S.lev,
+                     S.shadow, S.act, S.ss, S.sc);
   hipLaunchKernelGGL(sim_advance_k, dim3(1), dim3(64), 0, s, S.sc, c->b.ctl);
 }
 

@@ -23,12 +23,13 @@ void free_graphs(gothic_ctx *c) {
       (void)hipGraphExecDestroy(e);
       e = nullptr;
     }
-  for (auto &pair : G.exec_g)
-    for (auto &e : pair)
-      if (e) {
-        (void)hipGraphExecDestroy(e);
-        e = nullptr;
-      }
+  for (auto &width : G.exec_g)
+    for (auto &pair : width)
+      for (auto &e : pair)
+        if (e) {
+          (void)hipGraphExecDestroy(e);
+          e = nullptr;
+        }
   G.valid = false;
 }
 
@@ -42,8 +43,6 @@ void free_sim(gothic_ctx *c) {
   S = SimState();
   ++c->generation;
 }
-
-// The force pipeline with argument checks done: capacity, enqueue, and in
 
 static int sim_bind_impl(gothic_ctx *c, const Systems &sy, double *pos, double *vel,
                          const float *mass, double eta, int kmax, int shared_step,
@@ -87,6 +86,7 @@ static int sim_bind_impl(gothic_ctx *c, const Systems &sy, double *pos, double *
   c->tune.ready = false;
   c->tune.pending = -1;
   for (int &g : c->tune.class_G) g = 0;
+  for (int &w : c->tune.class_W) w = 0;
   {  // a new system: no tree to reuse, no growth history (the events stay)
     hipEvent_t m0 = c->tree.mk0, m1 = c->tree.mk1;
     c->tree = TreeState();
@@ -110,7 +110,7 @@ static int sim_bind_impl(gothic_ctx *c, const Systems &sy, double *pos, double *
       (rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize")))
     return rc;
   sim_launch_setup(c, s, eta, kmax, shared_step ? 1 : 0);
-  sim_launch_reset(c, s);
+  sim_launch_reset(c, s, true);
   sim_launch_shadow(c, s);
   if ((rc = hip_check(hipGetLastError(), "kernel launch"))) return rc;
   // t = 0 forces on every particle (synchronous, checked; the acceleration
@@ -122,7 +122,8 @@ static int sim_bind_impl(gothic_ctx *c, const Systems &sy, double *pos, double *
   c->prm = saved;
   if (rc) return rc;
   sim_launch_init(c, s);
-  sim_launch_reset(c, s);
+  sim_launch_reset(c, s, true);
+  sim_launch_predict(c, s);  // the first sub-step; later ones are predicted by the corrector
   if ((rc = hip_check(hipGetLastError(), "kernel launch"))) return rc;
   if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
   S.bound = true;
@@ -154,10 +155,7 @@ static int capture_segment(gothic_ctx *c, int seg, hipGraphExec_t *out) {
                       "hipStreamBeginCapture")))
     return rc;
   switch (seg) {
-    case 0:
-      sim_launch_predict(c, G.cap_stream);
-      enqueue_upload(c, sy, G.cap_stream);
-      break;
+    case 0: enqueue_upload(c, sy, G.cap_stream); break;
     case 1: enqueue_make(c, sy, S.shadow, G.cap_stream); break;
     case 2: enqueue_post(c, sy, S.shadow, nullptr, S.aold, G.cap_stream, true); break;
     case 3: enqueue_walk(c, sy.n, S.anew, G.cap_stream, false); break;
@@ -174,8 +172,8 @@ static int capture_segment(gothic_ctx *c, int seg, hipGraphExec_t *out) {
   return rc;
 }
 
-// the segments that do not depend on the group size (predict, tree, correct);
-// those that do are captured per group size by capture_groups
+// the segments that do not depend on the group shape (system table, tree,
+// correct + predict); those that do are captured per shape by capture_groups
 static int capture_step(gothic_ctx *c) {
   SimGraphs &G = c->graphs;
   SimState &S = c->sim;
@@ -200,13 +198,15 @@ static int capture_step(gothic_ctx *c) {
   return GOTHIC_OK;
 }
 
-// groups + moments and walk segments for group size G = 2^lg
-static int capture_groups(gothic_ctx *c, int lg) {
+// groups + moments and walk segments for group size G = 2^lg and walk width
+// W = 16 << lw
+static int capture_groups(gothic_ctx *c, int lw, int lg) {
   SimGraphs &G = c->graphs;
   c->cur_G = 1 << lg;
+  c->cur_W = 16 << lw;
   int rc;
   for (int k = 0; k < 2; ++k)
-    if ((rc = capture_segment(c, 2 + k, &G.exec_g[lg][k]))) {
+    if ((rc = capture_segment(c, 2 + k, &G.exec_g[lw][lg][k]))) {
       free_graphs(c);
       return rc;
     }
@@ -265,15 +265,17 @@ int gothic_sim_step(gothic_ctx *c, void *stream) {
   int cls = __builtin_ctzll(snext);
   if (cls > S.kmax) cls = S.kmax;
   float r_crit = c->prm.r_crit;
-  // group size of the class: fixed by gothic_sim_set_group_sizes or a
+  // group shape of the class: fixed by gothic_sim_set_group_sizes or a
   // finished pick, else (autotune = 2) the candidate being timed
-  int gsize = c->prm.group_size;
+  int gsize = c->prm.group_size, wsize = walk_width_of(c->prm);
   bool picking = false;
   if (c->prm.autotune && (rc = meter_prepare(c))) return rc;
   if (T.class_G[cls] > 0) {
     gsize = T.class_G[cls];
+    wsize = T.class_W[cls] > 0 ? T.class_W[cls] : 64;
   } else if (c->prm.autotune == 2) {
     gsize = T.pick[cls].current();
+    wsize = T.pick[cls].current_width();
     picking = true;
   }
   const bool tuning = c->prm.autotune != 0 && !picking;
@@ -282,8 +284,8 @@ int gothic_sim_step(gothic_ctx *c, void *stream) {
     if ((rc = ensure_events(c))) return rc;
     if (!c->graphs.valid || c->graphs.generation != c->generation)
       if ((rc = capture_step(c))) return rc;
-    const int lg = log2_of(gsize);
-    if (!c->graphs.exec_g[lg][0] && (rc = capture_groups(c, lg))) return rc;
+    const int lg = log2_of(gsize), lw = log2_of(wsize) - 4;
+    if (!c->graphs.exec_g[lw][lg][0] && (rc = capture_groups(c, lw, lg))) return rc;
     const Systems sy = sim_systems(S);
     const bool meter = metering(c);
     if (meter && ((rc = meter_prepare(c)) || (rc = meter_collect(c, S.kmax)))) return rc;
@@ -299,11 +301,11 @@ int gothic_sim_step(gothic_ctx *c, void *stream) {
       if ((rc = hip_check(hipGraphLaunch(G.exec[1], s), "hipGraphLaunch"))) return rc;
       if (meter) (void)hipEventRecord(c->tree.mk1, s);
     }
-    if ((rc = hip_check(hipGraphLaunch(G.exec_g[lg][0], s), "hipGraphLaunch"))) return rc;
+    if ((rc = hip_check(hipGraphLaunch(G.exec_g[lw][lg][0], s), "hipGraphLaunch"))) return rc;
     const bool timed = c->prm.timing && c->ev_used < (int)c->ev_start.size();
     if (meter) (void)hipEventRecord(T.ev0, s);
     if (timed) (void)hipEventRecord(c->ev_start[c->ev_used], s);
-    if ((rc = hip_check(hipGraphLaunch(G.exec_g[lg][1], s), "hipGraphLaunch"))) return rc;
+    if ((rc = hip_check(hipGraphLaunch(G.exec_g[lw][lg][1], s), "hipGraphLaunch"))) return rc;
     if (timed) (void)hipEventRecord(c->ev_stop[c->ev_used++], s);
     if (meter) (void)hipEventRecord(T.ev1, s);
     if ((rc = hip_check(hipGraphLaunch(G.exec[4], s), "hipGraphLaunch"))) return rc;
@@ -311,13 +313,13 @@ int gothic_sim_step(gothic_ctx *c, void *stream) {
     if (rebuild) ++S.builds;
     if (meter) meter_mark(c, cls, rebuild, tuning, picking);
   } else {
-    sim_launch_predict(c, s);
     EvalOpts o;
     o.meter_class = cls;
     o.tuned = tuning;
     o.picked = picking;
     o.kmax = S.kmax;
     o.group_G = gsize;
+    o.walk_W = wsize;
     o.sign_active = true;
     rc = run_forces(c, sim_systems(S), S.shadow, nullptr, S.aold, S.anew, s, r_crit, o);
     if (rc) return rc;
@@ -330,7 +332,7 @@ int gothic_sim_step(gothic_ctx *c, void *stream) {
 }
 
 int gothic_sim_get_tuning(gothic_ctx *c, int nclass, float *r_crit_best, int *searches,
-                          int *group_size) {
+                          int *group_size, int *walk_width) {
   if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
   if (nclass < 0 || nclass > kTuneClasses)
     return set_error(GOTHIC_EINVAL, "nclass must be in 0..32");
@@ -340,33 +342,40 @@ int gothic_sim_get_tuning(gothic_ctx *c, int nclass, float *r_crit_best, int *se
     if (r_crit_best) r_crit_best[k] = have ? -(float)std::exp2(T.cls[k].best) : 0.f;
     if (searches) searches[k] = T.ready ? T.cls[k].searches : 0;
     if (group_size) group_size[k] = T.class_G[k] > 0 ? T.class_G[k] : c->prm.group_size;
+    if (walk_width)
+      walk_width[k] = T.class_G[k] > 0 ? (T.class_W[k] > 0 ? T.class_W[k] : 64)
+                                       : walk_width_of(c->prm);
   }
   return GOTHIC_OK;
 }
 
-int gothic_sim_set_group_sizes(gothic_ctx *c, int nclass, const int *group_size) {
+int gothic_sim_set_group_sizes(gothic_ctx *c, int nclass, const int *group_size,
+                               const int *walk_width) {
   if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
   if (nclass < 0 || nclass > kTuneClasses)
     return set_error(GOTHIC_EINVAL, "nclass must be in 0..32");
   if (nclass > 0 && !group_size) return set_error(GOTHIC_EINVAL, "group_size must not be NULL");
   for (int k = 0; k < nclass; ++k) {
     const int G = group_size[k];
+    const int W = walk_width ? walk_width[k] : 64;
     if (G != 0 && (G < 1 || G > 64 || (G & (G - 1))))
       return set_error(GOTHIC_EINVAL, "group sizes must be 0 or a power of two in 1..64");
+    if (W != 0 && W != 16 && W != 32 && W != 64)
+      return set_error(GOTHIC_EINVAL, "walk widths must be 0, 16, 32 or 64");
+    if (G > (W ? W : 64)) return set_error(GOTHIC_EINVAL, "a group size exceeds its walk width");
   }
-  for (int k = 0; k < nclass; ++k) c->tune.class_G[k] = group_size[k];
+  for (int k = 0; k < nclass; ++k) {
+    c->tune.class_G[k] = group_size[k];
+    c->tune.class_W[k] = walk_width ? walk_width[k] : 64;
+  }
   return GOTHIC_OK;
 }
-
-// One evaluation with the current tunables and a new tree, timed with the
-// tuner's events (enqueued directly: no checks, no user timing).  Flags make
-// it invalid.
 
 int gothic_sim_reset_counters(gothic_ctx *c, void *stream) {
   if (!c) return set_error(GOTHIC_EINVAL, "context is NULL");
   if (!c->sim.bound) return set_error(GOTHIC_EINVAL, "no system bound (gothic_sim_bind)");
   DeviceGuard guard(c->device);
-  sim_launch_reset(c, reinterpret_cast<hipStream_t>(stream));
+  sim_launch_reset(c, reinterpret_cast<hipStream_t>(stream), false);
   c->sim.builds = 0;
   return hip_check(hipGetLastError(), "kernel launch");
 }

@@ -148,20 +148,24 @@ struct OnlineTuner {
   }
 };
 
-// Group size per sub-step class.  A block time step changes the number of
+// Group shape per sub-step class.  A block time step changes the number of
 // i-particles from step to step by orders of magnitude, and the best number
 // of threads sharing one i-particle (S) depends on it (Section 3.4, Fig. 7);
 // the paper fixes S and names choosing it per step as future work (Section
-// 4).  Here a wave holds one group of G i-particles with S = 64 / G lanes
-// each, so choosing S is choosing G.  The candidates are timed round-robin,
+// 4).  Here a group of G i-particles is walked by W lanes (the walk width,
+// the paper's T_sub of Table 2) with S = W / G lanes each, so a shape is a
+// pair (G, W).  The candidates are timed round-robin,
 // `rounds` walks each (interleaved, so a tree that ages between rebuilds
 // weighs on every candidate alike), and the smallest mean walk time wins.
 struct GroupPicker {
-  static constexpr int kCand = 4;
-  static constexpr int kSizes[kCand] = {8, 16, 32, 64};
+  // candidate shapes: group size G with one group per wave64 (W = 64), and
+  // G with walk width W < 64 (64 / W groups walked side by side in a wave)
+  static constexpr int kCand = 8;
+  static constexpr int kSizes[kCand] = {8, 16, 32, 64, 4, 8, 8, 16};
+  static constexpr int kWidths[kCand] = {64, 64, 64, 64, 16, 16, 32, 32};
   int rounds = 2;
-  double sum[kCand] = {0, 0, 0, 0};
-  int count[kCand] = {0, 0, 0, 0};
+  double sum[kCand] = {};
+  int count[kCand] = {};
   int next = 0;     // candidate timed next
   int chosen = -1;  // index of the winner once every candidate is timed
 
@@ -176,9 +180,10 @@ struct GroupPicker {
   }
   bool decided() const { return chosen >= 0; }
   int current() const { return kSizes[decided() ? chosen : next]; }
-  void choose(int G) {  // fixed from outside
+  int current_width() const { return kWidths[decided() ? chosen : next]; }
+  void choose(int G, int W = 64) {  // fixed from outside
     for (int k = 0; k < kCand; ++k)
-      if (kSizes[k] == G) chosen = k;
+      if (kSizes[k] == G && kWidths[k] == W) chosen = k;
   }
   void observe(double t) {
     if (decided()) return;

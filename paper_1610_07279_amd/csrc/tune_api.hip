@@ -1,6 +1,6 @@
 // Timed search of the tunables of one workload (gothic_autotune): group
-// size and list budget by exhaustive timing, then Brent's method on the
-// critical separation r_crit of Section 2.4.
+// size, walk width and list budget by exhaustive timing, then Brent's method
+// on the critical separation r_crit of Section 2.4.
 #include <string.h>
 
 #include <algorithm>
@@ -18,6 +18,7 @@ static int timed_eval(gothic_ctx *c, const Systems &sy, const float4 *x4, const 
   if ((rc = ensure(c, sy.n, sy.nsys, nodes_wanted(c, sy.n, sy.nsys), c->spill_per_wave)))
     return rc;
   c->cur_G = c->prm.group_size;
+  c->cur_W = walk_width_of(c->prm);
   (void)hipEventRecord(T.ev0, s);
   if ((rc = enqueue_forces(c, sy, x4, act, nullptr, o4, s, r_crit, true))) return rc;
   (void)hipEventRecord(T.ev1, s);
@@ -52,6 +53,7 @@ static int autotune_impl(gothic_ctx *c, const Systems &sy, const float4 *x4, con
   const int64_t na = c->b.ctl_host->n_active;
   memset(out, 0, sizeof(*out));
   out->group_size = c->prm.group_size;
+  out->walk_width = walk_width_of(c->prm);
   out->list_depth = c->prm.list_depth;
   out->r_crit = c->prm.r_crit;
   if (na == 0) return GOTHIC_OK;
@@ -68,12 +70,16 @@ static int autotune_impl(gothic_ctx *c, const Systems &sy, const float4 *x4, con
     c->prm.timing = 0;
     int evals = 0;
     double best = HUGE_VAL;
-    int bestG = saved.group_size, bestD = saved.list_depth;
-    const int Gs[4] = {8, 16, 32, 64};
+    int bestG = saved.group_size, bestW = walk_width_of(saved), bestD = saved.list_depth;
+    // shapes (G, W): one group per wave64, then 64 / W groups side by side
+    const int Gs[8] = {8, 16, 32, 64, 4, 8, 8, 16};
+    const int Ws[8] = {64, 64, 64, 64, 16, 16, 32, 32};
     const int Ds[5] = {128, 256, 384, 512, 768};
-    for (int G : Gs)
+    for (int k = 0; k < 8; ++k)
       for (int D : Ds) {
+        const int G = Gs[k], W = Ws[k];
         c->prm.group_size = G;
+        c->prm.walk_width = W;
         c->prm.list_depth = D;
         double t1, t2;
         if ((rc = timed_eval(c, sy, x4, act, o4, s, saved.r_crit, &t1)) ||
@@ -86,10 +92,12 @@ static int autotune_impl(gothic_ctx *c, const Systems &sy, const float4 *x4, con
         if (t < best) {
           best = t;
           bestG = G;
+          bestW = W;
           bestD = D;
         }
       }
     c->prm.group_size = bestG;
+    c->prm.walk_width = bestW;
     c->prm.list_depth = bestD;
     // Brent over log2(r_crit / L), the quantity the paper tunes
     BrentMin bm;
@@ -116,6 +124,7 @@ static int autotune_impl(gothic_ctx *c, const Systems &sy, const float4 *x4, con
     const float rbest = -(float)std::exp2(best_u);
     const bool r_wins = best_rt < best;
     out->group_size = bestG;
+    out->walk_width = bestW;
     out->list_depth = bestD;
     out->r_crit = r_wins ? rbest : saved.r_crit;
     out->ms = r_wins ? best_rt : best;
@@ -124,6 +133,7 @@ static int autotune_impl(gothic_ctx *c, const Systems &sy, const float4 *x4, con
   }
   gothic_params chosen = c->prm;
   chosen.group_size = out->group_size;
+  chosen.walk_width = out->walk_width;
   chosen.list_depth = out->list_depth;
   chosen.r_crit = out->r_crit;
   if ((rc = gothic_set_params(c, &chosen))) return rc;

@@ -66,7 +66,8 @@ struct WalkArgs {
   float mac_delta;
   int mac;              // 0 opening angle, 1 acceleration, 2 multipole (Warren-Salmon)
   int G, logG, D, DQ;
-  int wave_bytes;
+  int wave_bytes;       // LDS of a wave
+  int seg_bytes;        // LDS of one walk of a wave (W < 64: 64 / W walks per wave)
   int compensated;
   // list read-back: the groups gsel[0 .. ngsel) are walked (each by the waves
   // in turn, no claim counters) and every accepted node J is recorded as J,
@@ -465,20 +466,310 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   }
 }
 
-static int wave_bytes_for(int multi, int D, int DQ) {
-  return D * 16 + (multi == 2 ? 3 * DQ * 16 : 0) + kQueueCap * 4 + 2 * 64 * 4;
+// ---------------------------------------------------------------------------
+// Walk width W < 64.  The paper shares one traversal among the T_sub threads
+// of a warp (Table 2); here a wave64 holds NSEG = 64 / W independent walks
+// ("segments") of W lanes, each with its own group, pending stack (LDS ring of
+// 8 W entries and a global spill region), interaction list and leaf-gather
+// table, all carved from the wave's LDS.  A group has up to G i-particles with
+// S = W / G lanes each.  Every count that steers a segment's loops is uniform
+// over that segment's lanes, so segments diverge from each other but never
+// inside themselves, and every ballot, prefix sum and broadcast below reads
+// lanes of its own segment only.  A segment that finds no group left leaves
+// the claim loop while the others go on.
+
+// inclusive prefix sum inside each segment of W = 2^LOGW lanes (W >= 16):
+// the row steps of wave_incl_sum, then row_bcast:15 for W = 32
+template <int LOGW>
+__device__ __forceinline__ unsigned seg_incl_sum(unsigned v) {
+  v += dpp_or_zero<0x111, 0xf>(v);
+  v += dpp_or_zero<0x112, 0xf>(v);
+  v += dpp_or_zero<0x114, 0xf>(v);
+  v += dpp_or_zero<0x118, 0xf>(v);
+  if (LOGW >= 5) v += dpp_or_zero<0x142, 0xa>(v);
+  if (LOGW >= 6) v += dpp_or_zero<0x143, 0xc>(v);
+  return v;
 }
 
-// LDS list sizes (in float4 slots, list_depth in total): monopole entries take
-// one slot; with quadrupole nodes half the budget holds particle entries and
-// half holds node entries of three slots each.  Small lists keep the LDS per
-// wave near 8 KB so 16 waves fit on a CU and hide the walk's memory latency.
-static void list_dims(int multi, int depth, int *D, int *DQ) {
+template <int MULTI, int LOGS, int LOGW, bool REC>
+__global__ void __launch_bounds__(256) walk_seg_k(WalkArgs a) {
+  constexpr int W = 1 << LOGW;
+  constexpr int NSEG = 64 >> LOGW;
+  constexpr unsigned QC = 8u * W;  // the children of W rejected nodes always fit
+  constexpr unsigned QM = QC - 1;
+  constexpr unsigned CHUNK = QC / 2;
+  extern __shared__ float4 smem[];
+  const int w = threadIdx.x >> 6;
+  const int lane = lane_id();
+  const int seg = lane >> LOGW, sl = lane & (W - 1);
+  const unsigned long long segm = (((1ull << (W - 1)) << 1) - 1ull) << (seg * W);
+  char *sbase = reinterpret_cast<char *>(smem) + (size_t)w * a.wave_bytes +
+                (size_t)seg * a.seg_bytes;
+  float4 *pl = reinterpret_cast<float4 *>(sbase);
+  float4 *ql = pl + a.D;
+  uint32_t *queue = reinterpret_cast<uint32_t *>(ql + (MULTI == 2 ? 3 * a.DQ : 0));
+  uint32_t *tpre = queue + QC;
+  uint32_t *tsrc = tpre + W;
+
+  const int64_t wslot = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
+  const int64_t slot = wslot * NSEG + seg;
+  uint32_t *spill = a.spill + slot * a.spill_cap;
+  const int G = a.G;
+  const int S = W >> a.logG;
+  const int il = sl & (G - 1), sub = sl >> a.logG;
+  Ctl *ctl = a.ctl;
+  if (ctl->flags & kFlagNodeOverflow) return;  // no valid tree: the host repeats
+  const unsigned ng = ctl->n_groups, nn = ctl->n_nodes, nsys = ctl->nsys;
+  const unsigned nwork = REC ? a.ngsel : ng;
+  const int D = a.D, DQ = a.DQ;
+  if (wslot * NSEG >= (int64_t)nwork) return;  // the whole wave has nothing to claim
+
+  unsigned long long t_node = 0, t_part = 0, t_int = 0, t_nint = 0, t_mac = 0;
+  unsigned xr = blockIdx.x % kXcds;
+  int tried = 0;
+  int64_t rec_item = slot;
+  const int64_t nslots = (int64_t)gridDim.x * (blockDim.x >> 6) * NSEG;
+  for (;;) {
+    unsigned g = ng;
+    unsigned rk = 0;
+    if (REC) {
+      if (rec_item < (int64_t)nwork) {
+        rk = (unsigned)rec_item;
+        g = a.gsel[rk];
+        if (g >= ng) g = ng;
+        rec_item += nslots;
+      }
+      tried = kXcds;
+    }
+    while (tried < kXcds) {
+      const unsigned lo = (unsigned)(((unsigned long long)xr * ng) / kXcds);
+      const unsigned hi = (unsigned)(((unsigned long long)(xr + 1) * ng) / kXcds);
+      unsigned cl = 0u;
+      if (sl == 0) cl = atomicAdd(&ctl->xwork[kXworkStride * xr], 1u);
+      cl = __shfl(cl, 0, W);
+      if (lo + cl < hi) {
+        g = lo + cl;
+        break;
+      }
+      ++tried;
+      xr = (xr + 1) % kXcds;
+    }
+    if (g >= ng) break;
+    const unsigned gs = a.gfirst[g];
+    const unsigned ge = a.gfirst[g + 1];
+    const int gc0 = (int)(ge > gs ? ge - gs : 0u);
+    const int gc = gc0 < G ? gc0 : G;
+    const float4 bl = a.ball[g];
+    const bool vi = il < gc;
+    const uint32_t ki0 = a.alist[gs + (vi ? il : 0)];
+    const uint32_t ki = ki0 < a.n ? ki0 : 0u;
+    const float4 pi = a.pos[ki];
+    const uint32_t k_first = a.alist[gs];
+    const unsigned sy = sys_of(a.soff, nsys, k_first < a.n ? k_first : 0u);
+    const float eps2 = a.sys[sy].eps2, theta = a.sys[sy].theta, inv_eps = a.sys[sy].inv_eps;
+    const float dfac = a.mac == 1 ? a.mac_delta * a.gamin[g] : 0.f;
+    Acc acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int np = 0, nq = 0;
+    unsigned qb = 0, qt = 1;
+    int64_t stop = 0;
+    unsigned long long e_node = 0, e_part = 0, n_mac = 0;
+    int64_t rec_len = 0, rec_leaves = 0;
+    if (sl == 0) queue[0] = sy;
+    wave_sync();
+
+    unsigned long long pops = 0;
+    while ((qt > qb || stop > 0) && pops <= (unsigned long long)nn) {
+      if (qt == qb) {  // LDS part empty: bring back the newest spilled entries
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        const int64_t m = stop < (int64_t)CHUNK ? stop : (int64_t)CHUNK;
+        for (int64_t t = sl; t < m; t += W) queue[(qb + t) & QM] = spill[stop - m + t];
+        stop -= m;
+        qt = qb + (unsigned)m;
+        wave_sync();
+      }
+      const unsigned nb = (qt - qb) < (unsigned)W ? (qt - qb) : (unsigned)W;
+      const bool has = (unsigned)sl < nb;
+      const unsigned qv = queue[(qt - nb + sl) & QM];
+      const unsigned node = (has && qv < nn) ? qv : 0u;
+      qt -= nb;
+      n_mac += nb;
+      pops += nb;
+      const float4 r0 = a.nrec[2 * (size_t)node];
+      const float4 r1 = a.nrec[2 * (size_t)node + 1];
+      float4 s0 = make_float4(0.f, 0.f, 0.f, 0.f), s1 = s0;
+      if (MULTI == 2) {
+        s0 = a.quad[2 * (size_t)node];
+        s1 = a.quad[2 * (size_t)node + 1];
+      }
+      const float dx = r0.x - bl.x, dy = r0.y - bl.y, dz = r0.z - bl.z;
+      const float rji = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+      const float dist = fmaxf(rji - bl.w, 0.f);
+      bool mac_ok;
+      if (a.mac == 0) {
+        mac_ok = r1.x <= theta * dist;
+      } else {
+        const bool outside = !(r1.x > 0.f && r1.x >= dist);
+        if (a.mac == 1) {
+          const float d2 = dist * dist;
+          mac_ok = outside && (r0.w * r1.x * r1.x <= dfac * (d2 * d2));
+        } else {
+          mac_ok = outside && (a.mcrit[node] <= dist);
+        }
+      }
+      const bool accept = has && qv < nn && mac_ok;
+      const bool leaf = __float_as_uint(r1.w) != 0u;
+      const bool open_leaf = has && qv < nn && !accept && leaf;
+      const bool open_int = has && qv < nn && !accept && !leaf;
+      if (REC) {
+        const unsigned long long rm = __ballot(accept || open_leaf) & segm;
+        const int64_t at = rec_len + (int64_t)lanes_below(rm);
+        if ((accept || open_leaf) && at < a.rec_cap)
+          a.rec[(int64_t)rk * a.rec_cap + at] = node | (open_leaf ? kRecLeaf : 0u);
+        rec_len += __popcll(rm);
+        rec_leaves += __popcll(__ballot(open_leaf) & segm);
+      }
+
+      // (1) accepted pseudo j-particles
+      const unsigned long long am = __ballot(accept) & segm;
+      const int nacc = __popcll(am);
+      if (nacc) {
+        if (MULTI == 1) {
+          if (np + nacc > D) {
+            flush<MULTI, LOGS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
+            np = 0; nq = 0;
+          }
+          if (accept) pl[np + lanes_below(am)] = r0;
+          np += nacc;
+        } else {
+          if (nq + nacc > DQ) {
+            flush<MULTI, LOGS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
+            np = 0; nq = 0;
+          }
+          if (accept) {
+            const int q = nq + (int)lanes_below(am);
+            ql[3 * q] = r0;
+            ql[3 * q + 1] = make_float4(3.f * s0.x, 3.f * s0.y, 3.f * s0.z, 3.f * s0.w);
+            ql[3 * q + 2] = make_float4(3.f * s1.x, 3.f * s1.y, -0.5f * s1.z, -1.5f * s1.z);
+          }
+          nq += nacc;
+        }
+        e_node += (unsigned)nacc;
+      }
+
+      // (2) children of rejected internal nodes -> pending stack
+      const unsigned nc = open_int ? __float_as_uint(r1.z) : 0u;
+      const unsigned cf = __float_as_uint(r1.y);
+      const unsigned cinc = seg_incl_sum<LOGW>(nc);
+      const unsigned C = __shfl(cinc, W - 1, W);
+      if (C) {
+        const unsigned pre = cinc - nc;
+        if ((qt - qb) + C > QC) {
+          unsigned k = (qt - qb) + C - QC;
+          k = (k + CHUNK - 1) / CHUNK * CHUNK;
+          if (k > qt - qb) k = qt - qb;
+          if (stop + k <= a.spill_cap) {
+            for (unsigned t = sl; t < k; t += W) spill[stop + t] = queue[(qb + t) & QM];
+            stop += k;
+            qb += k;
+          } else {
+            atomicOr(&ctl->flags, kFlagSpillOverflow);
+          }
+          wave_sync();
+        }
+        if ((qt - qb) + C <= QC) {
+          for (unsigned q = 0; q < nc; ++q) queue[(qt + pre + q) & QM] = cf + q;
+          qt += C;
+        }
+        wave_sync();
+      }
+
+      // (3) member particles of rejected leaves -> list
+      const unsigned pc = open_leaf ? __float_as_uint(r1.z) : 0u;
+      const unsigned pf = __float_as_uint(r1.y);
+      const unsigned pinc = seg_incl_sum<LOGW>(pc);
+      const unsigned P = __shfl(pinc, W - 1, W);
+      if (P) {
+        tpre[sl] = pinc - pc;
+        tsrc[sl] = pf;
+        wave_sync();
+        for (unsigned t0 = 0; t0 < P; t0 += W) {
+          if (np + W > D) {
+            flush<MULTI, LOGS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
+            np = 0; nq = 0;
+          }
+          const unsigned t = t0 + sl;
+          if (t < P) {
+            int o = 0;
+#pragma unroll
+            for (int step = W / 2; step >= 1; step >>= 1)
+              if (tpre[o + step] <= t) o += step;
+            const uint32_t src = tsrc[o] + (t - tpre[o]);
+            pl[np + sl] = a.pos[src < a.n ? src : 0u];
+          }
+          np += (int)((P - t0) < (unsigned)W ? (P - t0) : (unsigned)W);
+        }
+        e_part += P;
+        wave_sync();
+      }
+    }
+    if (pops > (unsigned long long)nn) atomicOr(&ctl->flags, kFlagBadIndex);
+    flush<MULTI, LOGS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
+
+    float ax = acc.x + acc.cx, ay = acc.y + acc.cy, az = acc.z + acc.cz, ap = acc.p + acc.cp;
+    for (int m = G; m < W; m <<= 1) {
+      ax += __shfl_xor(ax, m, W);
+      ay += __shfl_xor(ay, m, W);
+      az += __shfl_xor(az, m, W);
+      ap += __shfl_xor(ap, m, W);
+    }
+    const uint32_t dst = a.perm[ki];
+    if (sub == 0 && vi && ki0 < a.n && dst < a.n)
+      a.out[dst] = make_float4(ax, ay, az, -ap + pi.w * inv_eps);
+    a.gent[2 * (size_t)g] = (uint32_t)e_node;
+    a.gent[2 * (size_t)g + 1] = (uint32_t)e_part;
+    if (REC && sl == 0) {
+      a.rec_n[2 * (size_t)rk] = (uint32_t)(rec_len - rec_leaves);
+      a.rec_n[2 * (size_t)rk + 1] = (uint32_t)rec_leaves;
+    }
+    t_node += e_node;
+    t_part += e_part;
+    t_int += (unsigned long long)gc * (e_node + e_part);
+    t_nint += (unsigned long long)gc * e_node;
+    t_mac += n_mac;
+  }
+  if (!REC && sl == 0 && t_mac) {
+    atomicAdd(&ctl->node_entries, t_node);
+    atomicAdd(&ctl->part_entries, t_part);
+    atomicAdd(&ctl->interactions, t_int);
+    atomicAdd(&ctl->node_interactions, t_nint);
+    atomicAdd(&ctl->mac_tests, t_mac);
+  }
+}
+
+// LDS of one walk (a whole wave for W = 64, one segment otherwise): the
+// particle list, the quadrupole node list, the pending ring (512 entries for
+// W = 64, 8 W for a segment) and the leaf-gather table (W prefix sums and
+// sources).
+static int walk_bytes_for(int multi, int D, int DQ, int W) {
+  const int ring = W == 64 ? kQueueCap : 8 * W;
+  return D * 16 + (multi == 2 ? 3 * DQ * 16 : 0) + ring * 4 + 2 * W * 4;
+}
+
+// LDS list sizes (in float4 slots): list_depth is the budget of a wave, split
+// evenly among its 64 / W walks.  Monopole entries take one slot; with
+// quadrupole nodes half a walk's budget holds particle entries and half holds
+// node entries of three slots each.  A walk's lists hold at least one batch
+// (W entries), and for W = 64 at least 64 of each kind.  Small lists keep the
+// LDS per wave near 8 KB so 16 waves fit on a CU and hide the walk's memory
+// latency.
+static void list_dims(int multi, int depth, int W, int *D, int *DQ) {
+  const int per = depth / (64 / W);
+  const int lo = W == 64 ? 64 : W;
   if (multi == 2) {
-    *D = depth / 2 < 64 ? 64 : depth / 2;
-    *DQ = depth / 6 < 64 ? 64 : depth / 6;
+    *D = per / 2 < lo ? lo : per / 2;
+    *DQ = per / 6 < lo ? lo : per / 6;
   } else {
-    *D = depth;
+    *D = per < lo ? lo : per;
     *DQ = 0;
   }
 }
@@ -488,12 +779,31 @@ static int waves_per_block(int wb) {
   return w >= 4 ? 4 : (w < 1 ? 1 : w);
 }
 
-// walk_k<MULTI, LOGS> for the S = 64 / G the launch uses: compile-time S for
-// G = 64, 32, 16, 8 (the tuner's candidates), run-time S otherwise
+static int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// The walk kernel for group size G and walk width W (S = W / G lanes per
+// i-particle): compile-time S for the tuner's candidates, run-time S
+// otherwise.
 typedef void (*WalkFn)(WalkArgs);
+template <int MULTI, int LOGW, bool REC>
+static WalkFn walk_seg_fn(int S) {
+  switch (S) {
+    case 1: return walk_seg_k<MULTI, 0, LOGW, REC>;
+    case 2: return walk_seg_k<MULTI, 1, LOGW, REC>;
+    case 4: return walk_seg_k<MULTI, 2, LOGW, REC>;
+    default: return walk_seg_k<MULTI, -1, LOGW, REC>;
+  }
+}
+
 template <bool REC>
-static WalkFn walk_fn(int multi, int G) {
-  const int S = 64 / G;
+static WalkFn walk_fn(int multi, int G, int W) {
+  const int S = W / G;
+  if (W == 16) return multi == 2 ? walk_seg_fn<2, 4, REC>(S) : walk_seg_fn<1, 4, REC>(S);
+  if (W == 32) return multi == 2 ? walk_seg_fn<2, 5, REC>(S) : walk_seg_fn<1, 5, REC>(S);
   if (multi == 2) {
     switch (S) {
       case 1: return walk_k<2, 0, REC>;
@@ -512,32 +822,41 @@ static WalkFn walk_fn(int multi, int G) {
   }
 }
 
-// resident walk waves of the kernel for each group size G = 2^lg, kept per
-// (multipole, list depth)
+// resident walk waves of the kernel for each walk width W = 16 << lw and
+// group size G = 2^lg <= W, kept per (multipole, list depth)
 static void walk_occupancy(gothic_ctx *c) {
   const int multi = c->prm.multipole;
-  int D, DQ;
-  list_dims(multi, c->prm.list_depth, &D, &DQ);
-  if (c->slots_multi == multi && c->slots_D == D) return;
-  const int wb = wave_bytes_for(multi, D, DQ);
-  const int wpb = waves_per_block(wb);
-  for (int lg = 0; lg < kGroupSizes; ++lg) {
-    int per_cu = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, walk_fn<false>(multi, 1 << lg), wpb * 64, wpb * wb);
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
-    c->slots_g[lg] = c->num_cus * per_cu * wpb;
+  const int depth = c->prm.list_depth;
+  if (c->slots_multi == multi && c->slots_D == depth) return;
+  for (int lw = 0; lw < kWalkWidths; ++lw) {
+    const int W = 16 << lw;
+    int D, DQ;
+    list_dims(multi, depth, W, &D, &DQ);
+    const int wb = (64 / W) * walk_bytes_for(multi, D, DQ, W);
+    const int wpb = waves_per_block(wb);
+    for (int lg = 0; lg < kGroupSizes; ++lg) {
+      if ((1 << lg) > W) {
+        c->slots_g[lw][lg] = 0;
+        continue;
+      }
+      int per_cu = 0;
+      const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, walk_fn<false>(multi, 1 << lg, W), wpb * 64, wpb * wb);
+      if (e != hipSuccess || per_cu < 1) per_cu = 1;
+      c->slots_g[lw][lg] = c->num_cus * per_cu * wpb;
+    }
   }
   c->slots_multi = multi;
-  c->slots_D = D;
+  c->slots_D = depth;
 }
 
-// the most persistent waves a walk of any group size launches (the spill
-// stacks are sized for it)
+// the most persistent waves a walk of any shape launches (the spill stacks
+// are sized for it)
 int walk_slots(gothic_ctx *c) {
   walk_occupancy(c);
   int m = 0;
-  for (int lg = 0; lg < kGroupSizes; ++lg) m = c->slots_g[lg] > m ? c->slots_g[lg] : m;
+  for (int lw = 0; lw < kWalkWidths; ++lw)
+    for (int lg = 0; lg < kGroupSizes; ++lg) m = c->slots_g[lw][lg] > m ? c->slots_g[lw][lg] : m;
   return m;
 }
 
@@ -545,6 +864,8 @@ void launch_walk(gothic_ctx *c, int64_t n, float4 *acc_pot, hipStream_t s) {
   Buffers &B = c->b;
   WalkArgs a;
   const int multi = c->prm.multipole;
+  const int W = c->cur_W;
+  const int nseg = 64 / W;
   a.ctl = B.ctl;
   a.n = n;
   a.nrec = B.nrec;
@@ -557,7 +878,7 @@ void launch_walk(gothic_ctx *c, int64_t n, float4 *acc_pot, hipStream_t s) {
   a.out = acc_pot;
   a.gent = B.gent;
   a.spill = B.spill;
-  a.spill_cap = c->spill_per_wave;
+  a.spill_cap = c->spill_per_wave / nseg;  // a wave's region, split among its walks
   a.sys = B.sys;
   a.soff = B.soff;
   a.gamin = B.gamin;
@@ -565,11 +886,11 @@ void launch_walk(gothic_ctx *c, int64_t n, float4 *acc_pot, hipStream_t s) {
   a.mac_delta = c->prm.mac_delta;
   a.mac = c->prm.mac;
   a.G = c->cur_G;
-  int lg = 0;
-  while ((1 << lg) < a.G) ++lg;
+  const int lg = log2i(a.G);
   a.logG = lg;
-  list_dims(multi, c->prm.list_depth, &a.D, &a.DQ);
-  a.wave_bytes = wave_bytes_for(multi, a.D, a.DQ);
+  list_dims(multi, c->prm.list_depth, W, &a.D, &a.DQ);
+  a.seg_bytes = walk_bytes_for(multi, a.D, a.DQ, W);
+  a.wave_bytes = nseg * a.seg_bytes;
   a.compensated = c->prm.compensated;
   a.gsel = B.gsel;
   a.ngsel = B.ngsel;
@@ -579,11 +900,11 @@ void launch_walk(gothic_ctx *c, int64_t n, float4 *acc_pot, hipStream_t s) {
   const bool rec = B.rec != nullptr;
   const int wpb = waves_per_block(a.wave_bytes);
   walk_occupancy(c);
-  const int own = c->slots_g[lg];
+  const int own = c->slots_g[log2i(W) - 4][lg];
   const int slots = own < c->walk_waves ? own : c->walk_waves;
   const int blocks = slots / wpb;
-  hipLaunchKernelGGL(rec ? walk_fn<true>(multi, a.G) : walk_fn<false>(multi, a.G), dim3(blocks),
-                     dim3(wpb * 64), wpb * a.wave_bytes, s, a);
+  hipLaunchKernelGGL(rec ? walk_fn<true>(multi, a.G, W) : walk_fn<false>(multi, a.G, W),
+                     dim3(blocks), dim3(wpb * 64), wpb * a.wave_bytes, s, a);
 }
 
 }  // namespace gothic

@@ -178,7 +178,16 @@ def gate_forces(ctx, ref, out, act, eps, theta, multipole=1, mac=0, delta=0.0, a
         n_checked = tg.size
         in_window = int(info[:, 1].sum())
     e_acc = rel_rms(out[rows], target[rows])
-    e_pot = rel_rms(out[rows], target[rows], cols=slice(3, 4))
+    # The kernel forms P_i = sum_j m_j / R_ij over the list, the self pair
+    # (m_i / eps) included, and returns phi_i = -P_i + m_i / eps: its float32
+    # rounding is relative to P_i, which equals |phi_i| unless the self pair
+    # dominates (a few heavy particles).  The potential's error is measured
+    # relative to P_i.
+    m = np.empty(out.shape[0], np.float64)
+    m[perm] = ref["ps"][:, 3]
+    P = np.abs(np.asarray(target[rows][:, 3], np.float64)) + m[rows] / eps
+    d_pot = np.asarray(out[rows][:, 3], np.float64) - target[rows][:, 3]
+    e_pot = float(np.sqrt((d_pot ** 2).sum() / max((P ** 2).sum(), 1e-300)))
     g_acc = rel_rms(out[rows], ref_acc[rows])
     say(f"  {label}rms acc {e_acc:.2e} pot {e_pot:.2e} (vs the float64 tree over the same rows: "
         f"{g_acc:.2e}); groups {sel.size}, with near ties {ties.size} (replayed {n_checked}, "

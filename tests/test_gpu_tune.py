@@ -42,11 +42,13 @@ def test_autotune_choice_cache_and_parity():
     say("[gpu] autotune NFW 30000, 25% active")
     res = ctx.autotune(xt, eps, theta, active=at, out=out)
     say(f"  {res}")
-    assert res["group_size"] in (8, 16, 32, 64)
+    shapes = {(8, 64), (16, 64), (32, 64), (64, 64), (4, 16), (8, 16), (8, 32), (16, 32)}
+    assert (res["group_size"], res["walk_width"]) in shapes
     assert res["list_depth"] in (128, 256, 384, 512, 768)
-    assert res["r_crit"] < 0 and res["evaluations"] > 40 and res["ms"] > 0
+    assert res["r_crit"] < 0 and res["evaluations"] > 80 and res["ms"] > 0
     p = ctx.params
-    assert (p["group_size"], p["list_depth"]) == (res["group_size"], res["list_depth"])
+    assert (p["group_size"], p["walk_width"], p["list_depth"]) == \
+        (res["group_size"], res["walk_width"], res["list_depth"])
     assert p["r_crit"] == pytest.approx(res["r_crit"])
     o = out.cpu().numpy()
     assert np.all(np.isnan(o[act == 0])) and np.all(np.isfinite(o[act == 1]))
@@ -55,8 +57,8 @@ def test_autotune_choice_cache_and_parity():
     # same bucket: from the cache, identical choice
     res2 = ctx.autotune(xt, eps, theta, active=at, out=out)
     assert res2["evaluations"] == 0
-    assert (res2["group_size"], res2["list_depth"], res2["r_crit"]) == \
-        (res["group_size"], res["list_depth"], res["r_crit"])
+    assert (res2["group_size"], res2["walk_width"], res2["list_depth"], res2["r_crit"]) == \
+        (res["group_size"], res["walk_width"], res["list_depth"], res["r_crit"])
     # another active fraction is another bucket
     res3 = ctx.autotune(xt, eps, theta, out=out)
     assert res3["evaluations"] > 0
@@ -130,22 +132,24 @@ def _bound(x, v, eps, **kw):
 
 
 def test_group_size_per_class_replays_equal_launches():
-    """A group size per sub-step class (S = 64 / G lanes per i-particle per
-    class): captured sub-steps with one groups + walk graph per size give the
-    launched sub-steps bit for bit, and the table is what the classes use."""
+    """A group shape per sub-step class (G i-particles walked by W lanes, S =
+    W / G lanes per i-particle): captured sub-steps with one groups + walk
+    graph per shape give the launched sub-steps bit for bit, and the table is
+    what the classes use."""
     kmax = 3
     x, v = ics.plummer(6000, seed=85, with_vel=True)
-    table = [8, 64, 16, 32]
-    say(f"[gpu] group sizes per class {table}, graph vs launched")
+    table = [8, 64, 16, 8]
+    widths = [16, 64, 32, 64]
+    say(f"[gpu] group sizes per class {table}, walk widths {widths}, graph vs launched")
     runs = []
     for graph in (0, 1):
         ctx, pos, vel, mass = _bound(x, v, 1 / 64, graph=graph)
         ctx.sim_bind(pos, vel, mass, 1 / 64, 0.5, eta=0.1, kmax=kmax)
         ctx.set_params(check=0)
-        ctx.sim_set_group_sizes(table)
+        ctx.sim_set_group_sizes(table, widths)
         runs.append((ctx, pos, vel))
-    _, _, gs = runs[1][0].sim_tuning(kmax + 2, with_groups=True)
-    assert gs.tolist() == table + [32]
+    _, _, gs, ws = runs[1][0].sim_tuning(kmax + 2, with_groups=True)
+    assert gs.tolist() == table + [32] and ws.tolist() == widths + [64]
     for step in range(3 << kmax):
         for ctx, _, _ in runs:
             ctx.sim_step()
@@ -170,6 +174,10 @@ def test_group_size_per_class_replays_equal_launches():
     assert a8 == a64 == x.shape[0] and g8 >= a8 // 8 and g64 < g8
     with pytest.raises(g.GothicError):
         runs[0][0].sim_set_group_sizes([12])
+    with pytest.raises(g.GothicError):
+        runs[0][0].sim_set_group_sizes([32], [16])  # more i-particles than lanes
+    with pytest.raises(g.GothicError):
+        runs[0][0].sim_set_group_sizes([8], [8])  # not a walk width
 
 
 @pytest.mark.parametrize("graph", [0, 1])
@@ -187,9 +195,11 @@ def test_autotune_picks_group_size_per_class(graph):
         assert ctx.stats()["sticky_flags"] == 0
         runs.append((ctx, pos.cpu().numpy()))
     (c0, p0), (c1, p1) = runs
-    r, k, gs = c1.sim_tuning(kmax + 1, with_groups=True)
-    say(f"  group size per class {gs.tolist()}, r_crit searches {k.tolist()}")
-    assert set(gs.tolist()) <= {8, 16, 32, 64}
+    r, k, gs, ws = c1.sim_tuning(kmax + 1, with_groups=True)
+    say(f"  group size per class {gs.tolist()}, walk width {ws.tolist()}, r_crit searches "
+        f"{k.tolist()}")
+    shapes = {(8, 64), (16, 64), (32, 64), (64, 64), (4, 16), (8, 16), (8, 32), (16, 32)}
+    assert set(zip(gs.tolist(), ws.tolist())) <= shapes
     assert k[0] >= 1 and np.all(r[k > 0] < 0)
     dx = np.abs(p1 - p0).max(1) / (np.abs(p0).max(1) + 1e-3)
     say(f"  position difference to the untuned run: p99 {np.percentile(dx, 99):.2e}")
@@ -225,8 +235,9 @@ def test_group_sizes_with_batched_systems_and_errors():
         ctx.sim_set_group_sizes([0] * 33)  # more classes than there are
     with pytest.raises(g.GothicError):
         ctx.sim_set_group_sizes([32, 128])  # not a size the walk has
-    _, _, gs = ctx.sim_tuning(4, with_groups=True)
+    _, _, gs, ws = ctx.sim_tuning(4, with_groups=True)
     assert gs.tolist() == [16, 64, 8, 32]  # unchanged by the refused calls
+    assert ws.tolist() == [64] * 4
     with pytest.raises(g.GothicError):
         ctx.sim_tuning(33)
     # autotune = 2 on the batched run: sizes picked from the candidates
@@ -239,6 +250,6 @@ def test_group_sizes_with_batched_systems_and_errors():
     ctx2.sim_step(16 << kmax)
     torch.cuda.synchronize()
     assert ctx2.stats()["sticky_flags"] == 0
-    _, _, gs2 = ctx2.sim_tuning(kmax + 1, with_groups=True)
-    say(f"  picked group sizes per class {gs2.tolist()}")
-    assert set(gs2.tolist()) <= {8, 16, 32, 64}
+    _, _, gs2, ws2 = ctx2.sim_tuning(kmax + 1, with_groups=True)
+    say(f"  picked group sizes per class {gs2.tolist()}, walk widths {ws2.tolist()}")
+    assert set(gs2.tolist()) <= {4, 8, 16, 32, 64} and set(ws2.tolist()) <= {16, 32, 64}

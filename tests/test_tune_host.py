@@ -22,9 +22,10 @@ using gothic::GroupPicker;
 extern "C" {
 void *gp_new(int rounds) { auto *g = new GroupPicker(); g->init(rounds); return g; }
 int gp_current(void *p) { return static_cast<GroupPicker *>(p)->current(); }
+int gp_width(void *p) { return static_cast<GroupPicker *>(p)->current_width(); }
 int gp_decided(void *p) { return static_cast<GroupPicker *>(p)->decided(); }
 void gp_observe(void *p, double t) { static_cast<GroupPicker *>(p)->observe(t); }
-void gp_choose(void *p, int G) { static_cast<GroupPicker *>(p)->choose(G); }
+void gp_choose(void *p, int G, int W) { static_cast<GroupPicker *>(p)->choose(G, W); }
 void *rm_new(double n_max) { auto *r = new RebuildModels(); r->n_max = n_max; return r; }
 void rm_rebuilt(void *p, double t) { static_cast<RebuildModels *>(p)->rebuilt(t); }
 void rm_sample(void *p, double t) { static_cast<RebuildModels *>(p)->sample(t); }
@@ -93,7 +94,8 @@ def lib(tmp_path_factory):
     L.gp_current.argtypes = [P]
     L.gp_decided.argtypes = [P]
     L.gp_observe.argtypes = [P, D]
-    L.gp_choose.argtypes = [P, I]
+    L.gp_choose.argtypes = [P, I, I]
+    L.gp_width.argtypes = [P]
     L.rm_new.argtypes = [D]
     L.rm_new.restype = P
     L.rm_rebuilt.argtypes = [P, D]
@@ -247,29 +249,42 @@ def test_rebuild_becomes_due_at_the_optimum(lib):
 
 
 def test_group_picker_times_candidates_in_turn(lib):
-    """Per-class group size (the per-step S the paper leaves as future work):
-    candidates 8, 16, 32, 64 are visited round-robin, `rounds` times each, and
-    the smallest mean time wins; a later observation changes nothing."""
-    cost = {8: 3.0, 16: 2.0, 32: 2.5, 64: 4.0}
+    """Per-class group shape (the per-step S the paper leaves as future work):
+    the candidates (G, W) = (8, 64), (16, 64), (32, 64), (64, 64), (4, 16),
+    (8, 16), (8, 32), (16, 32) are visited round-robin, `rounds` times each,
+    and the smallest mean time wins; a later observation changes nothing."""
+    shapes = [(8, 64), (16, 64), (32, 64), (64, 64), (4, 16), (8, 16), (8, 32), (16, 32)]
+    cost = {(8, 64): 3.0, (16, 64): 2.0, (32, 64): 2.5, (64, 64): 4.0,
+            (4, 16): 3.5, (8, 16): 2.6, (8, 32): 2.2, (16, 32): 2.4}
     g = lib.gp_new(3)
     seen = []
     while not lib.gp_decided(g):
-        G = lib.gp_current(g)
-        seen.append(G)
+        sh = (lib.gp_current(g), lib.gp_width(g))
+        seen.append(sh)
         # an ageing tree: every later walk is slower, by more than the gap
-        # between 16 and 32 over the whole pick
-        lib.gp_observe(g, cost[G] + 0.05 * len(seen))
-    assert seen == [8, 16, 32, 64] * 3
-    assert lib.gp_current(g) == 16
+        # between the two best shapes over the whole pick
+        lib.gp_observe(g, cost[sh] + 0.01 * len(seen))
+    assert seen == shapes * 3
+    assert (lib.gp_current(g), lib.gp_width(g)) == (16, 64)
     lib.gp_observe(g, 0.0)
-    assert lib.gp_current(g) == 16
+    assert (lib.gp_current(g), lib.gp_width(g)) == (16, 64)
     # noise that reverses one round does not reverse the means
     g2 = lib.gp_new(2)
-    times = iter([3.0, 2.9, 2.5, 4.0, 3.0, 1.0, 2.5, 4.0])
+    times = iter([3.0, 2.9, 2.5, 4.0, 3.3, 3.0, 2.4, 2.6,
+                  3.0, 1.0, 2.5, 4.0, 3.3, 3.0, 2.4, 2.6])
     while not lib.gp_decided(g2):
         lib.gp_observe(g2, next(times))
-    assert lib.gp_current(g2) == 16  # means 3.0, 1.95, 2.5, 4.0
-    # a size fixed from outside
+    assert (lib.gp_current(g2), lib.gp_width(g2)) == (16, 64)  # 1.95 against 2.4 for (8, 32)
+    # a walk width below 64 can win
+    g4 = lib.gp_new(1)
+    times = iter([3.0, 2.9, 2.5, 4.0, 3.3, 3.0, 2.0, 2.6])
+    while not lib.gp_decided(g4):
+        lib.gp_observe(g4, next(times))
+    assert (lib.gp_current(g4), lib.gp_width(g4)) == (8, 32)
+    # a shape fixed from outside
     g3 = lib.gp_new(2)
-    lib.gp_choose(g3, 64)
-    assert lib.gp_decided(g3) and lib.gp_current(g3) == 64
+    lib.gp_choose(g3, 64, 64)
+    assert lib.gp_decided(g3) and lib.gp_current(g3) == 64 and lib.gp_width(g3) == 64
+    g5 = lib.gp_new(2)
+    lib.gp_choose(g5, 8, 16)
+    assert lib.gp_decided(g5) and (lib.gp_current(g5), lib.gp_width(g5)) == (8, 16)

@@ -62,12 +62,17 @@ def walk_traffic():
         return None
 
 
-def run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, shared, steps, warmup):
+def run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, shared, steps, warmup,
+            class_groups=None):
+    """class_groups: group size per sub-step class (S per step), or None."""
     import torch
     pos = pos0.clone()
     vel = vel0.clone()
     ctx.set_params(check=1)
     ctx.sim_bind(pos, vel, mass, eps, theta, eta=eta, kmax=kmax, shared=shared)
+    if class_groups and not shared:
+        table = [class_groups[min(c, len(class_groups) - 1)] for c in range(kmax + 1)]
+        ctx.sim_set_group_sizes(table)
     # warm-up: checked steps (they grow any scratch), the last one unchecked
     # (with params.graph it is the capture)
     for i in range(warmup):
@@ -660,6 +665,10 @@ def main():
     ap.add_argument("--group-size", type=int, default=32)
     ap.add_argument("--walk-width", type=int, default=64, choices=(16, 32, 64),
                     help="lanes sharing one traversal (64: one group per wave)")
+    ap.add_argument("--class-groups", default="",
+                    help="group size per sub-step class of the block steps, comma-separated "
+                         "from class 0 (the last value repeats), e.g. 8,16,32; default: "
+                         "--group-size for every class")
     ap.add_argument("--list-depth", type=int, default=384)
     ap.add_argument("--r-crit", type=float, default=0.25,
                     help="critical separation splitting groups (Section 2.4)")
@@ -754,7 +763,9 @@ def main():
                     autotune=args.autotune)
 
     log(f"bench: block steps (warmup {args.warmup}, timed {args.steps})")
-    blk = run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, False, args.steps, args.warmup)
+    class_groups = [int(v) for v in args.class_groups.split(",") if v.strip()]
+    blk = run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, False, args.steps, args.warmup,
+                  class_groups=class_groups or None)
     tuning = None
     if args.autotune:
         # the online tuner's state after the block run: r_crit and (with
@@ -801,7 +812,7 @@ def main():
                    "n": n, "group_size": args.group_size, "walk_width": args.walk_width,
                    "list_depth": args.list_depth, "r_crit": args.r_crit, "graph": args.graph,
                    "rebuild_interval": args.rebuild_interval, "ball": args.ball,
-                   "autotune": args.autotune,
+                   "autotune": args.autotune, "class_groups": args.class_groups or None,
                    "parallelism": "single GPU"},
         "block": {"s_per_step": blk["seconds"] / args.steps,
                   "interactions_per_s": inter / blk["seconds"],

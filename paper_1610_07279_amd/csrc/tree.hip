@@ -5,8 +5,9 @@
 // digit changes.  The tree is built one level at a time, breadth first, with
 // every count on the device:
 //   count: each level-l node holding more than n_leaf particles (and above
-//          level 21) finds its child boundaries by a lock-step binary search
-//          of the seven digit changes and counts its non-empty children;
+//          level 21) finds its child boundaries by searching for the seven
+//          digit changes (nine-way steps over long runs, then bisection) and
+//          counts its non-empty children;
 //          other nodes become leaves;
 //   scan:  exclusive prefix sum of the child counts = serial numbers of the
 //          level-(l+1) nodes (the prefix sums of Section 2.1);
@@ -104,11 +105,39 @@ build_count_k(int l, int n_leaf, int64_t n, int64_t cap_nodes, int64_t cap_level
     if ((int64_t)f + c > n) {
       atomicOr(&ctl->flags, kFlagBadIndex);
     } else if (c > (uint32_t)n_leaf && l < kNlev) {
-      // lower_bound of digit >= d for d = 1..7, all searches in lock step
+      // the first index with digit >= d, for d = 1..7: each lies in [a[d], b[d]]
+      // (indices below a[d] have a smaller digit, those from b[d] on one at
+      // least d).  Runs of more than 2^16 (the few nodes of the top levels,
+      // where the search latency is not hidden by other nodes) are narrowed
+      // by eight probes per digit and round (every load of a round in
+      // flight at once); then bisection, all digits in lock step.
       uint32_t a[8], b[8];
 #pragma unroll
       for (int d = 1; d < 8; ++d) { a[d] = f; b[d] = f + c; }
-      for (uint32_t len = c; len > 0; len >>= 1) {
+      for (uint32_t len = c; len > 64 && c > 65536u; len = (len + 8) / 9) {
+#pragma unroll
+        for (int d = 1; d < 8; ++d) {
+          const uint32_t span = b[d] - a[d];
+          if (span <= 8) continue;
+          uint32_t q[8];
+          bool g[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            q[j] = a[d] + (uint32_t)(((uint64_t)span * (uint64_t)(j + 1)) / 9u);
+            g[j] = digit_at(ks[q[j]], shift) >= (unsigned)d;
+          }
+          uint32_t na = a[d], nb = b[d];
+#pragma unroll
+          for (int j = 7; j >= 0; --j)
+            if (g[j]) nb = q[j];
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (!g[j]) na = q[j] + 1;
+          a[d] = na;
+          b[d] = nb;
+        }
+      }
+      for (uint32_t len = c > 65536u ? 64u : c; len > 0; len >>= 1) {
 #pragma unroll
         for (int d = 1; d < 8; ++d) {
           if (a[d] < b[d]) {

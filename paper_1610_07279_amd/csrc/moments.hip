@@ -315,6 +315,32 @@ __device__ __forceinline__ unsigned seg_max_scan(unsigned v, unsigned head) {
 __device__ __forceinline__ void radius_level(float4 *nrec, RadiusCarry &rc, int w, int l,
                                              unsigned key, float dist, bool at_start) {
   const int lane = lane_id();
+  // one node under the whole tile (the tiles of the upper levels): keys are
+  // contiguous runs, so equal first and last keys mean a single run, whose
+  // maximum is a plain scan over the wave
+  const unsigned k0 = (unsigned)__builtin_amdgcn_readfirstlane((int)key);
+  const unsigned k63 = (unsigned)__builtin_amdgcn_readlane((int)key, 63);
+  if (k0 == k63 && k0 != kNone) {
+    const float mx = __uint_as_float((unsigned)__builtin_amdgcn_readlane(
+        (int)seg_max_scan(__float_as_uint(dist), lane == 0 ? 1u : 0u), 63));
+    unsigned rn = __builtin_amdgcn_readfirstlane(rc.node[w][l]);
+    float rm = rc.max[w][l];
+    bool ropen = __builtin_amdgcn_readfirstlane(rc.open[w][l]) != 0u;
+    if (k0 == rn) {
+      rm = fmaxf(rm, mx);
+    } else {
+      if (rn != kNone) put_b(nrec, rn, rm, ropen);
+      rn = k0;
+      rm = mx;
+      ropen = at_start;
+    }
+    rc.node[w][l] = rn;  // same value from every lane
+    rc.max[w][l] = rm;
+    rc.open[w][l] = ropen ? 1u : 0u;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    return;
+  }
   const bool part = key != kNone;
   // runs of equal key: heads from the previous lane's key, the run maximum
   // at each run's last lane

@@ -165,7 +165,7 @@ def test_list_depth_and_compensation(D, comp):
     _check_forces(ics.nfw(7000, seed=12), 1 / 128, 0.5, list_depth=D, compensated=comp)
 
 
-@pytest.mark.parametrize("G", [32, 8])
+@pytest.mark.parametrize("G", [32, 8, 1])
 def test_quadrupole(G):
     _check_forces(ics.nfw(20000, seed=13), 1 / 128, 0.5, multipole=2, group_size=G)
 

@@ -15,8 +15,8 @@
 //   accepted nodes        -> the LDS interaction list (pseudo particles),
 //   rejected internal     -> their children onto the pending stack,
 //   rejected leaves       -> their member particles to the LDS list.
-// The pending nodes form a last-in-first-out stack whose top lives in an LDS
-// ring and whose older part spills to a per-wave global stack.  Taking the
+// The pending nodes form a last-in-first-out stack whose top lives in LDS
+// and whose older part spills to a per-wave global stack.  Taking the
 // newest 64 nodes first keeps the stack near depth x 512 entries, where a
 // first-in-first-out frontier would grow to a whole tree level for groups
 // spread over the system (sparse block-step groups).  The set of interactions
@@ -40,9 +40,11 @@
 
 namespace gothic {
 
-constexpr int kQueueCap = 512;   // LDS part of the pending stack per wave (power of two)
+// LDS part of the pending stack per wave: room for the children of 64 opened
+// nodes (8 each), so one batch's pushes always fit once older entries spill
+constexpr int kQueueCap = 512;
+constexpr int kQueueSlack = 8;   // above the LDS stack: the child writes run up to 7 past it
 constexpr int kXcds = 8;         // MI355X: 8 XCDs, workgroups dispatched round-robin
-constexpr int kQueueMask = kQueueCap - 1;
 constexpr int kSpillChunk = 256;  // entries moved to the global stack at a time
 
 struct WalkArgs {
@@ -150,15 +152,17 @@ __device__ __forceinline__ void quad_term(const float4 q0, const float4 q1, cons
 // The list is split into rounds of S entries, lane sub of an i-particle
 // taking entry round * S + sub.  Full rounds run under wave-uniform loop
 // control (scalar compare, immediate LDS offsets in the unrolled body); the
-// last partial round, if any, under per-lane control.
-template <int MULTI, int LOGS>
+// last partial round, if any, under per-lane control.  LISTS selects the
+// lists evaluated (bit 0 particles, bit 1 quadrupole nodes): a full list is
+// flushed alone, both at the end of the walk.
+template <int MULTI, int LOGS, int LISTS = 3>
 __device__ __forceinline__ void flush(const WalkArgs &a, const float4 *pl, const float4 *ql,
                                       int np, int nq, float4 pi, float eps2, int sub, int S_rt,
                                       Acc &acc) {
   wave_sync();
   const int S = lanes_per_i<LOGS>(S_rt);
   float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
-  {
+  if (LISTS & 1) {
     constexpr int U = 4;
     const float4 *pj = pl + sub;
     int k0 = 0;
@@ -168,7 +172,7 @@ __device__ __forceinline__ void flush(const WalkArgs &a, const float4 *pl, const
     }
     for (int k = k0 + sub; k < np; k += S) mono_term(pl[k], pi, eps2, fx, fy, fz, fp);
   }
-  if (MULTI == 2) {
+  if (MULTI == 2 && (LISTS & 2)) {
     constexpr int U = 2;
     const float4 *qj = ql + 3 * sub;
     int k0 = 0;
@@ -202,7 +206,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   float4 *pl = reinterpret_cast<float4 *>(wbase);
   float4 *ql = pl + a.D;  // quadrupole entries, three float4 each
   uint32_t *queue = reinterpret_cast<uint32_t *>(ql + (MULTI == 2 ? 3 * a.DQ : 0));
-  uint32_t *tpre = queue + kQueueCap;
+  uint32_t *tpre = queue + kQueueCap + kQueueSlack;
   uint32_t *tsrc = tpre + 64;
 
   const int64_t slot = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
@@ -274,9 +278,9 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     const float dfac = a.mac == 1 ? a.mac_delta * a.gamin[g] : 0.f;
     Acc acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int np = 0, nq = 0;
-    // LDS ring holds stack entries [qb, qt) (ring positions mod kQueueCap);
-    // the global stack holds the older entries [0, stop)
-    unsigned qb = 0, qt = 1;
+    // the LDS stack holds the newest entries [0, qt), the global stack the
+    // older entries [0, stop)
+    unsigned qt = 1;
     int64_t stop = 0;
     unsigned long long e_node = 0, e_part = 0, n_mac = 0;
     int64_t rec_len = 0, rec_leaves = 0;
@@ -286,19 +290,20 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     // a valid walk pops every node at most once; the bound only guards
     // against a corrupted tree
     unsigned long long pops = 0;
-    while ((qt > qb || stop > 0) && pops <= (unsigned long long)nn) {
-      if (qt == qb) {  // LDS part empty: bring back the newest spilled entries
+    while ((qt > 0 || stop > 0) && pops <= (unsigned long long)nn) {
+      if (qt == 0) {  // LDS part empty: bring back the newest spilled entries
         // the spill entries were written by other lanes of this wave
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
         const int64_t m = stop < kQueueCap / 2 ? stop : kQueueCap / 2;
-        for (int64_t t = lane; t < m; t += 64) queue[(qb + t) & kQueueMask] = spill[stop - m + t];
+        for (int64_t t = lane; t < m; t += 64) queue[t] = spill[stop - m + t];
         stop -= m;
-        qt = qb + (unsigned)m;
+        qt = (unsigned)m;
         wave_sync();
       }
-      const unsigned nb = (qt - qb) < 64u ? (qt - qb) : 64u;
+      const unsigned nb = qt < 64u ? qt : 64u;
       const bool has = (unsigned)lane < nb;
-      const unsigned qv = queue[(qt - nb + lane) & kQueueMask];
+      // below max(qt, 64) <= kQueueCap for every lane
+      const unsigned qv = queue[qt - nb + lane];
       // lanes without a node read the root; an entry past the node count
       // (never produced by a valid tree) is dropped the same way
       const unsigned node = (has && qv < nn) ? qv : 0u;
@@ -360,8 +365,8 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
           np += nacc;
         } else {
           if (nq + nacc > DQ) {
-            flush<MULTI, LOGS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
-            np = 0; nq = 0;
+            flush<MULTI, LOGS, 2>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
+            nq = 0;
           }
           if (accept) {
             const int q = nq + (int)lanes_below(am);
@@ -375,28 +380,52 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       }
 
       // (2) children of rejected internal nodes -> pending stack
-      const unsigned nc = open_int ? __float_as_uint(r1.z) : 0u;
+      const unsigned nc0 = open_int ? __float_as_uint(r1.z) : 0u;
+      const unsigned nc = nc0 < 8u ? nc0 : 8u;  // an octree node has at most eight
       const unsigned cf = __float_as_uint(r1.y);
-      const unsigned cinc = wave_incl_sum(nc);
+      unsigned cinc = wave_incl_sum(nc);
       const unsigned C = wave_last(cinc);
       if (C) {
+        // keeps the compiler from rebuilding cinc - nc out of the scan's terms
+        asm volatile("" : "+v"(cinc));
         const unsigned pre = cinc - nc;
-        if ((qt - qb) + C > (unsigned)kQueueCap) {
+        if (qt + C > (unsigned)kQueueCap) {
           // move the oldest LDS entries to the global stack to make room
-          unsigned k = (qt - qb) + C - (unsigned)kQueueCap;
+          unsigned k = qt + C - (unsigned)kQueueCap;
           k = (k + kSpillChunk - 1) / kSpillChunk * kSpillChunk;
-          if (k > qt - qb) k = qt - qb;
+          if (k > qt) k = qt;
           if (stop + k <= a.spill_cap) {
-            for (unsigned t = lane; t < k; t += 64) spill[stop + t] = queue[(qb + t) & kQueueMask];
+            for (unsigned t = lane; t < k; t += 64) spill[stop + t] = queue[t];
             stop += k;
-            qb += k;
+            // shift the remaining entries to the bottom, 64 at a time from
+            // the bottom up: each round reads above what it writes
+            const unsigned rest = qt - k;
+            for (unsigned t0 = 0; t0 < rest; t0 += 64) {
+              const unsigned t = t0 + lane;
+              const uint32_t v = t < rest ? queue[k + t] : 0u;
+              wave_sync();
+              if (t < rest) queue[t] = v;
+              wave_sync();
+            }
+            qt = rest;
           } else {
             atomicOr(&ctl->flags, kFlagSpillOverflow);  // all lanes, same bit
           }
           wave_sync();
         }
-        if ((qt - qb) + C <= (unsigned)kQueueCap) {
-          for (unsigned q = 0; q < nc; ++q) queue[(qt + pre + q) & kQueueMask] = cf + q;
+        if (qt + C <= (unsigned)kQueueCap) {
+          if (nc) {
+            // all eight slots from the node's first child on are written,
+            // the highest first: a slot past this node's children belongs to
+            // a later lane, which writes it at a lower child index, hence
+            // later; slots past the last child land in the slack above
+            uint32_t *dst = queue + qt + pre;
+#pragma unroll
+            for (int q = 7; q >= 0; --q) {
+              dst[q] = cf + (unsigned)q;
+              __atomic_signal_fence(__ATOMIC_SEQ_CST);  // keeps the stores in this order
+            }
+          }
           qt += C;
         }
         wave_sync();
@@ -413,8 +442,8 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
         wave_sync();
         for (unsigned t0 = 0; t0 < P; t0 += 64) {
           if (np + 64 > D) {
-            flush<MULTI, LOGS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
-            np = 0; nq = 0;
+            flush<MULTI, LOGS, 1>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
+            np = 0;
           }
           const unsigned t = t0 + lane;
           if (t < P) {
@@ -747,11 +776,11 @@ __global__ void __launch_bounds__(256) walk_seg_k(WalkArgs a) {
 }
 
 // LDS of one walk (a whole wave for W = 64, one segment otherwise): the
-// particle list, the quadrupole node list, the pending ring (512 entries for
+// particle list, the quadrupole node list, the pending stack (512 + 8 entries for
 // W = 64, 8 W for a segment) and the leaf-gather table (W prefix sums and
 // sources).
 static int walk_bytes_for(int multi, int D, int DQ, int W) {
-  const int ring = W == 64 ? kQueueCap : 8 * W;
+  const int ring = W == 64 ? kQueueCap + kQueueSlack : 8 * W;
   return D * 16 + (multi == 2 ? 3 * DQ * 16 : 0) + ring * 4 + 2 * W * 4;
 }
 

@@ -28,41 +28,50 @@ template <int CTRL>
 __device__ __forceinline__ float row_dpp(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
-// sum / max over the 16 lanes of a row (lanes 16r .. 16r+15), in every lane:
-// rotate by 8 and 4 within the row, then swap lane pairs of each quad
-// (quad_perm [2,3,0,1] and [1,0,3,2])
-__device__ __forceinline__ float row_sum16(float v) {
-  v += row_dpp<0x128>(v);  // row_ror:8
-  v += row_dpp<0x124>(v);  // row_ror:4
+// sum / max over aligned groups of L lanes (L = 4 or 16), in every lane:
+// for L = 16 rotate by 8 and 4 within the row first; then swap lane pairs
+// of each quad (quad_perm [2,3,0,1] and [1,0,3,2])
+template <int L>
+__device__ __forceinline__ float grp_sum(float v) {
+  if (L == 16) {
+    v += row_dpp<0x128>(v);  // row_ror:8
+    v += row_dpp<0x124>(v);  // row_ror:4
+  }
   v += row_dpp<0x4e>(v);
   v += row_dpp<0xb1>(v);
   return v;
 }
-__device__ __forceinline__ float row_max16(float v) {
-  v = fmaxf(v, row_dpp<0x128>(v));
-  v = fmaxf(v, row_dpp<0x124>(v));
+template <int L>
+__device__ __forceinline__ float grp_max(float v) {
+  if (L == 16) {
+    v = fmaxf(v, row_dpp<0x128>(v));
+    v = fmaxf(v, row_dpp<0x124>(v));
+  }
   v = fmaxf(v, row_dpp<0x4e>(v));
   v = fmaxf(v, row_dpp<0xb1>(v));
   return v;
 }
 
-// Leaves: 16 lanes per node, each lane taking members lane, lane + 16, ...
-// (coalesced loads, held in registers for both passes), sums and maxima
-// reduced across the row.  Rows whose
-// node is internal take no part but run the same shuffles.
+// Leaves: L lanes per node (4 when leaves hold at most 16 particles, else
+// 16), each lane taking members lane, lane + L, ... (coalesced loads, the
+// first 4 L held in registers for both passes), sums and maxima reduced
+// across the L lanes.  Groups whose node is internal take no part but run the
+// same shuffles.
+template <int L>
 __global__ void __launch_bounds__(256)
 leaf_moments_k(Ctl *__restrict__ ctl, int64_t n, const uint32_t *__restrict__ first,
                const uint32_t *__restrict__ count, const uint8_t *__restrict__ n_child,
-               const float4 *__restrict__ pos, uint32_t *__restrict__ leaf_of,
-               float4 *__restrict__ nrec, float4 *__restrict__ quad, int want_quad) {
+               const float4 *__restrict__ pos, float4 *__restrict__ nrec,
+               float4 *__restrict__ quad, int want_quad) {
   if (ctl->flags & kFlagNodeOverflow) return;  // incomplete tree: nothing to do
+  constexpr int NPW = 64 / L;                  // nodes per wave pass
   const int64_t nn = ctl->n_nodes;
   const int lane = lane_id();
-  const int rl = lane & 15;
+  const int rl = lane & (L - 1);
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t k0 = wave * 4; k0 < nn; k0 += nwaves * 4) {  // wave-uniform
-    const int64_t k = k0 + (lane >> 4);
+  for (int64_t k0 = wave * NPW; k0 < nn; k0 += nwaves * NPW) {  // wave-uniform
+    const int64_t k = k0 + lane / L;
     bool leaf = k < nn && n_child[k] == 0;
     const uint32_t f = leaf ? first[k] : 0u, c = leaf ? count[k] : 0u;
     if (leaf && (c == 0 || (int64_t)f + c > n)) {
@@ -71,14 +80,13 @@ leaf_moments_k(Ctl *__restrict__ ctl, int64_t n, const uint32_t *__restrict__ fi
     }
     const uint32_t cnt = leaf ? c : 0u;
     const float4 p0 = pos[leaf ? f : 0u];
-    // the first 64 members (all of them unless particles share a level-21
+    // the first 4 L members (all of them unless particles share a level-21
     // cell): up to four per lane, kept in registers for the second pass
     float4 m[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const uint32_t t = (uint32_t)rl + 16u * u;
+      const uint32_t t = (uint32_t)rl + (uint32_t)L * u;
       m[u] = t < cnt ? pos[f + t] : make_float4(0.f, 0.f, 0.f, 0.f);
-      if (t < cnt) leaf_of[f + t] = (uint32_t)k;
     }
     float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
 #pragma unroll
@@ -88,18 +96,17 @@ leaf_moments_k(Ctl *__restrict__ ctl, int64_t n, const uint32_t *__restrict__ fi
       sy += m[u].w * (m[u].y - p0.y);
       sz += m[u].w * (m[u].z - p0.z);
     }
-    for (uint32_t t = (uint32_t)rl + 64u; t < cnt; t += 16) {  // members past 64
+    for (uint32_t t = (uint32_t)rl + 4u * L; t < cnt; t += L) {  // members past 4 L
       const float4 p = pos[f + t];
       M += p.w;
       sx += p.w * (p.x - p0.x);
       sy += p.w * (p.y - p0.y);
       sz += p.w * (p.z - p0.z);
-      leaf_of[f + t] = (uint32_t)k;
     }
-    M = row_sum16(M);
-    sx = row_sum16(sx);
-    sy = row_sum16(sy);
-    sz = row_sum16(sz);
+    M = grp_sum<L>(M);
+    sx = grp_sum<L>(sx);
+    sy = grp_sum<L>(sy);
+    sz = grp_sum<L>(sz);
     float cx = p0.x, cy = p0.y, cz = p0.z;
     if (M > 0.f) {
       cx = p0.x + sx / M;
@@ -109,24 +116,24 @@ leaf_moments_k(Ctl *__restrict__ ctl, int64_t n, const uint32_t *__restrict__ fi
     float b2 = 0.f, xx = 0.f, yy = 0.f, zz = 0.f, xy = 0.f, xz = 0.f, yz = 0.f;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if ((uint32_t)rl + 16u * u >= cnt) continue;
+      if ((uint32_t)rl + (uint32_t)L * u >= cnt) continue;
       const float4 p = m[u];
       const float dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
       b2 = fmaxf(b2, dx * dx + dy * dy + dz * dz);
       xx += p.w * dx * dx; yy += p.w * dy * dy; zz += p.w * dz * dz;
       xy += p.w * dx * dy; xz += p.w * dx * dz; yz += p.w * dy * dz;
     }
-    for (uint32_t t = (uint32_t)rl + 64u; t < cnt; t += 16) {
+    for (uint32_t t = (uint32_t)rl + 4u * L; t < cnt; t += L) {
       const float4 p = pos[f + t];
       const float dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
       b2 = fmaxf(b2, dx * dx + dy * dy + dz * dz);
       xx += p.w * dx * dx; yy += p.w * dy * dy; zz += p.w * dz * dz;
       xy += p.w * dx * dy; xz += p.w * dx * dz; yz += p.w * dy * dz;
     }
-    b2 = row_max16(b2);
+    b2 = grp_max<L>(b2);
     if (want_quad) {
-      xx = row_sum16(xx); yy = row_sum16(yy); zz = row_sum16(zz);
-      xy = row_sum16(xy); xz = row_sum16(xz); yz = row_sum16(yz);
+      xx = grp_sum<L>(xx); yy = grp_sum<L>(yy); zz = grp_sum<L>(zz);
+      xy = grp_sum<L>(xy); xz = grp_sum<L>(xz); yz = grp_sum<L>(yz);
     } else {
       xx = yy = zz = xy = xz = yz = 0.f;
     }
@@ -321,8 +328,7 @@ __device__ __forceinline__ void radius_level(float4 *nrec, RadiusCarry &rc, int 
   const unsigned k0 = (unsigned)__builtin_amdgcn_readfirstlane((int)key);
   const unsigned k63 = (unsigned)__builtin_amdgcn_readlane((int)key, 63);
   if (k0 == k63 && k0 != kNone) {
-    const float mx = __uint_as_float((unsigned)__builtin_amdgcn_readlane(
-        (int)seg_max_scan(__float_as_uint(dist), lane == 0 ? 1u : 0u), 63));
+    const float mx = __uint_as_float(wave_last(wave_incl_max(__float_as_uint(dist))));
     unsigned rn = __builtin_amdgcn_readfirstlane(rc.node[w][l]);
     float rm = rc.max[w][l];
     bool ropen = __builtin_amdgcn_readfirstlane(rc.open[w][l]) != 0u;
@@ -498,8 +504,15 @@ void launch_moments(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
   const int wq = (c->prm.multipole == 2 || c->prm.mac == 2) ? 1 : 0;
   int64_t nb = (c->cap_nodes + 15) / 16;  // 16 nodes per workgroup pass
   int g = (int)(nb > 8192 ? 8192 : (nb < 1 ? 1 : nb));
-  hipLaunchKernelGGL(leaf_moments_k, dim3(g), dim3(256), 0, s, B.ctl, n, B.first, B.count,
-                     B.n_child, B.pos, B.leaf_of, B.nrec, B.quad, wq);
+  if (c->prm.n_leaf <= 16) {
+    int64_t nb4 = (c->cap_nodes + 63) / 64;  // 64 nodes per workgroup pass
+    int g4 = (int)(nb4 > 8192 ? 8192 : (nb4 < 1 ? 1 : nb4));
+    hipLaunchKernelGGL(leaf_moments_k<4>, dim3(g4), dim3(256), 0, s, B.ctl, n, B.first, B.count,
+                       B.n_child, B.pos, B.nrec, B.quad, wq);
+  } else {
+    hipLaunchKernelGGL(leaf_moments_k<16>, dim3(g), dim3(256), 0, s, B.ctl, n, B.first, B.count,
+                       B.n_child, B.pos, B.nrec, B.quad, wq);
+  }
   for (int l = kNlev - 1; l >= 0; --l) {
     int64_t widest = nsys;
     for (int q = 0; q < l && widest < c->cap_nodes; ++q) widest *= 8;

@@ -33,6 +33,18 @@ __device__ __forceinline__ unsigned wave_incl_sum(unsigned v) {
   return v;
 }
 
+// inclusive prefix maximum over the 64 lanes (all lanes active), the steps
+// of wave_incl_sum
+__device__ __forceinline__ unsigned wave_incl_max(unsigned v) {
+  v = max(v, dpp_or_zero<0x111, 0xf>(v));
+  v = max(v, dpp_or_zero<0x112, 0xf>(v));
+  v = max(v, dpp_or_zero<0x114, 0xf>(v));
+  v = max(v, dpp_or_zero<0x118, 0xf>(v));
+  v = max(v, dpp_or_zero<0x142, 0xa>(v));
+  v = max(v, dpp_or_zero<0x143, 0xc>(v));
+  return v;
+}
+
 // the value of lane 63
 __device__ __forceinline__ unsigned wave_last(unsigned v) {
   return (unsigned)__builtin_amdgcn_readlane((int)v, 63);

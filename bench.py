@@ -756,6 +756,8 @@ def main():
         flags = ctx.stats()["flags"]
         print(json.dumps({"forces_only": args.forces_only, "n": n, "interactions": st["interactions"],
                           "node_interactions": st["node_interactions"],
+                          "node_entries": st["node_entries"], "part_entries": st["part_entries"],
+                          "n_groups": st["n_groups"], "mac_tests": st["mac_tests"],
                           "walk_ms_mean": ms / max(k, 1), "flags": flags}), flush=True)
         return
     pos0 = torch.from_numpy(x[:, :3].astype(np.float64)).to(dev)

@@ -23,8 +23,9 @@
 // does not depend on the order in which pending nodes are tested.
 // When the list is full it is flushed: every lane accumulates the softened
 // force and potential of its i-particle from the list entries (broadcast LDS
-// reads, FP32 with the hardware reciprocal square root).  With G < 64 the
-// S = 64/G lanes sharing an i-particle take every S-th entry
+// reads, FP32 with the hardware reciprocal square root).  A group of gc <= G
+// particles is laid out on the fewest power-of-two slots that hold it, and the
+// S = 64 / slots lanes sharing an i-particle take every S-th entry
 // (ij-parallelisation) and are summed at the end.  Each flush's partial sums
 // are added to the running totals with Neumaier compensation (or plainly).
 //
@@ -197,6 +198,19 @@ __device__ __forceinline__ void flush(const WalkArgs &a, const float4 *pl, const
   wave_sync();
 }
 
+// The flush for a group's lane shape: shape 0 is the kernel's own (G
+// i-particles, S = 64 / G lanes each), shape 1 half as many i-particles with
+// twice the lanes (both with compile-time S), shape 2 fewer still (run-time S).
+template <int MULTI, int LOGS, int LISTS = 3>
+__device__ __forceinline__ void flush_shape(int shape, const WalkArgs &a, const float4 *pl,
+                                            const float4 *ql, int np, int nq, float4 pi,
+                                            float eps2, int sub, int S, Acc &acc) {
+  constexpr int LOGS1 = LOGS >= 0 && LOGS < 6 ? LOGS + 1 : -1;
+  if (shape == 0) flush<MULTI, LOGS, LISTS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
+  else if (shape == 1) flush<MULTI, LOGS1, LISTS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
+  else flush<MULTI, -1, LISTS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
+}
+
 template <int MULTI, int LOGS, bool REC>
 __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   extern __shared__ float4 smem[];
@@ -215,8 +229,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
   // a cross-lane operation inside a loop: the compiler may otherwise split the
   // loops by lane and leave a shuffle reading an inactive lane.
   uint32_t *spill = a.spill + slot * a.spill_cap;
-  const int G = a.G, S = 64 >> a.logG;
-  const int il = lane & (G - 1), sub = lane >> a.logG;
+  const int G = a.G;
   Ctl *ctl = a.ctl;
   if (ctl->flags & kFlagNodeOverflow) return;  // no valid tree: the host repeats
   const unsigned ng = ctl->n_groups, nn = ctl->n_nodes, nsys = ctl->nsys;
@@ -265,6 +278,14 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
     const int gc0 = (int)(ge > gs ? ge - gs : 0u);
     const int gc = gc0 < G ? gc0 : G;
     const float4 bl = a.ball[g];
+    // The group's gc particles take the fewest of 2^lgx <= G slots that hold
+    // them, each slot S = 64 / 2^lgx lanes: a group split short by r_crit
+    // (sparse regions, few active particles) keeps every lane of the flush.
+    int lgx = a.logG;
+    while (lgx > 0 && (1 << (lgx - 1)) >= gc) --lgx;  // wave-uniform
+    const int shape = lgx == a.logG ? 0 : (lgx == a.logG - 1 ? 1 : 2);
+    const int Gx = 1 << lgx, S = 64 >> lgx;
+    const int il = lane & (Gx - 1), sub = lane >> lgx;
     const bool vi = il < gc;
     const uint32_t ki0 = a.alist[gs + (vi ? il : 0)];
     const uint32_t ki = ki0 < a.n ? ki0 : 0u;
@@ -358,14 +379,14 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       if (nacc) {
         if (MULTI == 1) {
           if (np + nacc > D) {
-            flush<MULTI, LOGS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
+            flush_shape<MULTI, LOGS>(shape, a, pl, ql, np, nq, pi, eps2, sub, S, acc);
             np = 0; nq = 0;
           }
           if (accept) pl[np + lanes_below(am)] = r0;
           np += nacc;
         } else {
           if (nq + nacc > DQ) {
-            flush<MULTI, LOGS, 2>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
+            flush_shape<MULTI, LOGS, 2>(shape, a, pl, ql, np, nq, pi, eps2, sub, S, acc);
             nq = 0;
           }
           if (accept) {
@@ -442,7 +463,7 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
         wave_sync();
         for (unsigned t0 = 0; t0 < P; t0 += 64) {
           if (np + 64 > D) {
-            flush<MULTI, LOGS, 1>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
+            flush_shape<MULTI, LOGS, 1>(shape, a, pl, ql, np, nq, pi, eps2, sub, S, acc);
             np = 0;
           }
           const unsigned t = t0 + lane;
@@ -461,10 +482,10 @@ __global__ void __launch_bounds__(256) walk_k(WalkArgs a) {
       }
     }
     if (pops > (unsigned long long)nn) atomicOr(&ctl->flags, kFlagBadIndex);
-    flush<MULTI, LOGS>(a, pl, ql, np, nq, pi, eps2, sub, S, acc);
+    flush_shape<MULTI, LOGS>(shape, a, pl, ql, np, nq, pi, eps2, sub, S, acc);
 
     float ax = acc.x + acc.cx, ay = acc.y + acc.cy, az = acc.z + acc.cz, ap = acc.p + acc.cp;
-    for (int m = G; m < 64; m <<= 1) {
+    for (int m = Gx; m < 64; m <<= 1) {
       ax += __shfl_xor(ax, m, 64);
       ay += __shfl_xor(ay, m, 64);
       az += __shfl_xor(az, m, 64);

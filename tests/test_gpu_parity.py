@@ -154,6 +154,22 @@ def test_critical_separation(r_crit):
     _check_forces(ics.nfw(20000, seed=23), 1 / 128, 0.5, multipole=2, r_crit=r_crit)
 
 
+@pytest.mark.parametrize("G,multipole", [(64, 1), (32, 2), (8, 2)])
+def test_groups_of_every_size_take_their_lane_shape(G, multipole):
+    """Groups shorter than G (split by r_crit in a sparse active set) are laid
+    out on the fewest power-of-two slots that hold them, with more lanes per
+    i-particle: the kernel's own shape, half of it and the run-time shapes below
+    must all appear and match the float64 evaluation of the same lists."""
+    x = ics.nfw(30000, seed=25)
+    act = ics.random_active(30000, 0.5, seed=26)
+    ctx, _, _ = _check_forces(x, 1 / 128, 0.5, active=act, group_size=G, r_crit=0.4,
+                              multipole=multipole)
+    cnt = ctx.groups()["count"]
+    slots = 2 ** np.ceil(np.log2(np.maximum(cnt, 1))).astype(int)
+    say(f"  G={G}: groups {cnt.size}, by slots {dict(zip(*np.unique(slots, return_counts=True)))}")
+    assert (slots == G).any() and (slots == G // 2).any() and (slots < G // 2).any()
+
+
 @pytest.mark.parametrize("G", [64, 16, 8, 1])
 def test_group_sizes_and_ij_parallel(G):
     _check_forces(ics.plummer(6000, seed=11), 1 / 64, 0.5, group_size=G)

@@ -668,7 +668,8 @@ def main():
     ap.add_argument("--class-groups", default="auto",
                     help="group size per sub-step class of the block steps (S per step), "
                          "comma-separated from class 0 (the last value repeats); 'auto' "
-                         "(default, with --walk-width 64): 1,<--group-size>, i.e. in the sparse "
+                         "(default, with --walk-width 64 and no --autotune 2): 1,<--group-size>, "
+                         "i.e. in the sparse "
                          "class 0 (only the finest level due) every due particle walks the tree "
                          "alone with 64 lanes, the other classes groups of --group-size "
                          "(measured at NFW 2^24, fixed rebuild interval 4: 12.03 against 12.42 "
@@ -770,7 +771,9 @@ def main():
 
     log(f"bench: block steps (warmup {args.warmup}, timed {args.steps})")
     if args.class_groups == "auto":
-        args.class_groups = f"1,{args.group_size}" if args.walk_width == 64 else ""
+        # the online picker (autotune 2) chooses the shapes itself
+        args.class_groups = (f"1,{args.group_size}"
+                             if args.walk_width == 64 and args.autotune != 2 else "")
     class_groups = [int(v) for v in args.class_groups.split(",") if v.strip()]
     blk = run_sim(ctx, pos0, vel0, mass, eps, theta, eta, kmax, False, args.steps, args.warmup,
                   class_groups=class_groups or None)

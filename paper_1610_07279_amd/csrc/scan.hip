@@ -3,7 +3,8 @@
 // Used for the child numbering of the breadth-first tree (Section 2.1 of the
 // paper numbers new cells by prefix sums), for active-particle compaction and
 // for the radix-sort offsets.  Three launches over a fixed grid so the length
-// may live on the device (no host read-back, capturable in a graph):
+// may live on the device (no host read-back, capturable in a graph), or one
+// workgroup when the host's bound on the length is small:
 //   1. each block sums its contiguous chunk,
 //   2. one block scans the chunk sums and writes the total,
 //   3. each block scans its chunk again, offset by its chunk prefix.
@@ -145,9 +146,44 @@ scan_apply_k(const uint32_t *in, uint32_t *out, int64_t n_host, const unsigned *
   }
 }
 
+// At most kSmallScan elements (a bound the host knows): one workgroup scans
+// them in rounds of four per thread, carrying the running total, in one
+// launch instead of three (small systems, upper tree levels, short sort
+// histograms: the three launches' latency is most of their cost).
+constexpr int kSmallThreads = 1024;
+constexpr int64_t kSmallScan = 2 * 4 * kSmallThreads;
+
+__global__ void __launch_bounds__(kSmallThreads)
+scan_small_k(const uint32_t *in, uint32_t *out, int64_t n_host, const unsigned *n_dev,
+             const unsigned *lo_dev, int64_t n_max, unsigned *total_dev) {
+  __shared__ unsigned sh[kSmallThreads / 64 + 1];
+  int64_t n = scan_len(n_host, n_dev, lo_dev);
+  if (n > n_max) n = n_max;
+  unsigned run = 0;
+  for (int64_t base = 0; base < n; base += 4 * kSmallThreads) {  // block-uniform
+    const int64_t i = base + 4 * (int64_t)threadIdx.x;
+    const uint4 v = load4(in, i, n);
+    unsigned tot;
+    const unsigned ex = block_excl_sum<kSmallThreads>(v.x + v.y + v.z + v.w, sh, &tot);
+    uint4 o;
+    o.x = run + ex;
+    o.y = o.x + v.x;
+    o.z = o.y + v.y;
+    o.w = o.z + v.z;
+    store4(out, i, n, o);
+    run += tot;
+  }
+  if (threadIdx.x == 0 && total_dev) *total_dev = run;
+}
+
 void scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n_host, const unsigned *n_dev,
                     const unsigned *lo_dev, int64_t n_max, unsigned *total_dev, uint32_t *part,
                     hipStream_t s) {
+  if (n_max <= kSmallScan) {
+    hipLaunchKernelGGL(scan_small_k, dim3(1), dim3(kSmallThreads), 0, s, in, out, n_host, n_dev,
+                       lo_dev, n_max, total_dev);
+    return;
+  }
   hipLaunchKernelGGL(scan_reduce_k, dim3(kScanBlocks), dim3(kScanThreads), 0, s, in, n_host,
                      n_dev, lo_dev, n_max, part);
   hipLaunchKernelGGL(scan_partials_k, dim3(1), dim3(kScanBlocks), 0, s, part, total_dev);

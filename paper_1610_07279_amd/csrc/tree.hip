@@ -260,7 +260,11 @@ void launch_build(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
                        c->cap_n, B.ctl, B.keyA, B.first, B.count, B.child_first, B.n_child,
                        B.nch, B.bnd);
     if (l == kNlev) break;
-    scan_exclusive(B.nch, B.nch, 0, &B.ctl->lvl_start[l + 1], &B.ctl->lvl_start[l], c->cap_n,
+    // the nodes of level l: at most nsys 8^l (and at most cap_n)
+    int64_t lvl_max = nsys;
+    for (int q = 0; q < l && lvl_max < c->cap_n; ++q) lvl_max *= 8;
+    if (lvl_max > c->cap_n) lvl_max = c->cap_n;
+    scan_exclusive(B.nch, B.nch, 0, &B.ctl->lvl_start[l + 1], &B.ctl->lvl_start[l], lvl_max,
                    &B.ctl->scan_total, B.part, s);
     hipLaunchKernelGGL(build_write_k, dim3(g), dim3(kBuildThreads), 0, s, l, c->prm.n_leaf, n, cap,
                        c->cap_n, B.ctl,

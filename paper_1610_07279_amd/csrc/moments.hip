@@ -522,8 +522,13 @@ void launch_moments(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
     hipLaunchKernelGGL(internal_moments_k, dim3(gl), dim3(256), 0, s, l, B.ctl, B.child_first,
                        B.n_child, B.nrec, B.quad, wq);
   }
-  // about 1024 particles per wave chunk (more waves only for small n)
+  // about 1024 particles per wave chunk; small systems take chunks of down
+  // to one tile of 64 so that at least 256 workgroups share the levels' work
   int64_t pb = (n + 4095) / 4096;
+  if (pb < 256) {
+    const int64_t small = (n + 255) / 256;
+    pb = small < 256 ? small : 256;
+  }
   int gp = (int)(pb > 16384 ? 16384 : (pb < 1 ? 1 : pb));
   hipLaunchKernelGGL(radius_k, dim3(gp), dim3(256), 0, s, B.ctl, n, B.pos, B.anc, B.leaflev,
                      B.nrec);

@@ -85,6 +85,127 @@ __device__ __forceinline__ unsigned digit_at(uint64_t key, int shift) {
   return (unsigned)(key >> shift) & 7u;
 }
 
+// The children of node k of level l (particles [f, f + c) in key order):
+// records the 7 inner boundaries in bnd8[1..7] and returns how many of the 8
+// digit runs are non-empty (0 for a leaf).  KS is a global or an LDS key
+// array.
+template <class KS>
+__device__ __forceinline__ unsigned count_children(int l, int n_leaf, int64_t n, KS ks,
+                                                   uint32_t f, uint32_t c, Ctl *ctl,
+                                                   uint32_t *bnd8) {
+  const int shift = 3 * (kNlev - 1 - l);
+  unsigned nc = 0;
+  if ((int64_t)f + c > n) {
+    atomicOr(&ctl->flags, kFlagBadIndex);
+  } else if (c > (uint32_t)n_leaf && l < kNlev) {
+    // the first index with digit >= d, for d = 1..7: each lies in [a[d], b[d]]
+    // (indices below a[d] have a smaller digit, those from b[d] on one at
+    // least d).  Runs of more than 2^16 (the few nodes of the top levels,
+    // where the search latency is not hidden by other nodes) are narrowed
+    // by eight probes per digit and round (every load of a round in
+    // flight at once); then bisection, all digits in lock step.
+    uint32_t a[8], b[8];
+#pragma unroll
+    for (int d = 1; d < 8; ++d) { a[d] = f; b[d] = f + c; }
+    for (uint32_t len = c; len > 64 && c > 65536u; len = (len + 8) / 9) {
+#pragma unroll
+      for (int d = 1; d < 8; ++d) {
+        const uint32_t span = b[d] - a[d];
+        if (span <= 8) continue;
+        uint32_t q[8];
+        bool g[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          q[j] = a[d] + (uint32_t)(((uint64_t)span * (uint64_t)(j + 1)) / 9u);
+          g[j] = digit_at(ks[q[j]], shift) >= (unsigned)d;
+        }
+        uint32_t na = a[d], nb = b[d];
+#pragma unroll
+        for (int j = 7; j >= 0; --j)
+          if (g[j]) nb = q[j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (!g[j]) na = q[j] + 1;
+        a[d] = na;
+        b[d] = nb;
+      }
+    }
+    for (uint32_t len = c > 65536u ? 64u : c; len > 0; len >>= 1) {
+#pragma unroll
+      for (int d = 1; d < 8; ++d) {
+        if (a[d] < b[d]) {
+          const uint32_t mid = a[d] + ((b[d] - a[d]) >> 1);
+          if (digit_at(ks[mid], shift) >= (unsigned)d) b[d] = mid; else a[d] = mid + 1;
+        }
+      }
+    }
+    // one more pass guarantees convergence for any length
+#pragma unroll
+    for (int d = 1; d < 8; ++d) {
+      while (a[d] < b[d]) {
+        const uint32_t mid = a[d] + ((b[d] - a[d]) >> 1);
+        if (digit_at(ks[mid], shift) >= (unsigned)d) b[d] = mid; else a[d] = mid + 1;
+      }
+    }
+    uint32_t prev = f;
+#pragma unroll
+    for (int d = 1; d < 8; ++d) {
+      bnd8[d] = a[d];
+      nc += (a[d] > prev) ? 1u : 0u;
+      prev = a[d];
+    }
+    nc += (f + c > prev) ? 1u : 0u;
+  }
+  return nc;
+}
+
+// The children of node k of level l, numbered from base (the next level's
+// start plus the node's exclusive prefix of child counts): written from the
+// boundaries the count pass stored.
+__device__ __forceinline__ void write_children(int l, int n_leaf, int64_t n, int64_t cap_nodes,
+                                               int64_t k, uint32_t f, uint32_t c, int64_t base,
+                                               const uint32_t *bnd8, uint32_t *child_first,
+                                               uint8_t *n_child, uint32_t *cfirst,
+                                               uint32_t *ccount, uint32_t *cparent,
+                                               uint8_t *clevel) {
+  // only nodes the count pass split have boundaries stored
+  if (c <= (uint32_t)n_leaf || (int64_t)f + c > n) return;
+  // recover the non-empty children from the stored boundaries
+  int made = 0;
+  {
+    uint32_t s = f;
+#pragma unroll
+    for (int d = 1; d <= 8; ++d) {
+      const uint32_t e = (d < 8) ? bnd8[d] : f + c;
+      if (e > s) { ++made; s = e; }
+    }
+  }
+  if (made == 0) return;
+  if (base + made > cap_nodes) {
+    // out of node capacity: keep the tree consistent by leaving this node a
+    // leaf (flagged; the host grows the arrays and repeats the evaluation)
+    child_first[k] = 0;
+    n_child[k] = 0;
+    return;
+  }
+  uint32_t s = f;
+  int j = 0;
+#pragma unroll
+  for (int d = 1; d <= 8; ++d) {
+    const uint32_t e = (d < 8) ? bnd8[d] : f + c;
+    if (e > s) {
+      cfirst[base + j] = s;
+      ccount[base + j] = e - s;
+      cparent[base + j] = (uint32_t)k;
+      clevel[base + j] = (uint8_t)(l + 1);
+      ++j;
+      s = e;
+    }
+  }
+  child_first[k] = (uint32_t)base;
+  n_child[k] = (uint8_t)made;
+}
+
 // Count children of every level-l node; record the 7 inner boundaries.
 __global__ void __launch_bounds__(kBuildThreads)
 build_count_k(int l, int n_leaf, int64_t n, int64_t cap_nodes, int64_t cap_level, Ctl *ctl,
@@ -97,72 +218,10 @@ build_count_k(int l, int n_leaf, int64_t n, int64_t cap_nodes, int64_t cap_level
   int64_t hi = ctl->lvl_start[l + 1];
   if (hi > cap_nodes) hi = cap_nodes;
   if (hi - lo > cap_level) hi = lo + cap_level;
-  const int shift = 3 * (kNlev - 1 - l);
   for (int64_t k = lo + (int64_t)blockIdx.x * kBuildThreads + threadIdx.x; k < hi;
        k += (int64_t)gridDim.x * kBuildThreads) {
-    const uint32_t f = first[k], c = count[k];
-    unsigned nc = 0;
-    if ((int64_t)f + c > n) {
-      atomicOr(&ctl->flags, kFlagBadIndex);
-    } else if (c > (uint32_t)n_leaf && l < kNlev) {
-      // the first index with digit >= d, for d = 1..7: each lies in [a[d], b[d]]
-      // (indices below a[d] have a smaller digit, those from b[d] on one at
-      // least d).  Runs of more than 2^16 (the few nodes of the top levels,
-      // where the search latency is not hidden by other nodes) are narrowed
-      // by eight probes per digit and round (every load of a round in
-      // flight at once); then bisection, all digits in lock step.
-      uint32_t a[8], b[8];
-#pragma unroll
-      for (int d = 1; d < 8; ++d) { a[d] = f; b[d] = f + c; }
-      for (uint32_t len = c; len > 64 && c > 65536u; len = (len + 8) / 9) {
-#pragma unroll
-        for (int d = 1; d < 8; ++d) {
-          const uint32_t span = b[d] - a[d];
-          if (span <= 8) continue;
-          uint32_t q[8];
-          bool g[8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            q[j] = a[d] + (uint32_t)(((uint64_t)span * (uint64_t)(j + 1)) / 9u);
-            g[j] = digit_at(ks[q[j]], shift) >= (unsigned)d;
-          }
-          uint32_t na = a[d], nb = b[d];
-#pragma unroll
-          for (int j = 7; j >= 0; --j)
-            if (g[j]) nb = q[j];
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            if (!g[j]) na = q[j] + 1;
-          a[d] = na;
-          b[d] = nb;
-        }
-      }
-      for (uint32_t len = c > 65536u ? 64u : c; len > 0; len >>= 1) {
-#pragma unroll
-        for (int d = 1; d < 8; ++d) {
-          if (a[d] < b[d]) {
-            const uint32_t mid = a[d] + ((b[d] - a[d]) >> 1);
-            if (digit_at(ks[mid], shift) >= (unsigned)d) b[d] = mid; else a[d] = mid + 1;
-          }
-        }
-      }
-      // one more pass guarantees convergence for any length
-#pragma unroll
-      for (int d = 1; d < 8; ++d) {
-        while (a[d] < b[d]) {
-          const uint32_t mid = a[d] + ((b[d] - a[d]) >> 1);
-          if (digit_at(ks[mid], shift) >= (unsigned)d) b[d] = mid; else a[d] = mid + 1;
-        }
-      }
-      uint32_t prev = f;
-#pragma unroll
-      for (int d = 1; d < 8; ++d) {
-        bnd[(k - lo) * 8 + d] = a[d];
-        nc += (a[d] > prev) ? 1u : 0u;
-        prev = a[d];
-      }
-      nc += (f + c > prev) ? 1u : 0u;
-    }
+    const unsigned nc = count_children(l, n_leaf, n, ks, first[k], count[k], ctl,
+                                       bnd + (k - lo) * 8);
     nch[k - lo] = nc;
     if (nc == 0) {
       child_first[k] = 0;
@@ -192,45 +251,71 @@ build_write_k(int l, int n_leaf, int64_t n, int64_t cap_nodes, int64_t cap_level
   if (hi > cap_nodes) hi = cap_nodes;
   if (hi - lo > cap_level) hi = lo + cap_level;
   for (int64_t k = lo + (int64_t)blockIdx.x * kBuildThreads + threadIdx.x; k < hi;
-       k += (int64_t)gridDim.x * kBuildThreads) {
-    const uint32_t f = first[k], c = count[k];
-    // only nodes the count pass split have boundaries stored
-    if (c <= (uint32_t)n_leaf || (int64_t)f + c > n) continue;
-    // recover the non-empty children from the stored boundaries
-    const int64_t base = nxt + ofs[k - lo];
-    int made = 0;
-    {
-      uint32_t s = f;
-#pragma unroll
-      for (int d = 1; d <= 8; ++d) {
-        const uint32_t e = (d < 8) ? bnd[(k - lo) * 8 + d] : f + c;
-        if (e > s) { ++made; s = e; }
+       k += (int64_t)gridDim.x * kBuildThreads)
+    write_children(l, n_leaf, n, cap_nodes, k, first[k], count[k], nxt + ofs[k - lo],
+                   bnd + (k - lo) * 8, child_first, n_child, cfirst, ccount, cparent, clevel);
+}
+
+// Small systems (n <= kSmallBuild particles, a bound the host knows): the
+// whole level loop (count, prefix sum of the child counts, write) in one
+// workgroup, with the sorted keys in LDS and a barrier between the phases,
+// instead of three to five launches per level.  Same arithmetic and outputs
+// as build_count_k / scan / build_write_k.
+constexpr int kSmallBuild = 8192;
+constexpr int kSmallBuildThreads = 1024;
+
+__global__ void __launch_bounds__(kSmallBuildThreads)
+build_small_k(int n_leaf, int64_t n, int64_t cap_nodes, int64_t cap_level, Ctl *ctl,
+              const uint64_t *__restrict__ ks_g, uint32_t *first, uint32_t *count,
+              uint32_t *child_first, uint8_t *n_child, uint32_t *parent, uint8_t *level,
+              uint32_t *nch, uint32_t *bnd) {
+  __shared__ uint64_t ks[kSmallBuild];
+  __shared__ unsigned sh[kSmallBuildThreads / 64 + 1];
+  const int t = threadIdx.x;
+  for (int64_t i = t; i < n; i += kSmallBuildThreads) ks[i] = ks_g[i];
+  __syncthreads();
+  for (int l = 0; l <= kNlev; ++l) {
+    if (ctl->flags & kFlagNodeOverflow) break;  // block-uniform (read after a barrier)
+    const int64_t lo = ctl->lvl_start[l];
+    int64_t hi = ctl->lvl_start[l + 1];
+    if (hi > cap_nodes) hi = cap_nodes;
+    if (hi - lo > cap_level) hi = lo + cap_level;
+    for (int64_t k = lo + t; k < hi; k += kSmallBuildThreads) {
+      const unsigned nc = count_children(l, n_leaf, n, ks, first[k], count[k], ctl,
+                                         bnd + (k - lo) * 8);
+      nch[k - lo] = nc;
+      if (nc == 0) {
+        child_first[k] = 0;
+        n_child[k] = 0;
       }
     }
-    if (made == 0) continue;
-    if (base + made > cap_nodes) {
-      // out of node capacity: keep the tree consistent by leaving this node a
-      // leaf (flagged; the host grows the arrays and repeats the evaluation)
-      child_first[k] = 0;
-      n_child[k] = 0;
-      continue;
+    __syncthreads();
+    if (l == kNlev) break;
+    // exclusive prefix sum of the child counts over the level (in place),
+    // in rounds of one count per thread
+    const int64_t m = hi > lo ? hi - lo : 0;
+    unsigned run = 0;
+    for (int64_t b0 = 0; b0 < m; b0 += kSmallBuildThreads) {  // block-uniform
+      const int64_t i = b0 + t;
+      const unsigned v = i < m ? nch[i] : 0u;
+      unsigned tot;
+      const unsigned ex = block_excl_sum<kSmallBuildThreads>(v, sh, &tot);
+      if (i < m) nch[i] = run + ex;
+      run += tot;
     }
-    uint32_t s = f;
-    int j = 0;
-#pragma unroll
-    for (int d = 1; d <= 8; ++d) {
-      const uint32_t e = (d < 8) ? bnd[(k - lo) * 8 + d] : f + c;
-      if (e > s) {
-        cfirst[base + j] = s;
-        ccount[base + j] = e - s;
-        cparent[base + j] = (uint32_t)k;
-        clevel[base + j] = (uint8_t)(l + 1);
-        ++j;
-        s = e;
-      }
+    const int64_t nxt = ctl->lvl_start[l + 1];
+    __syncthreads();
+    if (t == 0) {
+      const int64_t end = nxt + run;
+      ctl->lvl_start[l + 2] = (unsigned)(end > 0xffffffffll ? 0xffffffffll : end);
+      if (end > cap_nodes) atomicOr(&ctl->flags, kFlagNodeOverflow);
     }
-    child_first[k] = (uint32_t)base;
-    n_child[k] = (uint8_t)made;
+    // (with the level past the node capacity the write still runs, as
+    // build_write_k does: nodes whose children do not fit stay leaves)
+    for (int64_t k = lo + t; k < hi; k += kSmallBuildThreads)
+      write_children(l, n_leaf, n, cap_nodes, k, first[k], count[k], nxt + nch[k - lo],
+                     bnd + (k - lo) * 8, child_first, n_child, first, count, parent, level);
+    __syncthreads();
   }
 }
 
@@ -249,6 +334,13 @@ void launch_build(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
   hipLaunchKernelGGL(build_init_k, dim3(ib > 1024 ? 1024 : ib), dim3(256), 0, s, B.ctl, nsys,
                      B.soff, B.first, B.count, B.parent, B.level);
   const int64_t cap = c->cap_nodes;
+  if (n <= kSmallBuild) {
+    hipLaunchKernelGGL(build_small_k, dim3(1), dim3(kSmallBuildThreads), 0, s, c->prm.n_leaf, n,
+                       cap, c->cap_n, B.ctl, B.keyA, B.first, B.count, B.child_first, B.n_child,
+                       B.parent, B.level, B.nch, B.bnd);
+    hipLaunchKernelGGL(build_final_k, dim3(1), dim3(64), 0, s, B.ctl, cap);
+    return;
+  }
   // grid large enough for the widest level (at most min(cap, nsys 8^l) nodes)
   for (int l = 0; l <= kNlev; ++l) {
     int64_t widest = nsys;

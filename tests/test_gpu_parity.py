@@ -46,6 +46,9 @@ def _uniform(n, seed):
 
 
 SYSTEMS = {
+    # systems of at most 8192 particles take the one-workgroup octree build,
+    # larger ones the level-by-level launches: both are held to the oracle
+    "nfw20k": lambda: ics.nfw(20000, seed=8),
     "plummer8k": lambda: ics.plummer(8192, seed=101),
     "nfw4097": lambda: ics.nfw(4097, seed=7),
     "uniform777": lambda: _uniform(777, 5),

@@ -158,19 +158,16 @@ __device__ __forceinline__ float seg_sum8(float v) {
 // reading child q (all children's records in flight at once), sums reduced
 // across the 8 lanes; second moments about the new centre by the
 // parallel-axis rule.
-__global__ void __launch_bounds__(256)
-internal_moments_k(int l, Ctl *__restrict__ ctl, const uint32_t *__restrict__ child_first,
-                   const uint8_t *__restrict__ n_child, float4 *__restrict__ nrec,
-                   float4 *__restrict__ quad, int want_quad) {
-  if (ctl->flags & kFlagNodeOverflow) return;
+__device__ __forceinline__ void internal_level(int l, Ctl *ctl, const uint32_t *child_first,
+                                               const uint8_t *n_child, float4 *nrec,
+                                               float4 *quad, int want_quad, int64_t wave,
+                                               int64_t nwaves) {
   const int64_t hi_all = ctl->n_nodes;
   const int64_t lo = ctl->lvl_start[l];
   int64_t hi = ctl->lvl_start[l + 1];
   if (hi > hi_all) hi = hi_all;
   const int lane = lane_id();
   const unsigned q = (unsigned)(lane & 7);
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t k0 = lo + wave * 8; k0 < hi; k0 += nwaves * 8) {  // wave-uniform
     const int64_t k = k0 + (lane >> 3);
     const unsigned nc = k < hi ? n_child[k] : 0u;
@@ -215,6 +212,34 @@ internal_moments_k(int l, Ctl *__restrict__ ctl, const uint32_t *__restrict__ ch
       quad[2 * k] = make_float4(xx, yy, zz, xy);
       quad[2 * k + 1] = make_float4(xz, yz, xx + yy + zz, 0.f);
     }
+  }
+}
+
+
+__global__ void __launch_bounds__(256)
+internal_moments_k(int l, Ctl *__restrict__ ctl, const uint32_t *__restrict__ child_first,
+                   const uint8_t *__restrict__ n_child, float4 *__restrict__ nrec,
+                   float4 *__restrict__ quad, int want_quad) {
+  if (ctl->flags & kFlagNodeOverflow) return;
+  internal_level(l, ctl, child_first, n_child, nrec, quad, want_quad,
+                 ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6,
+                 ((int64_t)gridDim.x * blockDim.x) >> 6);
+}
+
+// Small trees (systems of at most kSmallMoments particles, a bound the host
+// knows): every level in one workgroup, deepest first, a barrier between
+// levels, instead of one launch per level.
+constexpr int kSmallMoments = 8192;
+
+__global__ void __launch_bounds__(1024)
+internal_moments_small_k(Ctl *__restrict__ ctl, const uint32_t *__restrict__ child_first,
+                         const uint8_t *__restrict__ n_child, float4 *nrec, float4 *quad,
+                         int want_quad) {
+  if (ctl->flags & kFlagNodeOverflow) return;
+  for (int l = kNlev - 1; l >= 0; --l) {
+    internal_level(l, ctl, child_first, n_child, nrec, quad, want_quad, threadIdx.x >> 6,
+                   blockDim.x >> 6);
+    __syncthreads();
   }
 }
 
@@ -513,14 +538,19 @@ void launch_moments(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
     hipLaunchKernelGGL(leaf_moments_k<16>, dim3(g), dim3(256), 0, s, B.ctl, n, B.first, B.count,
                        B.n_child, B.pos, B.nrec, B.quad, wq);
   }
-  for (int l = kNlev - 1; l >= 0; --l) {
-    int64_t widest = nsys;
-    for (int q = 0; q < l && widest < c->cap_nodes; ++q) widest *= 8;
-    if (widest > c->cap_nodes) widest = c->cap_nodes;
-    int64_t lb = (widest + 31) / 32;  // 32 nodes per workgroup pass
-    int gl = (int)(lb > 4096 ? 4096 : (lb < 1 ? 1 : lb));
-    hipLaunchKernelGGL(internal_moments_k, dim3(gl), dim3(256), 0, s, l, B.ctl, B.child_first,
+  if (n <= kSmallMoments) {
+    hipLaunchKernelGGL(internal_moments_small_k, dim3(1), dim3(1024), 0, s, B.ctl, B.child_first,
                        B.n_child, B.nrec, B.quad, wq);
+  } else {
+    for (int l = kNlev - 1; l >= 0; --l) {
+      int64_t widest = nsys;
+      for (int q = 0; q < l && widest < c->cap_nodes; ++q) widest *= 8;
+      if (widest > c->cap_nodes) widest = c->cap_nodes;
+      int64_t lb = (widest + 31) / 32;  // 32 nodes per workgroup pass
+      int gl = (int)(lb > 4096 ? 4096 : (lb < 1 ? 1 : lb));
+      hipLaunchKernelGGL(internal_moments_k, dim3(gl), dim3(256), 0, s, l, B.ctl,
+                         B.child_first, B.n_child, B.nrec, B.quad, wq);
+    }
   }
   // about 1024 particles per wave chunk; small systems take chunks of down
   // to one tile of 64 so that at least 256 workgroups share the levels' work

@@ -21,7 +21,15 @@ namespace gothic {
 
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
-constexpr int kSortTile = kSortThreads * kSortItems;
+// up to kSmallSortN elements the tiles hold 2 items per thread: four times
+// the workgroups, each with a quarter of the rounds (small systems are bound
+// by the latency of each pass, not by its bytes)
+constexpr int kSmallSortItems = 2;
+constexpr int64_t kSmallSortN = 65536;
+
+static int sort_tile(int64_t n) {
+  return kSortThreads * (n <= kSmallSortN ? kSmallSortItems : kSortItems);
+}
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kPasses = 8;
@@ -42,11 +50,18 @@ __device__ __forceinline__ unsigned digit_of(uint64_t key, uint32_t id, int shif
   return (sys_of(soff, nsys, id) >> sys_shift) & (kRadix - 1);
 }
 
+// table entries for any length up to n: the small tiles' count for lengths up
+// to kSmallSortN, the large tiles' beyond
 int64_t radix_hist_entries(int64_t n) {
-  int64_t tiles = (n + kSortTile - 1) / kSortTile;
+  const int64_t small_n = n < kSmallSortN ? n : kSmallSortN;
+  const int small_tile = kSortThreads * kSmallSortItems, tile = kSortThreads * kSortItems;
+  int64_t tiles = (small_n + small_tile - 1) / small_tile;
+  const int64_t large = (n + tile - 1) / tile;
+  if (large > tiles) tiles = large;
   return (tiles < 1 ? 1 : tiles) * kRadix;
 }
 
+template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads)
 radix_hist_k(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ ids, int64_t n,
              int shift, int sys_shift, const uint32_t *__restrict__ soff, unsigned nsys,
@@ -54,9 +69,9 @@ radix_hist_k(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ ids
   __shared__ unsigned cnt[kRadix];
   for (int t = threadIdx.x; t < kRadix; t += kSortThreads) cnt[t] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = (int64_t)blockIdx.x * kSortThreads * ITEMS;
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const int64_t e = base + r * kSortThreads + threadIdx.x;
     if (e < n) {
       const unsigned d = sys_shift < 0 ? (unsigned)(keys[e] >> shift) & (kRadix - 1)
@@ -69,20 +84,22 @@ radix_hist_k(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ ids
     hist[(int64_t)t * ntiles + blockIdx.x] = cnt[t];
 }
 
+template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads)
 radix_scatter_k(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ iin,
                 uint64_t *__restrict__ kout, uint32_t *__restrict__ iout, int64_t n, int shift,
                 int sys_shift, const uint32_t *__restrict__ soff, unsigned nsys, int64_t ntiles,
                 const uint32_t *__restrict__ hist, const uint32_t *__restrict__ ofs) {
   constexpr int NW = kSortThreads / 64;
+  constexpr int TILE = kSortThreads * ITEMS;
   static_assert(kSortThreads == kRadix, "one digit per thread in the local scan");
   __shared__ unsigned gofs[kRadix];    // global start of (digit, this tile)
   __shared__ unsigned lstart[kRadix];  // start of the digit inside the tile
   __shared__ unsigned run[kRadix];
   __shared__ unsigned wcnt[NW][kRadix];
   __shared__ unsigned scan_sh[NW + 1];
-  __shared__ uint64_t sk[kSortTile];   // the tile in digit order
-  __shared__ uint32_t si[kSortTile];
+  __shared__ uint64_t sk[TILE];   // the tile in digit order
+  __shared__ uint32_t si[TILE];
   const int t0 = threadIdx.x;
   gofs[t0] = ofs[(int64_t)t0 * ntiles + blockIdx.x];
   run[t0] = 0;
@@ -90,10 +107,10 @@ radix_scatter_k(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ i
   lstart[t0] = block_excl_sum<kSortThreads>(hist[(int64_t)t0 * ntiles + blockIdx.x], scan_sh,
                                             &total);
   const int w = threadIdx.x >> 6;
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = (int64_t)blockIdx.x * TILE;
   // rank stably inside the tile (item round, then wave, then lane) and
   // place each element at its digit's run in LDS
-  for (int r = 0; r < kSortItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     for (int t = threadIdx.x; t < NW * kRadix; t += kSortThreads) (&wcnt[0][0])[t] = 0;
     __syncthreads();
     const int64_t e = base + r * kSortThreads + threadIdx.x;
@@ -115,7 +132,7 @@ radix_scatter_k(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ i
     if (valid) {
       unsigned pos = lstart[d] + run[d] + below;
       for (int v = 0; v < w; ++v) pos += wcnt[v][d];
-      if (pos < (unsigned)kSortTile) {
+      if (pos < (unsigned)TILE) {
         sk[pos] = key;
         si[pos] = id;
       }
@@ -130,7 +147,7 @@ radix_scatter_k(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ i
   }
   // write the tile out in digit order: neighbouring threads write
   // neighbouring addresses inside each digit's bucket
-  const int64_t m_tile = n - base < kSortTile ? n - base : kSortTile;
+  const int64_t m_tile = n - base < TILE ? n - base : TILE;
   for (int j = threadIdx.x; j < m_tile; j += kSortThreads) {
     const uint64_t key = sk[j];
     const uint32_t id = si[j];
@@ -154,18 +171,22 @@ void launch_radix_sort(gothic_ctx *c, int64_t n, int nsys, hipStream_t s) {
     ia = c->b.idxB; ib = c->b.idxA;
   }
   if (n <= 1) return;  // then nsys <= 1 (systems are never empty): an even count, in A
-  const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+  const bool small = n <= kSmallSortN;
+  const int tile = sort_tile(n);
+  const int64_t ntiles = (n + tile - 1) / tile;
   uint32_t *hist = c->b.hist;
   uint32_t *ofs = c->b.hist + ntiles * kRadix;
   for (int p = 0; p < passes; ++p) {
     const int shift = p < kPasses ? p * kRadixBits : 0;
     const int sys_shift = p < kPasses ? -1 : (p - kPasses) * kRadixBits;
-    hipLaunchKernelGGL(radix_hist_k, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, ka, ia, n,
-                       shift, sys_shift, c->b.soff, (unsigned)nsys, ntiles, hist);
+    hipLaunchKernelGGL(small ? radix_hist_k<kSmallSortItems> : radix_hist_k<kSortItems>,
+                       dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, ka, ia, n, shift,
+                       sys_shift, c->b.soff, (unsigned)nsys, ntiles, hist);
     scan_exclusive(hist, ofs, ntiles * kRadix, nullptr, nullptr, ntiles * kRadix,
                    &c->b.ctl->scan_total, c->b.part, s);
-    hipLaunchKernelGGL(radix_scatter_k, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, ka, ia,
-                       kb, ib, n, shift, sys_shift, c->b.soff, (unsigned)nsys, ntiles, hist, ofs);
+    hipLaunchKernelGGL(small ? radix_scatter_k<kSmallSortItems> : radix_scatter_k<kSortItems>,
+                       dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, ka, ia, kb, ib, n, shift,
+                       sys_shift, c->b.soff, (unsigned)nsys, ntiles, hist, ofs);
     uint64_t *tk = ka; ka = kb; kb = tk;
     uint32_t *ti = ia; ia = ib; ib = ti;
   }

@@ -278,6 +278,13 @@ build_small_k(int n_leaf, int64_t n, int64_t cap_nodes, int64_t cap_level, Ctl *
     if (ctl->flags & kFlagNodeOverflow) break;  // block-uniform (read after a barrier)
     const int64_t lo = ctl->lvl_start[l];
     int64_t hi = ctl->lvl_start[l + 1];
+    if (lo >= hi) {
+      // an empty level: so are all deeper ones, which end where it does
+      // (what the remaining count / scan / write passes would record)
+      if (t == 0)
+        for (int j = l + 2; j <= kNlev + 1; ++j) ctl->lvl_start[j] = (unsigned)hi;
+      break;
+    }
     if (hi > cap_nodes) hi = cap_nodes;
     if (hi - lo > cap_level) hi = lo + cap_level;
     for (int64_t k = lo + t; k < hi; k += kSmallBuildThreads) {

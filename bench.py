@@ -490,12 +490,24 @@ def config_c1(args):
     if not np.array_equal(out.cpu().numpy(), a):
         raise RuntimeError("the captured evaluation differs from the eager one")
     ref = g.Context(device=0).direct_forces(xd, eps).cpu().numpy()
+    # the same evaluation with the tunables gothic_autotune picks for it
+    tctx = g.Context(device=0, timing=1)
+    res = tctx.autotune(xd, eps, theta)
+    tout = tctx.tree_forces(xd, eps, theta)
+    tst = tctx.stats()
+    tctx.set_params(check=0)
+    twall, twalk = _time_forces(tctx, xd, eps, theta, tout, reps=200)
     row = {"config": "C1", "workload": "Plummer N=8192 (seed 101), eps 1/64, theta 0.5, "
                                         "monopole, all active",
            "us_per_evaluation": wall * 1e3, "us_per_evaluation_graph_replay": replay_us,
            "walk_us": walk * 1e3,
            "interactions": st["interactions"], "groups": st["n_groups"],
-           "vs_float64_direct": _rel_stats(a, ref)}
+           "vs_float64_direct": _rel_stats(a, ref),
+           "tuned": {"autotune": {k: res[k] for k in ("group_size", "walk_width", "list_depth",
+                                                      "r_crit", "evaluations")},
+                     "us_per_evaluation": twall * 1e3, "walk_us": twalk * 1e3,
+                     "interactions": tst["interactions"], "groups": tst["n_groups"],
+                     "vs_float64_direct": _rel_stats(tout.cpu().numpy(), ref)}}
     if not args.no_cpu:
         import oracle
         t0 = time.perf_counter()

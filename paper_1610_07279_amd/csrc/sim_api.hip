@@ -286,6 +286,10 @@ int gothic_sim_step(gothic_ctx *c, void *stream) {
       if ((rc = capture_step(c))) return rc;
     const int lg = log2_of(gsize), lw = log2_of(wsize) - 4;
     if (!c->graphs.exec_g[lw][lg][0] && (rc = capture_groups(c, lw, lg))) return rc;
+    // the shape of this evaluation for read-backs that walk again
+    // (gothic_get_lists): a replay does not pass through capture_groups
+    c->cur_G = 1 << lg;
+    c->cur_W = 16 << lw;
     const Systems sy = sim_systems(S);
     const bool meter = metering(c);
     if (meter && ((rc = meter_prepare(c)) || (rc = meter_collect(c, S.kmax)))) return rc;

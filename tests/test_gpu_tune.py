@@ -131,6 +131,19 @@ def _bound(x, v, eps, **kw):
     return ctx, pos, vel, mass
 
 
+def _rewalk_reproduces(ctx, k=8):
+    """The forces the list read-back's walk writes for k groups of the last
+    evaluation are that evaluation's, bit for bit."""
+    gg = ctx.groups()
+    _, perm, _ = ctx.keys()
+    acc, _, _ = ctx.sim_state()
+    pick = np.unique(np.linspace(0, gg["first"].size - 1, k).astype(np.int64))
+    _, rewalk = ctx.lists(pick)
+    for q in pick:
+        rows = perm[gg["alist"][gg["first"][q]:gg["first"][q] + gg["count"][q]]]
+        assert rows.size and np.array_equal(rewalk[rows], acc[rows]), q
+
+
 def test_group_size_per_class_replays_equal_launches():
     """A group shape per sub-step class (G i-particles walked by W lanes, S =
     W / G lanes per i-particle): captured sub-steps with one groups + walk
@@ -158,6 +171,14 @@ def test_group_size_per_class_replays_equal_launches():
         assert torch.equal(p0, p1) and torch.equal(v0, v1), step
         assert c0.stats()["n_groups"] == c1.stats()["n_groups"], step
     assert runs[1][0].stats()["sticky_flags"] == 0
+    # a read-back that walks the groups again (gothic_get_lists) takes the
+    # shape of the last evaluation, also when that was a replay: class 1 (G 64)
+    # after the last capture (class 3, G 8)
+    for _ in range(2):
+        for ctx, _, _ in runs:
+            ctx.sim_step()
+    for ctx, _, _ in runs:
+        _rewalk_reproduces(ctx)
     # the last sub-step of a cycle (every particle due) walks groups of the
     # size its class is given
     n_groups = []

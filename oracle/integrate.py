@@ -82,6 +82,28 @@ class BlockSim:
         self.si = np.zeros(n, np.int64)  # sub-step of each particle's last update
         self.s = 0
 
+    @classmethod
+    def from_state(cls, pos, vel, acc3, mass, levels, last, s, dt_fine, eps, eta, kmax,
+                   shared=False):
+        """The state at the end of sub-step s, given rather than integrated:
+        float64 positions and velocities at each particle's last update, the
+        accelerations of that update, float32 masses, levels and last-update
+        sub-steps, with the finest step dt_fine.  It predicts and selects
+        (predict, due) like an integrated one; step() needs a force."""
+        self = cls.__new__(cls)
+        self.x = np.array(pos, np.float64)
+        self.v = np.array(vel, np.float64)
+        self.a = np.array(np.asarray(acc3)[:, :3], np.float64)
+        self.m = np.array(mass, np.float32)
+        self.phi = None
+        self.eps, self.eta, self.kmax, self.force, self.shared = eps, eta, kmax, None, shared
+        self.dt_fine = float(dt_fine)
+        self.dt_max = float(np.ldexp(self.dt_fine, kmax))
+        self.k = np.array(levels, np.int64)
+        self.si = np.array(last, np.int64)
+        self.s = int(s)
+        return self
+
     def _shadow(self, pos):
         out = np.empty((pos.shape[0], 4), np.float32)
         out[:, :3] = pos

@@ -32,6 +32,16 @@ __device__ __forceinline__ int level_for(double dt, double dt_max, int kmax) {
   return k;
 }
 
+// One coordinate of the predictor, r + tau v + h a with h = tau^2 / 2, rounded
+// operation by operation in the written order (no fused multiply-adds), so the
+// float32 shadow is the rounding of the value the formula gives in plain
+// float64 arithmetic.
+__device__ __forceinline__ double predict_coord(double r, double v, double a, double tau,
+                                                double h) {
+#pragma clang fp contract(off)
+  return r + tau * v + h * a;
+}
+
 __device__ __forceinline__ double step_of(float4 a, double eps, double eta) {
   const double ax = a.x, ay = a.y, az = a.z;
   const double am = sqrt(ax * ax + ay * ay + az * az);
@@ -137,9 +147,9 @@ sim_predict_k(int64_t n, unsigned nsys, const uint32_t *__restrict__ soff,
       const double tau = (double)el * dtf;
       const float4 a = aold[i];
       const double h = 0.5 * tau * tau;
-      const double x = pos[3 * i] + tau * vel[3 * i] + h * (double)a.x;
-      const double y = pos[3 * i + 1] + tau * vel[3 * i + 1] + h * (double)a.y;
-      const double z = pos[3 * i + 2] + tau * vel[3 * i + 2] + h * (double)a.z;
+      const double x = predict_coord(pos[3 * i], vel[3 * i], (double)a.x, tau, h);
+      const double y = predict_coord(pos[3 * i + 1], vel[3 * i + 1], (double)a.y, tau, h);
+      const double z = predict_coord(pos[3 * i + 2], vel[3 * i + 2], (double)a.z, tau, h);
       const bool due = el == ((int64_t)1 << (kmax - lev[i]));
       // the sign of the (non-negative) mass carries the due flag to the
       // key-order gather, which then reads one array instead of two
@@ -221,9 +231,9 @@ sim_correct_predict_k(int64_t n, unsigned nsys, const uint32_t *__restrict__ sof
       const int64_t el = s + 1 - last;
       const double tau = (double)el * r.dt_fine;
       const double h = 0.5 * tau * tau;
-      const double px = x + tau * vx + h * (double)a.x;
-      const double py = y + tau * vy + h * (double)a.y;
-      const double pz = z + tau * vz + h * (double)a.z;
+      const double px = predict_coord(x, vx, (double)a.x, tau, h);
+      const double py = predict_coord(y, vy, (double)a.y, tau, h);
+      const double pz = predict_coord(z, vz, (double)a.z, tau, h);
       const bool due = el == ((int64_t)1 << (kmax - k));
       const float m = mass[i];
       shadow[i] = make_float4((float)px, (float)py, (float)pz, due ? -m : m);

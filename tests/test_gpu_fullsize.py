@@ -4,6 +4,11 @@
   benchmark times (G = 32, r_crit = 0.25, list depth 384, EBS balls): bit-exact
   keys, permutation, octree and groups; forces of 48 sampled groups against
   the float64 tree.
+* The benchmark's block sub-steps on that system (kmax 8, eta 0.1, captured
+  sub-steps, groups of one in sub-step class 0, trees rebuilt when the growth
+  models say so): sub-steps of both group sizes on a reused tree and the first
+  sub-step on a rebuilt one, each against the oracle's own prediction, tree,
+  groups and forces of sampled groups.
 * Galaxy-like model 2^22 (NFW halo + Hernquist bulge + exponential disk),
   eps 1/256, theta 0.5, monopole: plain FP32 and compensated accumulation
   against the float64 tree and the float64 direct sum on 4096 random
@@ -41,18 +46,25 @@ def _oracle_prep(x, n_leaf, G, r_crit, key_kind=0):
     return ks, perm, tree, ps, mom, rc
 
 
+@functools.lru_cache(maxsize=1)
+def _nfw16m():
+    """The benchmark's system (NFW 2^24, seed 501) with velocities, and the
+    oracle's keys, permutation, tree and moments of its float32 positions."""
+    x, v = ics.nfw(1 << 24, seed=501, with_vel=True)
+    say("  oracle tree at 2^24")
+    return (x, v) + _oracle_prep(x, 16, 32, 0.25)
+
+
 def test_nfw16m_bench_configuration():
     n, eps, theta = 1 << 24, 1 / 512, 0.5
     say("[gpu] NFW 2^24 quadrupole, G=32, r_crit=0.25, list depth 384, EBS balls")
-    x = ics.nfw(n, seed=501)
+    x, _, ks_o, perm_o, tree, ps, mom, rc = _nfw16m()
     ctx = g.Context(device=0, multipole=2, group_size=32, r_crit=0.25, list_depth=384,
                     ball=oracle.BALL_EBS)
     out = ctx.tree_forces(torch.from_numpy(x).cuda(), eps, theta).cpu().numpy()
     ks, perm, cube = ctx.keys()
     t = ctx.tree()
     gg = ctx.groups()
-    say("  oracle tree at 2^24")
-    ks_o, perm_o, tree, ps, mom, rc = _oracle_prep(x, 16, 32, 0.25)
     assert np.array_equal(ks, ks_o) and np.array_equal(perm, perm_o)
     for f in ("first", "count", "child_first", "n_child", "level"):
         assert np.array_equal(t[f], tree[f]), f
@@ -68,6 +80,80 @@ def test_nfw16m_bench_configuration():
     gate_forces(ctx, oracle_parts(tree, mom, ps, grp, perm), out, np.ones(n, bool), eps, theta,
                 2, sel=sel, label=f"sampled {sel.size} groups: ")
     assert ctx.stats()["sticky_flags"] == 0
+
+
+def test_nfw16m_bench_block_substeps():
+    """Sub-steps as the benchmark times them.  Before every sub-step the float64
+    state is read back; the oracle predicts every particle from it to the new
+    sub-step (float64, rounded to float32), selects the due ones, and, on the
+    sub-step that builds a new tree, builds its own from those positions (keys,
+    permutation and octree must be the library's, bit for bit).  On the checked
+    sub-steps it computes node moments on the tree in use, groups of the
+    class's size and the forces of sampled groups, which the library's must
+    match.  The first sub-step is checked and the rest captured, as in the
+    benchmark's warm-up."""
+    n, eps, theta, eta, kmax = 1 << 24, 1 / 512, 0.5, 0.1, 8
+    say("[gpu] NFW 2^24 block sub-steps, captured, groups of 1 in class 0 and 32 above, "
+        "growth-model rebuilds")
+    x, v, _, perm_t, tree_t, _, _, rc = _nfw16m()
+    ctx = g.Context(device=0, multipole=2, group_size=32, r_crit=0.25, list_depth=384,
+                    ball=oracle.BALL_EBS, graph=1, rebuild_interval=0)
+    pos = torch.from_numpy(x[:, :3].astype(np.float64)).cuda()
+    vel = torch.from_numpy(v).cuda()
+    m32 = np.ascontiguousarray(x[:, 3])
+    ctx.sim_bind(pos, vel, torch.from_numpy(m32).cuda(), eps, theta, eta=eta, kmax=kmax)
+    table = [1] + [32] * kmax  # group size per sub-step class
+    ctx.sim_set_group_sizes(table)
+    info = ctx.sim_info()
+    dt_fine, builds = info["dt_fine"], info["tree_builds"]
+    rng = np.random.default_rng(9)
+    checked = []
+    for s in range(1, 25):
+        acc, lev, last = ctx.sim_state()
+        st = I.BlockSim.from_state(pos.cpu().numpy(), vel.cpu().numpy(), acc, m32, lev, last,
+                                   s - 1, dt_fine, eps, eta, kmax)
+        del acc, lev, last
+        ctx.set_params(check=1 if s == 1 else 0)
+        ctx.sim_step()
+        torch.cuda.synchronize()
+        info = ctx.sim_info()
+        assert info["substep"] == s
+        rebuilt = info["tree_builds"] > builds
+        builds = info["tree_builds"]
+        if not (rebuilt or s in (5, 6)):
+            continue
+        shadow = st._shadow(st.predict(s))
+        if rebuilt:
+            say(f"  sub-step {s}: new tree")
+            k, _ = oracle.keys(shadow, 0)
+            ks_t, perm_t = oracle.sort(k)
+            tree_t = oracle.build(ks_t, 16)
+            ks, perm, _ = ctx.keys()
+            assert np.array_equal(ks, ks_t) and np.array_equal(perm, perm_t)
+            t = ctx.tree()
+            for f in ("first", "count", "child_first", "n_child", "level"):
+                assert np.array_equal(t[f], tree_t[f]), f
+        act = st.due(s)
+        G = table[min((s & -s).bit_length() - 1, kmax)]
+        ps = shadow[perm_t].astype(np.float64)
+        mom = oracle.moments(tree_t, ps)
+        grp = oracle.groups(act[perm_t].astype(np.uint8), ps, G, rc, oracle.BALL_EBS)
+        ng = grp["first"].size
+        assert ng == ctx.stats()["n_groups"] and act.sum() == ctx.stats()["n_active"]
+        sel = np.unique(np.r_[rng.choice(ng, min(40, ng), replace=False),
+                              np.argsort(-grp["ball"][:, 3])[:8]])
+        out, _, last_gpu = ctx.sim_state()
+        assert np.array_equal(last_gpu == s, act)
+        gate_forces(ctx, oracle_parts(tree_t, mom, ps, grp, perm_t), out, act, eps, theta, 2,
+                    sel=sel, label=f"sub-step {s} ({'new' if rebuilt else 'reused'} tree, "
+                                   f"{int(act.sum())} due, groups of <= {G}): ")
+        checked.append((s, rebuilt))
+        if s >= 6 and any(r for _, r in checked):
+            break
+    say(f"  checked sub-steps (sub-step, new tree): {checked}")
+    assert ctx.stats()["sticky_flags"] == 0
+    assert {5, 6} <= {c[0] for c in checked}
+    assert any(r for _, r in checked), "no tree built in 24 sub-steps"
 
 
 @functools.lru_cache(maxsize=1)

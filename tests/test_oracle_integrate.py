@@ -129,3 +129,20 @@ def test_block_cycle_bookkeeping():
     assert np.all(sim.si == sim.s)
     # no particle is active more often than the finest level allows
     assert counts.max() <= 1 << kmax
+
+
+def test_state_taken_mid_cycle_predicts_like_the_integrated_one():
+    x, v = ics.nfw(300, seed=5, with_vel=True)
+    eps, kmax = 1 / 32, 4
+    sim = I.BlockSim(x, v, eps, 0.1, kmax, _direct_force(eps))
+    for _ in range(3):
+        sim.step()
+    got = I.BlockSim.from_state(sim.x, sim.v, sim.a, sim.m, sim.k, sim.si, sim.s, sim.dt_fine,
+                                eps, 0.1, kmax)
+    s = sim.s + 1
+    assert np.array_equal(got.due(s), sim.due(s)) and got.due(s).any()
+    assert np.array_equal(got.predict(s), sim.predict(s))
+    assert got.dt_max == sim.dt_max
+    # the copy does not alias the integrated state
+    sim.step()
+    assert not np.array_equal(got.si, sim.si)

@@ -467,11 +467,15 @@ int gothic_get_scratch(gothic_ctx *c, int64_t *held, int64_t *required);
  *     particles), gfirst/gcount [n_groups] into alist, ball [n_groups][4]
  *     float (r_I, b_I), entries [n_groups][2] uint32 (node and particle list
  *     entries of the group's walk)
+ *   positions: xyzm_sorted [n][4] float, the positions and masses the moments,
+ *     groups and walk used, in key order (for a block sub-step the float32
+ *     prediction of Section 2.7, masses non-negative)
  */
 int gothic_get_keys(gothic_ctx *c, uint64_t *keys_sorted, uint32_t *perm, double *cube);
 int gothic_get_tree(gothic_ctx *c, int64_t *n_nodes, uint32_t *first, uint32_t *count,
                     uint32_t *child_first, uint8_t *n_child, uint8_t *level);
 int gothic_get_nodes(gothic_ctx *c, float *com_m, float *b, float *quad);
+int gothic_get_positions(gothic_ctx *c, float *xyzm_sorted);
 int gothic_get_groups(gothic_ctx *c, int64_t *n_active, int64_t *n_groups, uint32_t *alist,
                       uint32_t *gfirst, uint32_t *gcount, float *ball, uint32_t *entries);
 /* (n_nodes, n_active, n_groups: HOST int64 out-parameters, NULL skips.) */

@@ -93,6 +93,7 @@ def _load():
     lib.gothic_get_keys.argtypes = [P, P, P, P]
     lib.gothic_get_tree.argtypes = [P, P, P, P, P, P, P]
     lib.gothic_get_nodes.argtypes = [P, P, P, P]
+    lib.gothic_get_positions.argtypes = [P, P]
     lib.gothic_get_groups.argtypes = [P, P, P, P, P, P, P, P]
     lib.gothic_get_lists.argtypes = [P, i64, P, i64, P, P, P]
     lib.gothic_get_scratch.argtypes = [P, P, P]
@@ -113,6 +114,7 @@ def _load():
                  "gothic_get_stats", "gothic_get_lists", "gothic_get_scratch",
                  "gothic_clear_flags",
                  "gothic_get_keys", "gothic_get_tree", "gothic_get_nodes", "gothic_get_groups",
+                 "gothic_get_positions",
                  "gothic_get_walk_time", "gothic_sim_bind", "gothic_sim_bind_batched",
                  "gothic_sim_step", "gothic_sim_reset_counters", "gothic_sim_get_info",
                  "gothic_sim_get_state", "gothic_sim_get_steps", "gothic_sim_get_tuning",
@@ -500,6 +502,15 @@ class Context:
         q = torch.empty((m, 6), dtype=torch.float32, device=dev)
         _check(lib.gothic_get_nodes(self._h, _ptr(cm), _ptr(b), _ptr(q)))
         return cm[:nn].cpu().numpy(), b[:nn].cpu().numpy(), q[:nn].cpu().numpy()
+
+    def positions(self):
+        """[n,4] float32 numpy: the positions and masses of the last evaluation in
+        key order (the float32 prediction for a block sub-step)."""
+        import torch
+        n = self._stats_raw()["n"]
+        xs = torch.empty((max(n, 1), 4), dtype=torch.float32, device=self.torch_device)
+        _check(lib.gothic_get_positions(self._h, _ptr(xs)))
+        return xs[:n].cpu().numpy()
 
     def groups(self) -> dict:
         import torch

@@ -117,6 +117,18 @@ int gothic_get_keys(gothic_ctx *c, uint64_t *keys_sorted, uint32_t *perm, double
   return hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
+int gothic_get_positions(gothic_ctx *c, float *xyzm_sorted) {
+  if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");
+  DeviceGuard guard(c->device);
+  Ctl h;
+  int rc = last_counts(c, &h);
+  if (rc) return rc;
+  const Buffers &L = *c->lb;
+  hipStream_t s = c->last_stream;
+  if ((rc = d2d(xyzm_sorted, L.pos, (size_t)c->last_n * 16, s))) return rc;
+  return hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
 int gothic_get_tree(gothic_ctx *c, int64_t *n_nodes, uint32_t *first, uint32_t *count,
                     uint32_t *child_first, uint8_t *n_child, uint8_t *level) {
   if (!c) return set_error(GOTHIC_EINVAL, "NULL argument");

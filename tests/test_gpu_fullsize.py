@@ -85,8 +85,9 @@ def test_nfw16m_bench_configuration():
 def test_nfw16m_bench_block_substeps():
     """Sub-steps as the benchmark times them.  Before every sub-step the float64
     state is read back; the oracle predicts every particle from it to the new
-    sub-step (float64, rounded to float32), selects the due ones, and, on the
-    sub-step that builds a new tree, builds its own from those positions (keys,
+    sub-step (float64, rounded to float32: the library's key-ordered positions
+    must be these, bit for bit), selects the due ones, and, on the sub-step
+    that builds a new tree, builds its own from those positions (keys,
     permutation and octree must be the library's, bit for bit).  On the checked
     sub-steps it computes node moments on the tree in use, groups of the
     class's size and the forces of sampled groups, which the library's must
@@ -133,6 +134,9 @@ def test_nfw16m_bench_block_substeps():
             t = ctx.tree()
             for f in ("first", "count", "child_first", "n_child", "level"):
                 assert np.array_equal(t[f], tree_t[f]), f
+        # the float32 prediction in key order, bit for bit (Section 2.7's
+        # predictor, masses carried unchanged)
+        assert np.array_equal(ctx.positions(), shadow[perm_t])
         act = st.due(s)
         G = table[min((s & -s).bit_length() - 1, kmax)]
         ps = shadow[perm_t].astype(np.float64)

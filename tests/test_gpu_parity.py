@@ -73,6 +73,8 @@ def test_keys_sort_tree_bitexact(name, key_kind):
         assert np.array_equal(cube, cube_o)
         assert np.array_equal(ks, ks_o)
         assert np.array_equal(perm, perm_o)
+        # the key-order gather: positions and masses exactly the caller's
+        assert np.array_equal(ctx.positions(), x[perm_o])
         t = ctx.tree()
         t_o = oracle.build(ks_o, n_leaf)
         for f in ("first", "count", "child_first", "n_child", "level"):

@@ -40,6 +40,10 @@ def test_defaults_and_cpu_only_errors():
     assert rc == g.EINVAL
     assert b"NULL" in g.lib.gothic_last_error()
     assert g.lib.gothic_destroy(None) == g.OK
+    # so is every read-back of the last evaluation
+    for f, nargs in (("gothic_get_keys", 3), ("gothic_get_tree", 6), ("gothic_get_nodes", 3),
+                     ("gothic_get_groups", 7), ("gothic_get_positions", 1)):
+        assert getattr(g.lib, f)(None, *([None] * nargs)) == g.EINVAL, f
 
 
 def test_ctypes_structs_match_the_header(tmp_path):

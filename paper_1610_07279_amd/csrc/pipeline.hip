@@ -201,9 +201,10 @@ int ensure_events(gothic_ctx *c) {
   return GOTHIC_OK;
 }
 
-
-// built); otherwise by params.rebuild_interval: 1 every time, k > 1 after k
-// evaluations on one tree, 0 when the paper's growth models say so.
+// A new tree is built when the last one does not fit the call (no tree yet,
+// other systems, grown buffers, another leaf size or key kind); otherwise by
+// params.rebuild_interval: 1 every time, k > 1 after k evaluations on one
+// tree, 0 when the paper's growth models say so.
 bool must_rebuild(gothic_ctx *c, const Systems &sy) {
   const TreeState &T = c->tree;
   if (!T.valid || T.n != sy.n || T.off != sy.off || T.buffers != c->buffers ||
